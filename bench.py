@@ -1,0 +1,279 @@
+"""Benchmark: RgCSR SpMV GFLOP/s and achieved HBM GB/s on one MI355X, RgCSR
+vs Hybrid ELL+COO, on the 3D 7-point Laplacian 128^3 and the Zipf(2)
+n = 1,000,000 matrix (FP32 values and vectors).
+
+One step = one RgCSR SpMV of each of the two matrices (every hot-path kernel
+of the single-matrix SpMV).  Inputs are synthetic, seeded and resident in HBM
+before timing starts; the timed steps rotate over enough distinct copies of
+each matrix and its vectors that the working set exceeds the 256 MB Infinity
+Cache several times, so bytes come from HBM.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W]
+
+Prints one JSON line.  Flops count 2 per nonzero (the paper's convention,
+Section 3.4 peak estimate); algorithmic bytes per SpMV are
+    nnz*(s_v + 4) + n_rows*4 + n_cols*s_x + n_rows*s_y + (groups + 1)*8
+(values, int32 columns, one row length per row, x read once, y written once,
+group pointers); artificial zeros and repeated x reads are not credited.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+HBM_PEAK_GBS = 8000.0
+ROTATE_BYTES = 1 << 30
+
+# layouts timed by the benchmark (also used by the full-size parity test)
+LAYOUT_STENCIL = dict(G=64, T=1, sigma=1, tau=-1)          # the paper's layout
+LAYOUT_ZIPF = dict(G=64, T=1, sigma=1 << 40, tau=16)       # descending order + long-row path
+
+METRIC = "SpMV GFLOP/s and achieved HBM GB/s (% of peak), RgCSR vs Hybrid, 1 MI355X"
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def alg_bytes(nnz, n_rows, n_cols, groups, s_v=4, s_x=4, s_y=4, k=1):
+    return nnz * (s_v + 4) + n_rows * 4 + n_cols * k * s_x + n_rows * k * s_y + (groups + 1) * 8
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in ("kernels.hip", "kernels.h", "internal.h"):
+        with open(os.path.join(ROOT, "paper_1012_2270_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_record(kernel_key: str):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, when
+    it was taken on the current kernel source; else None."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    try:
+        with open(path) as f:
+            rec = json.load(f)
+    except (OSError, ValueError):
+        return None
+    r = rec.get(kernel_key)
+    if not r or r.get("kernel_source_sha") != kernel_source_hash():
+        return None
+    return r.get("bytes_per_launch")
+
+
+class Case:
+    """One matrix: rotating RgCSR and Hybrid copies plus their vectors."""
+
+    def __init__(self, name, A, x, layout, torch, rg):
+        self.name = name
+        self.A = A
+        self.x_host = x
+        t0 = time.time()
+        base = rg.rgcsr_from_csr(A, **layout)
+        self.build_s = time.time() - t0
+        self.info = base.info
+        t0 = time.time()
+        hyb = rg.hyb_from_csr(A)
+        self.hyb_build_s = time.time() - t0
+        self.hyb_info = hyb.info
+        per_copy = self.info["device_bytes"] + 4 * (A.n_rows + A.n_cols)
+        self.copies = max(1, math.ceil(ROTATE_BYTES / per_copy))
+        hyb_copy = self.hyb_info["device_bytes"] + 4 * (A.n_rows + A.n_cols)
+        self.hyb_copies = max(1, math.ceil(ROTATE_BYTES / hyb_copy))
+        self.mats = [base] + [base.clone() for _ in range(self.copies - 1)]
+        self.hybs = [hyb] + [hyb.clone() for _ in range(self.hyb_copies - 1)]
+        xd = torch.from_numpy(x).to("cuda:0")
+        ncopy = max(self.copies, self.hyb_copies)
+        self.xs = [xd.clone() for _ in range(ncopy)]
+        self.ys = [torch.empty(A.n_rows, dtype=torch.float32, device="cuda:0") for _ in range(ncopy)]
+        self.bytes = alg_bytes(A.nnz, A.n_rows, A.n_cols, self.info["n_groups"])
+        self.flops = 2 * A.nnz
+
+    def spmv(self, i, rg):
+        j = i % self.copies
+        rg.rgcsr_spmv(self.mats[j], self.xs[j], self.ys[j])
+
+    def hyb_spmv(self, i, rg):
+        j = i % self.hyb_copies
+        rg.hyb_spmv(self.hybs[j], self.xs[j], self.ys[j])
+
+
+def time_launches(torch, fn, n, warmup):
+    """Per-launch durations (ms) from events around each launch."""
+    for i in range(warmup):
+        fn(i)
+    torch.cuda.synchronize()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(n + 1)]
+    ev[0].record()
+    for i in range(n):
+        fn(i)
+        ev[i + 1].record()
+    torch.cuda.synchronize()
+    return [ev[i].elapsed_time(ev[i + 1]) for i in range(n)]
+
+
+def cpu_baseline(cases, budget_s=10.0):
+    """The FP64 oracle (plain serial CSR SpMV) on the same matrices, upcast to
+    float64, repeated for about budget_s seconds on one host core."""
+    import oracle
+    mats = [(c.A, c.A.astype(np.float64), c.x_host.astype(np.float64)) for c in cases]
+    oracle.csr_spmv(mats[0][1], mats[0][2])  # warm
+    passes, flops, t0 = 0, 0, time.perf_counter()
+    while True:
+        for A, A64, x64 in mats:
+            oracle.csr_spmv(A64, x64)
+            flops += 2 * A.nnz
+        passes += 1
+        el = time.perf_counter() - t0
+        if el >= budget_s:
+            break
+    return {"value": flops / el / 1e9, "unit": "GFLOP/s", "cores": 1, "kind": "oracle",
+            "sample": f"{passes} full passes over both matrices (the whole step), float64, "
+                      f"{el:.1f} s on one core"}
+
+
+def check_outputs(cases, torch):
+    """Scaled error of the last timed outputs against the oracle."""
+    import oracle
+    import paper_1012_2270_amd as rg
+    out = {}
+    for c in cases:
+        y = torch.empty(c.A.n_rows, dtype=torch.float32, device="cuda:0")
+        rg.rgcsr_spmv(c.mats[0], c.xs[0], y)
+        yh = torch.empty_like(y)
+        rg.hyb_spmv(c.hybs[0], c.xs[0], yh)
+        torch.cuda.synchronize()
+        ref = oracle.csr_spmv(c.A, c.x_host)
+        s = oracle.csr_absmv(c.A, c.x_host)
+        out[c.name] = {"rgcsr": oracle.scaled_error(y.cpu().numpy(), ref, s),
+                       "hybrid": oracle.scaled_error(yh.cpu().numpy(), ref, s)}
+    return out
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-check", action="store_true", help="skip the oracle check of the outputs")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print(json.dumps({"error": "this benchmark measures one GPU only; the single-matrix SpMV "
+                                   "is not sharded across GPUs",
+                          "n_gpus": args.gpus}))
+        sys.exit(2)
+
+    import torch
+    import paper_1012_2270_amd as rg
+    from paper_1012_2270_amd import workloads as W
+
+    rg._lib.load()
+    log("generating matrices ...")
+    A1, x1 = W.workload_laplace3d(128)
+    A2, x2 = W.workload_zipf(1_000_000)
+    log("building layouts ...")
+    cases = [Case("laplace3d_7pt_128", A1, x1, LAYOUT_STENCIL, torch, rg),
+             Case("zipf2_1e6", A2, x2, LAYOUT_ZIPF, torch, rg)]
+    for c in cases:
+        log(f"  {c.name}: nnz={c.A.nnz} copies={c.copies} hyb_copies={c.hyb_copies} "
+            f"build={c.build_s:.2f}s")
+
+    K, Wm = args.steps, args.warmup
+    # the step: one RgCSR SpMV per matrix, per-kernel events around each
+    for i in range(Wm):
+        for c in cases:
+            c.spmv(i, rg)
+    torch.cuda.synchronize()
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(len(cases) + 1)] for _ in range(K)]
+    start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t_wall = time.perf_counter()
+    start.record()
+    for i in range(K):
+        ev[i][0].record()
+        for ci, c in enumerate(cases):
+            c.spmv(i, rg)
+            ev[i][ci + 1].record()
+    end.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t_wall
+    total_ms = start.elapsed_time(end)
+    per_kernel = [[ev[i][ci].elapsed_time(ev[i][ci + 1]) for i in range(K)] for ci in range(len(cases))]
+
+    # Hybrid on the same matrices (comparison, not part of the step)
+    hyb_ms = []
+    for c in cases:
+        d = time_launches(torch, lambda i, c=c: c.hyb_spmv(i, rg), K, Wm)
+        hyb_ms.append(d)
+
+    flops = sum(c.flops for c in cases)
+    value = flops * K / (total_ms * 1e-3) / 1e9
+    detail = {}
+    for ci, c in enumerate(cases):
+        t = float(np.mean(per_kernel[ci]))
+        th = float(np.mean(hyb_ms[ci]))
+        detail[c.name] = {
+            "nnz": c.A.nnz, "n_rows": c.A.n_rows, "alg_bytes": c.bytes,
+            "layout": {k: int(v) for k, v in c.info.items()
+                       if k in ("group_size", "lanes_per_row", "sort_window", "long_row_threshold",
+                                "slots", "n_long", "long_work", "partials")},
+            "fill_pct": 100.0 * (c.info["slots"] + c.info["long_nnz"] - c.A.nnz) / max(1, c.A.nnz),
+            "rgcsr": {"us": 1e3 * t, "us_median": 1e3 * float(np.median(per_kernel[ci])),
+                      "gflops": c.flops / (t * 1e-3) / 1e9, "gbs": c.bytes / (t * 1e-3) / 1e9,
+                      "hbm_frac": c.bytes / (t * 1e-3) / 1e9 / HBM_PEAK_GBS},
+            "hybrid": {"us": 1e3 * th, "gflops": c.flops / (th * 1e-3) / 1e9,
+                       "gbs": c.bytes / (th * 1e-3) / 1e9, "hbm_frac": c.bytes / (th * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                       "ell_width": c.hyb_info["ell_width"], "coo_nnz": c.hyb_info["coo_nnz"]},
+            "rgcsr_over_hybrid": th / t,
+            "copies_rotated": c.copies,
+        }
+    # dominant kernel: the one with the larger share of the step
+    dom = max(range(len(cases)), key=lambda ci: float(np.mean(per_kernel[ci])))
+    dc = cases[dom]
+    t_dom = float(np.mean(per_kernel[dom])) * 1e-3
+    achieved = dc.bytes / t_dom / 1e9
+    tr = traffic_record(dc.name)
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "GFLOP/s",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": Wm,
+        "ms_per_step": total_ms / K,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic (seeded generators; 7-point Laplacian and Zipf row lengths)",
+        "config": {"workload": "RgCSR SpMV, FP32: 3D 7-point Laplacian 128^3 (n=2,097,152, "
+                               "nnz=14,581,760) + Zipf(2.0) rows clipped to [1,10000], n=1,000,000",
+                   "matrices": [c.name for c in cases], "parallelism": "single GPU"},
+        "hbm_gbs": sum(c.bytes for c in cases) * K / (total_ms * 1e-3) / 1e9,
+        "hbm_frac": sum(c.bytes for c in cases) * K / (total_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+        "roofline": {"bound": "hbm", "kernel": dc.name, "achieved": achieved, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": tr,
+                     "alg_bytes_per_launch": dc.bytes, "avg_launch_us": t_dom * 1e6},
+        "cases": detail,
+        "wall_s_timed": wall,
+    }
+    if not args.no_check:
+        out["max_scaled_error"] = check_outputs(cases, torch)
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(cases)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,312 @@
+/*
+ * rgcsr.h -- C ABI of librgcsr.so: sparse matrix-vector multiplication in the
+ * Row-grouped CSR (RgCSR) format on AMD Instinct MI355X (gfx950).
+ *
+ * Method: Oberhuber, Suzuki, Vacata, "New Row-grouped CSR format for storing
+ * the sparse matrices on GPU with implementation in CUDA".
+ *   Section 3.1  CSR input format (row pointers, ascending columns per row).
+ *   Section 3.4  RgCSR: rows split into groups; inside a group the first
+ *                nonzero of every row is stored, then the second, ...; rows
+ *                shorter than the group's longest are padded with artificial
+ *                zeros carrying a ghost column; groupPointers + rowLength
+ *                replace rowPointers; one thread per row walks its row with
+ *                the group size as stride and stops after rowLength steps.
+ *   Section 3.3  Hybrid ELLPACK + COO, the paper's comparison format.
+ *   Section 3.4  Peak model: 2 flops per nonzero; bytes per nonzero are the
+ *                column index, the value and (uncached) the x entry.
+ *
+ * Conventions for every call:
+ *   - Status codes only; nothing aborts and no C++ exception crosses the ABI.
+ *     rgcsr_last_error() returns a thread-local message for the last failure.
+ *   - "device pointer": memory from hipMalloc (or a torch CUDA tensor) on the
+ *     current HIP device.  "host pointer": ordinary CPU memory.
+ *   - stream: a hipStream_t passed as void*; NULL is the null stream.  Device
+ *     work is enqueued on it and calls return without a device-wide sync,
+ *     unless a call says otherwise.  Asynchronous kernel faults surface as
+ *     RGCSR_EHIP from a later call that synchronises.
+ *   - Index types: row pointers and group pointers are int64; column indices
+ *     and row lengths are int32 (as in the paper).
+ *   - Values are converted to the handle's storage dtype with round to
+ *     nearest even; float64 input bound for float16/bfloat16 storage is first
+ *     rounded to float32, then to the 16-bit type.
+ *   - Supported (stored value, vector, accumulator) triples for SpMV:
+ *     (F64,F64,F64) (F32,F32,F32) (F16,F32,F32) (BF16,F32,F32) (F32,F64,F64);
+ *     the vector dtype argument selects the vector/accumulator type.
+ */
+#ifndef RGCSR_H
+#define RGCSR_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    RGCSR_OK = 0,
+    RGCSR_EINVAL = 1,      /* bad argument (null pointer, unsupported size)   */
+    RGCSR_ECSR = 2,        /* malformed CSR input                             */
+    RGCSR_ENOMEM = 3,      /* host or device allocation failed                */
+    RGCSR_EOVERFLOW = 4,   /* a size does not fit the index types             */
+    RGCSR_EHIP = 5,        /* HIP runtime error                               */
+    RGCSR_EUNSUPPORTED = 6 /* valid request that this library does not handle */
+} rgcsr_status;
+
+typedef enum { RGCSR_F64 = 0, RGCSR_F32 = 1, RGCSR_F16 = 2, RGCSR_BF16 = 3 } rgcsr_dtype;
+
+/* Layout parameters (Section 3.4 and the project's readings of it).
+ *   group_size   G: rows per group, >= 1 (0 selects 64).  Device kernels
+ *                need G * lanes_per_row to be a multiple of 64 or a divisor of 64.
+ *   lanes_per_row T in {1, 2, 4, 8} (0 selects 1).  T = 1 is the paper's
+ *                layout.  With T > 1 each row's width is rounded up to a
+ *                multiple of T and nonzero j of local row t of group g sits at
+ *                gp[g] + (j / T) * (s_g * T) + t * T + j % T.
+ *   sort_window  sigma >= 1 (0 selects 1): inside each window of sigma rows
+ *                rows are ordered longest first, ties in original order (the
+ *                descending ordering of Section 4.4.2); 1 keeps paper order.
+ *   long_row_threshold tau: rows with more than tau nonzeros are stored
+ *                CSR-contiguous in a long-row segment (sorted longest first,
+ *                ties by original row) and multiplied by whole wavefronts;
+ *                negative = no split (paper).
+ *   value_dtype  storage dtype of values (rgcsr_dtype).
+ *   keep_csr_map keep the CSR row pointers on the device; required by
+ *                rgcsr_set_values and by the dvals output of the gradient.
+ *   build_transpose also build A^T (structure + value map) so the gradient
+ *                computes dx = A^T dy without atomics.
+ *   validate     1 (default) checks the CSR input; 0 trusts it (undefined
+ *                behaviour on malformed input).
+ */
+typedef struct {
+    int32_t group_size;
+    int32_t lanes_per_row;
+    int64_t sort_window;
+    int64_t long_row_threshold;
+    int32_t value_dtype;
+    int32_t keep_csr_map;
+    int32_t build_transpose;
+    int32_t validate;
+} rgcsr_opts;
+
+/* Fills *opts with the paper's layout: G = 64, T = 1, sigma = 1, no long
+ * rows, float32 storage, no CSR map, no transpose, validation on. */
+void rgcsr_default_opts(rgcsr_opts *opts);
+
+typedef struct rgcsr_matrix_s *rgcsr_handle;
+
+/* Sizes of a layout, in elements.  n_groups = groups of short rows,
+ * n_short / n_long = rows in the grouped / long-row parts, slots = grouped
+ * slots including artificial zeros (gp[n_groups]), long_nnz = nonzeros in the
+ * long-row segment, nnz = real nonzeros, n_rows / n_cols totals (a batch is a
+ * block-diagonal concatenation), n_matrices = 1 unless built as a batch,
+ * long_work = wavefront work items of the long-row path, partials = chunk
+ * partial sums of long rows split over several wavefronts. */
+typedef struct {
+    int64_t n_rows, n_cols, nnz;
+    int64_t n_groups, n_short, n_long, slots, long_nnz;
+    int64_t n_matrices, long_work, partials;
+    int32_t group_size, lanes_per_row, value_dtype, has_transpose;
+    int64_t sort_window, long_row_threshold;
+    int64_t device_bytes; /* device memory the handle owns */
+} rgcsr_info_t;
+
+/* ---- Host-only layout (no GPU needed; used to check the layout on CPU) ---- */
+
+/* Computes the sizes of the layout of a host CSR matrix (row_ptr[n_rows+1],
+ * col_idx[nnz], host pointers) under *opts.  Only out->n_groups, n_short,
+ * n_long, slots, long_nnz, nnz, n_rows, n_cols, long_work and partials are
+ * set.  Returns RGCSR_ECSR for malformed CSR when opts->validate != 0. */
+rgcsr_status rgcsr_layout_sizes(int64_t n_rows, int64_t n_cols, int64_t nnz,
+                                const int64_t *row_ptr, const int32_t *col_idx,
+                                const rgcsr_opts *opts, rgcsr_info_t *out);
+
+/* Writes every layout array of a host CSR matrix into caller-owned host
+ * buffers sized from rgcsr_layout_sizes:
+ *   gp[n_groups+1] (int64), short_len[n_short], short_row[n_short] (original
+ *   row of each grouped row), slot_val[slots] (storage dtype), slot_col[slots],
+ *   long_row[n_long], long_ptr[n_long+1] (int64), long_val[long_nnz],
+ *   long_col[long_nnz].
+ * Artificial zeros have all-zero value bits and the row's last column (0 for
+ * an empty row) as ghost index.  vals has dtype vals_dtype. */
+rgcsr_status rgcsr_layout_host(int64_t n_rows, int64_t n_cols, int64_t nnz,
+                               const int64_t *row_ptr, const int32_t *col_idx,
+                               const void *vals, rgcsr_dtype vals_dtype,
+                               const rgcsr_opts *opts, int64_t *gp, int32_t *short_len,
+                               int32_t *short_row, void *slot_val, int32_t *slot_col,
+                               int32_t *long_row, int64_t *long_ptr, void *long_val,
+                               int32_t *long_col);
+
+/* ---- Device handles ------------------------------------------------------ */
+
+/* rgcsr_from_csr: convert a CSR matrix (Section 3.1) to RgCSR on the current
+ * device.  inputs_on_device = 0: row_ptr/col_idx/vals are host pointers,
+ * borrowed for the duration of the call.  inputs_on_device = 1: they are
+ * device pointers; the call copies them to the host first (synchronising the
+ * stream).  The handle owns the device arrays it allocates (hipMalloc); the
+ * call synchronises the stream before returning, so the handle is ready. */
+rgcsr_status rgcsr_from_csr(int64_t n_rows, int64_t n_cols, int64_t nnz,
+                            const int64_t *row_ptr, const int32_t *col_idx,
+                            const void *vals, rgcsr_dtype vals_dtype,
+                            const rgcsr_opts *opts, int inputs_on_device, void *stream,
+                            rgcsr_handle *out);
+
+/* rgcsr_from_csr_batch: build one handle holding `count` independent host CSR
+ * matrices as a block-diagonal matrix: matrix m's rows follow matrix m-1's,
+ * and so do its columns, so x and y of the batch are the per-matrix vectors
+ * concatenated.  Groups never straddle two matrices.  All matrices use the
+ * same *opts.  row_ptr[m], col_idx[m], vals[m] are host pointers. */
+rgcsr_status rgcsr_from_csr_batch(int32_t count, const int64_t *n_rows, const int64_t *n_cols,
+                                  const int64_t *const *row_ptr, const int32_t *const *col_idx,
+                                  const void *const *vals, rgcsr_dtype vals_dtype,
+                                  const rgcsr_opts *opts, void *stream, rgcsr_handle *out);
+
+/* Row/column offsets of each matrix of a batch handle, host arrays of
+ * n_matrices+1 int64 entries each (last = totals). */
+rgcsr_status rgcsr_batch_offsets(rgcsr_handle A, int64_t *row_off, int64_t *col_off);
+
+/* rgcsr_spmv: y = A x (Section 3.4 kernel semantics: every row is
+ * overwritten, empty rows give 0).  x[n_cols], y[n_rows] are device pointers
+ * of vec_dtype (F32 or F64); x and y must not overlap.  One kernel launch. */
+rgcsr_status rgcsr_spmv(rgcsr_handle A, const void *x, void *y, rgcsr_dtype vec_dtype,
+                        void *stream);
+
+/* rgcsr_spmv_batched: Y = A X for k right-hand sides.  X is n_cols x k
+ * row-major with leading dimension ldx >= k, Y is n_rows x k with ldy >= k
+ * (device pointers, elements of vec_dtype).  For a batch handle this is
+ * Y_m = A_m X_m for every matrix m.  k in {1, 2, 4, 8, 16, 32} runs as one
+ * launch; other k run as several launches over column blocks.  When k > 1,
+ * X, Y must be 16-byte aligned and ldx, ldy multiples of 4 (F32) or 2 (F64).
+ * persistent = 1 launches a fixed grid of wavefronts that loop over the
+ * work items (one resident launch); 0 launches one wavefront per item. */
+rgcsr_status rgcsr_spmv_batched(rgcsr_handle A, int32_t k, const void *X, int64_t ldx,
+                                void *Y, int64_t ldy, rgcsr_dtype vec_dtype,
+                                int32_t persistent, void *stream);
+
+/* rgcsr_spmv_transpose_grad: backward of y = A(theta) x.  Given dy[n_rows]:
+ *   dx = A^T dy                        (if dx != NULL; dx[n_cols])
+ *   dvals[k] = dy[row(k)] * x[col(k)]  (if dvals != NULL; nnz entries in the
+ *                                       CSR order of the input matrix)
+ * All device pointers of vec_dtype (F32 or F64).  dx uses the transposed
+ * RgCSR when the handle was built with build_transpose (deterministic), else
+ * an atomic scatter (order of additions not deterministic).  dvals needs
+ * keep_csr_map or build_transpose. */
+rgcsr_status rgcsr_spmv_transpose_grad(rgcsr_handle A, const void *x, const void *dy,
+                                       void *dx, void *dvals, rgcsr_dtype vec_dtype,
+                                       void *stream);
+
+/* rgcsr_set_values: overwrite the stored values (and those of A^T, when
+ * built) from nnz values in the CSR order of the input matrix, converting to
+ * the storage dtype on the device.  vals is a device pointer when on_device
+ * = 1, else a host pointer (copied synchronously).  Needs keep_csr_map or
+ * build_transpose. */
+rgcsr_status rgcsr_set_values(rgcsr_handle A, const void *vals, rgcsr_dtype vals_dtype,
+                              int on_device, void *stream);
+
+/* rgcsr_export: copy the device layout arrays into host buffers laid out as
+ * for rgcsr_layout_host (any pointer may be NULL to skip that array).
+ * Synchronises the stream.  For checking the converter bit for bit. */
+rgcsr_status rgcsr_export(rgcsr_handle A, void *stream, int64_t *gp, int32_t *short_len,
+                          int32_t *short_row, void *slot_val, int32_t *slot_col,
+                          int32_t *long_row, int64_t *long_ptr, void *long_val,
+                          int32_t *long_col);
+
+/* rgcsr_to_csr: decode the device layout back to CSR in host buffers
+ * (row_ptr[n_rows+1], col_idx[nnz], vals[nnz] in the storage dtype).
+ * Values keep their bits.  Synchronises the stream. */
+rgcsr_status rgcsr_to_csr(rgcsr_handle A, void *stream, int64_t *row_ptr, int32_t *col_idx,
+                          void *vals);
+
+rgcsr_status rgcsr_info(rgcsr_handle A, rgcsr_info_t *out);
+
+/* rgcsr_clone: a new handle with its own device copy of every array of A
+ * (device-to-device copies on the stream, synchronised before return).  Used
+ * to rotate several copies of one matrix through the caches when timing. */
+rgcsr_status rgcsr_clone(rgcsr_handle A, void *stream, rgcsr_handle *out);
+
+/* Frees the device arrays and the handle (synchronises the device first).
+ * NULL is accepted. */
+rgcsr_status rgcsr_destroy(rgcsr_handle A);
+
+/* ---- Hybrid ELL + COO (Section 3.3) --------------------------------------- */
+
+typedef struct hyb_matrix_s *hyb_handle;
+
+typedef struct {
+    int64_t n_rows, n_cols, nnz, n_pad, ell_width, coo_nnz, device_bytes;
+    int32_t value_dtype;
+} hyb_info_t;
+
+/* ELL width K1 chosen by the project rule: K1 minimises
+ *   k * n_pad * (s_v + 4) + 3 * (s_v + 8) * sum_i max(0, len_i - k)
+ * over k in [0, max len] (ties: smallest k), n_pad = n_rows rounded up to 64,
+ * s_v = bytes of the storage dtype.  ell_width >= 0 forces K1 instead.
+ * ELL is column-major n_pad x K1 (padding column -1, value bits 0); COO keeps
+ * the remaining nonzeros in (row, column) order.  Host CSR inputs; the call
+ * synchronises the stream before returning. */
+rgcsr_status hyb_from_csr(int64_t n_rows, int64_t n_cols, int64_t nnz, const int64_t *row_ptr,
+                          const int32_t *col_idx, const void *vals, rgcsr_dtype vals_dtype,
+                          rgcsr_dtype value_dtype, int64_t ell_width, int validate,
+                          void *stream, hyb_handle *out);
+
+/* Host-only: the K1 the rule picks for this row-pointer array. */
+rgcsr_status hyb_choose_width(int64_t n_rows, const int64_t *row_ptr, rgcsr_dtype value_dtype,
+                              int64_t *k1);
+
+/* y = A x: an ELL kernel writes every row, then a COO kernel adds the
+ * remaining entries (two launches on the stream).  The COO step adds
+ * partial sums of rows that cross wavefront boundaries with atomics. */
+rgcsr_status hyb_spmv(hyb_handle A, const void *x, void *y, rgcsr_dtype vec_dtype, void *stream);
+
+/* Copies the device ELL/COO arrays to host buffers (ell_col/ell_val of
+ * n_pad * K1, coo_* of coo_nnz); any pointer may be NULL. */
+rgcsr_status hyb_export(hyb_handle A, void *stream, int32_t *ell_col, void *ell_val,
+                        int32_t *coo_row, int32_t *coo_col, void *coo_val);
+
+rgcsr_status hyb_info(hyb_handle A, hyb_info_t *out);
+
+/* Device copy of a Hybrid handle (same conventions as rgcsr_clone). */
+rgcsr_status hyb_clone(hyb_handle A, void *stream, hyb_handle *out);
+rgcsr_status hyb_destroy(hyb_handle A);
+
+/* ---- Mixed-precision conjugate gradients (Krylov consumer, Section 1) ----- */
+
+typedef struct {
+    int32_t outer_iterations;   /* FP64 refinement steps taken              */
+    int32_t inner_iterations;   /* total inner CG iterations (all steps)    */
+    double relres;              /* final ||b - A_hi x||_2 / ||b||_2 in FP64 */
+    double seconds;             /* host wall time of the solve              */
+    int32_t converged;
+} rgcsr_cg_stats;
+
+/* Solves A x = b (A symmetric positive definite) by iterative refinement:
+ * the outer loop forms r = b - A_hi x with FP64 vectors and accumulation
+ * (A_hi values F32 or F64) and stops when ||r|| / ||b|| <= tol; each inner
+ * step runs FP32 CG on A_lo (values F32, F16 or BF16; FP32 vectors and
+ * accumulation; dot products accumulated in FP64) on the scaled residual
+ * until its relative residual drops below inner_tol or max_inner iterations,
+ * then adds the correction to x in FP64.  A_lo and A_hi must have the same
+ * square shape; pass the same handle for a pure single-matrix refinement
+ * when A_lo stores F32.  b and x are device float64 arrays of n; x holds the
+ * initial guess and receives the solution.  Allocates its own device
+ * workspace (freed before return) and synchronises the stream. */
+rgcsr_status rgcsr_cg_solve(rgcsr_handle A_lo, rgcsr_handle A_hi, const double *b, double *x,
+                            double tol, double inner_tol, int32_t max_outer, int32_t max_inner,
+                            void *stream, rgcsr_cg_stats *stats);
+
+/* Plain CG with every vector and accumulation in FP64 on A (F64 or F32
+ * storage), the all-FP64 comparison solver.  Same conventions. */
+rgcsr_status rgcsr_cg_solve_f64(rgcsr_handle A, const double *b, double *x, double tol,
+                                int32_t max_iter, void *stream, rgcsr_cg_stats *stats);
+
+/* ---- Diagnostics ---------------------------------------------------------- */
+
+const char *rgcsr_status_string(rgcsr_status s);
+const char *rgcsr_last_error(void);
+
+/* Library version string, e.g. "rgcsr 0.1 gfx950". */
+const char *rgcsr_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RGCSR_H */

@@ -202,7 +202,8 @@ int64_t orc_cg(int64_t n, const int64_t *rp, const int32_t *col, const double *v
  *    is the paper's "first nonzero of every row, then the second, ...".
  *    Slots of a row past its length are artificial zeros: value bits all
  *    zero, column = the row's last column (0 for an empty row) as ghost index.
- * 6. Long rows keep CSR order, concatenated in long-list order.
+ * 6. Long rows keep CSR order.  The long list is ordered longest first,
+ *    ties by original row, and the rows are concatenated in that order.
  */
 
 typedef struct { int64_t len; int64_t idx; } orc_row_key;
@@ -284,16 +285,12 @@ void orc_rgcsr_build(int64_t n, const int64_t *rp, const int32_t *col, const uin
     orc_row_order(n, rp, sigma, order);
     /* step 2: split */
     int64_t ns = 0, nl = 0;
-    long_ptr[0] = 0;
+    orc_row_key *lk = (orc_row_key *)malloc(sizeof(orc_row_key) * (size_t)(n > 0 ? n : 1));
     for (int64_t p = 0; p < n; p++) {
         int64_t r = order[p], len = rp[r + 1] - rp[r];
         if (tau >= 0 && len > tau) {
-            long_row[nl] = (int32_t)r;
-            for (int64_t j = 0; j < len; j++) {
-                memcpy(long_val + (long_ptr[nl] + j) * esz, val + (rp[r] + j) * esz, (size_t)esz);
-                long_col[long_ptr[nl] + j] = col[rp[r] + j];
-            }
-            long_ptr[nl + 1] = long_ptr[nl] + len;
+            lk[nl].len = len;
+            lk[nl].idx = r;
             nl++;
         } else {
             short_row[ns] = (int32_t)r;
@@ -301,6 +298,19 @@ void orc_rgcsr_build(int64_t n, const int64_t *rp, const int32_t *col, const uin
             ns++;
         }
     }
+    /* step 6: long list longest first, ties by original row */
+    qsort(lk, (size_t)nl, sizeof(orc_row_key), orc_cmp_desc);
+    long_ptr[0] = 0;
+    for (int64_t i = 0; i < nl; i++) {
+        int64_t r = lk[i].idx, len = lk[i].len;
+        long_row[i] = (int32_t)r;
+        for (int64_t j = 0; j < len; j++) {
+            memcpy(long_val + (long_ptr[i] + j) * esz, val + (rp[r] + j) * esz, (size_t)esz);
+            long_col[long_ptr[i] + j] = col[rp[r] + j];
+        }
+        long_ptr[i + 1] = long_ptr[i] + len;
+    }
+    free(lk);
     /* steps 3-5: groups, widths, placement */
     int64_t ng = (ns + G - 1) / G;
     gp[0] = 0;

@@ -1,0 +1,424 @@
+"""RgCSR sparse matrix-vector multiplication on AMD Instinct MI355X.
+
+Row-grouped CSR (Oberhuber, Suzuki, Vacata; Section 3.4 of their paper)
+rebuilt for gfx950: the format conversion, the SpMV/SpMM kernels, the Hybrid
+ELL+COO comparison (Section 3.3), a backward pass and a mixed-precision CG all
+live in the native library ``librgcsr.so`` behind the C ABI of
+``include/rgcsr.h``.  This package is the thin Python binding: the functions
+named ``rgcsr_*`` / ``hyb_*`` marshal torch tensors and numpy arrays into those
+C calls and do no arithmetic themselves.  PyTorch provides device memory and
+streams only.
+
+Importing the package does not load the library; the first call does, and
+fails loudly when it has not been built.
+"""
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+
+from . import _lib
+from ._lib import RGCSR_BF16, RGCSR_F16, RGCSR_F32, RGCSR_F64, RgcsrError  # noqa: F401
+
+DTYPE_CODES = {"f64": RGCSR_F64, "f32": RGCSR_F32, "f16": RGCSR_F16, "bf16": RGCSR_BF16}
+CODE_BYTES = {RGCSR_F64: 8, RGCSR_F32: 4, RGCSR_F16: 2, RGCSR_BF16: 2}
+
+
+def _code_of_numpy(a: np.ndarray, bf16_bits: bool = False) -> int:
+    if bf16_bits:
+        return RGCSR_BF16
+    return {np.dtype(np.float64): RGCSR_F64, np.dtype(np.float32): RGCSR_F32,
+            np.dtype(np.float16): RGCSR_F16}[a.dtype]
+
+
+def _np_of_code(code: int):
+    return {RGCSR_F64: np.float64, RGCSR_F32: np.float32, RGCSR_F16: np.float16,
+            RGCSR_BF16: np.uint16}[code]
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _code_of_tensor(t) -> int:
+    torch = _torch()
+    return {torch.float64: RGCSR_F64, torch.float32: RGCSR_F32, torch.float16: RGCSR_F16,
+            torch.bfloat16: RGCSR_BF16}[t.dtype]
+
+
+def _stream(stream=None) -> int:
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return s.cuda_stream
+
+
+def _ptr(a) -> int:
+    if a is None:
+        return 0
+    if isinstance(a, np.ndarray):
+        return a.ctypes.data
+    return a.data_ptr()
+
+
+def _dev_check(t, name: str):
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a CUDA (HIP) tensor")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+
+
+def make_opts(G: int = 64, T: int = 1, sigma: int = 1, tau: int = -1, value_dtype: str = "f32",
+              keep_csr_map: bool = False, build_transpose: bool = False, validate: bool = True) -> _lib.Opts:
+    o = _lib.Opts()
+    o.group_size, o.lanes_per_row, o.sort_window, o.long_row_threshold = G, T, sigma, tau
+    o.value_dtype = DTYPE_CODES[value_dtype]
+    o.keep_csr_map, o.build_transpose, o.validate = int(keep_csr_map), int(build_transpose), int(validate)
+    return o
+
+
+def _csr_arrays(A):
+    rp = np.ascontiguousarray(A.row_ptr, dtype=np.int64)
+    col = np.ascontiguousarray(A.col, dtype=np.int32)
+    val = np.ascontiguousarray(A.val)
+    return rp, col, val
+
+
+# ----------------------------------------------------------------------------
+# Host-only layout (no GPU)
+# ----------------------------------------------------------------------------
+def rgcsr_layout_sizes(A, opts: _lib.Opts) -> dict:
+    rp, col, _ = _csr_arrays(A)
+    info = _lib.Info()
+    _lib.call("rgcsr_layout_sizes", A.n_rows, A.n_cols, int(rp[-1]) if rp.size else 0, _ptr(rp),
+              _ptr(col), ctypes.byref(opts), ctypes.byref(info))
+    return info.as_dict()
+
+
+def rgcsr_layout_host(A, opts: _lib.Opts, bf16_bits: bool = False) -> dict:
+    rp, col, val = _csr_arrays(A)
+    s = rgcsr_layout_sizes(A, opts)
+    vt = _np_of_code(opts.value_dtype)
+    out = dict(gp=np.zeros(s["n_groups"] + 1, np.int64), short_len=np.zeros(s["n_short"], np.int32),
+               short_row=np.zeros(s["n_short"], np.int32), slot_val=np.zeros(s["slots"], vt),
+               slot_col=np.zeros(s["slots"], np.int32), long_row=np.zeros(s["n_long"], np.int32),
+               long_ptr=np.zeros(s["n_long"] + 1, np.int64), long_val=np.zeros(s["long_nnz"], vt),
+               long_col=np.zeros(s["long_nnz"], np.int32))
+    _lib.call("rgcsr_layout_host", A.n_rows, A.n_cols, int(rp[-1]), _ptr(rp), _ptr(col), _ptr(val),
+              _code_of_numpy(val, bf16_bits), ctypes.byref(opts),
+              *[_ptr(out[k]) for k in ("gp", "short_len", "short_row", "slot_val", "slot_col",
+                                       "long_row", "long_ptr", "long_val", "long_col")])
+    out.update(s)
+    return out
+
+
+def hyb_choose_width(A, value_dtype: str = "f32") -> int:
+    rp = np.ascontiguousarray(A.row_ptr, dtype=np.int64)
+    k = ctypes.c_int64(0)
+    _lib.call("hyb_choose_width", A.n_rows, _ptr(rp), DTYPE_CODES[value_dtype], ctypes.byref(k))
+    return int(k.value)
+
+
+# ----------------------------------------------------------------------------
+# Device handles
+# ----------------------------------------------------------------------------
+class RgCSRMatrix:
+    """Owns one librgcsr handle (a matrix or a block-diagonal batch)."""
+
+    def __init__(self, handle: int):
+        self._h = ctypes.c_void_p(handle)
+        info = _lib.Info()
+        _lib.call("rgcsr_info", self._h, ctypes.byref(info))
+        self.info = info.as_dict()
+        self.n_rows, self.n_cols, self.nnz = self.info["n_rows"], self.info["n_cols"], self.info["nnz"]
+        self.value_dtype = self.info["value_dtype"]
+
+    @property
+    def handle(self):
+        return self._h
+
+    def close(self):
+        if self._h is not None and self._h.value:
+            _lib.call("rgcsr_destroy", self._h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # convenience forwarding to the module-level C-named functions
+    def spmv(self, x, y=None, stream=None):
+        torch = _torch()
+        if y is None:
+            y = torch.empty(self.n_rows, dtype=x.dtype, device=x.device)
+        rgcsr_spmv(self, x, y, stream)
+        return y
+
+    def spmm(self, X, Y=None, persistent: bool = False, stream=None):
+        torch = _torch()
+        if Y is None:
+            Y = torch.empty((self.n_rows, X.shape[1]), dtype=X.dtype, device=X.device)
+        rgcsr_spmv_batched(self, X, Y, persistent, stream)
+        return Y
+
+    def export(self, stream=None) -> dict:
+        return rgcsr_export(self, stream)
+
+    def clone(self, stream=None) -> "RgCSRMatrix":
+        return rgcsr_clone(self, stream)
+
+    def to_csr(self, stream=None):
+        return rgcsr_to_csr(self, stream)
+
+    def batch_offsets(self):
+        return rgcsr_batch_offsets(self)
+
+
+def rgcsr_from_csr(A, opts: _lib.Opts | None = None, stream=None, bf16_bits: bool = False,
+                   on_device: bool = False, **kw) -> RgCSRMatrix:
+    """Convert a host CSR matrix (workloads.CSR) to a device RgCSR handle."""
+    opts = opts if opts is not None else make_opts(**kw)
+    rp, col, val = _csr_arrays(A)
+    h = ctypes.c_void_p()
+    _lib.call("rgcsr_from_csr", A.n_rows, A.n_cols, int(rp[-1]), _ptr(rp), _ptr(col), _ptr(val),
+              _code_of_numpy(val, bf16_bits), ctypes.byref(opts), 0, _stream(stream), ctypes.byref(h))
+    return RgCSRMatrix(h.value)
+
+
+def rgcsr_from_csr_device(n_rows: int, n_cols: int, row_ptr, col, vals, opts: _lib.Opts, stream=None) -> RgCSRMatrix:
+    """Same as rgcsr_from_csr with CSR arrays already in device memory (torch tensors)."""
+    h = ctypes.c_void_p()
+    _lib.call("rgcsr_from_csr", n_rows, n_cols, int(col.numel()), _ptr(row_ptr), _ptr(col), _ptr(vals),
+              _code_of_tensor(vals), ctypes.byref(opts), 1, _stream(stream), ctypes.byref(h))
+    return RgCSRMatrix(h.value)
+
+
+def rgcsr_from_csr_batch(mats, opts: _lib.Opts | None = None, stream=None, **kw) -> RgCSRMatrix:
+    """One handle for a list of host CSR matrices (block-diagonal batch)."""
+    opts = opts if opts is not None else make_opts(**kw)
+    n = len(mats)
+    arrs = [_csr_arrays(A) for A in mats]
+    nr = np.array([A.n_rows for A in mats], np.int64)
+    nc = np.array([A.n_cols for A in mats], np.int64)
+    rps = (ctypes.c_void_p * n)(*[_ptr(a[0]) for a in arrs])
+    cols = (ctypes.c_void_p * n)(*[_ptr(a[1]) for a in arrs])
+    vals = (ctypes.c_void_p * n)(*[_ptr(a[2]) for a in arrs])
+    codes = {_code_of_numpy(a[2]) for a in arrs}
+    if len(codes) != 1:
+        raise ValueError("all matrices of a batch must share one value dtype")
+    h = ctypes.c_void_p()
+    _lib.call("rgcsr_from_csr_batch", n, _ptr(nr), _ptr(nc), ctypes.addressof(rps), ctypes.addressof(cols),
+              ctypes.addressof(vals), codes.pop(), ctypes.byref(opts), _stream(stream), ctypes.byref(h))
+    return RgCSRMatrix(h.value)
+
+
+def rgcsr_clone(A: RgCSRMatrix, stream=None) -> RgCSRMatrix:
+    h = ctypes.c_void_p()
+    _lib.call("rgcsr_clone", A.handle, _stream(stream), ctypes.byref(h))
+    return RgCSRMatrix(h.value)
+
+
+def rgcsr_batch_offsets(A: RgCSRMatrix):
+    m = A.info["n_matrices"]
+    ro = np.zeros(m + 1, np.int64)
+    co = np.zeros(m + 1, np.int64)
+    _lib.call("rgcsr_batch_offsets", A.handle, _ptr(ro), _ptr(co))
+    return ro, co
+
+
+def rgcsr_spmv(A: RgCSRMatrix, x, y, stream=None) -> None:
+    """y = A x (device tensors, float32 or float64)."""
+    _dev_check(x, "x")
+    _dev_check(y, "y")
+    if x.dtype != y.dtype or x.numel() != A.n_cols or y.numel() != A.n_rows:
+        raise ValueError("x/y shape or dtype mismatch")
+    _lib.call("rgcsr_spmv", A.handle, _ptr(x), _ptr(y), _code_of_tensor(x), _stream(stream))
+
+
+def rgcsr_spmv_batched(A: RgCSRMatrix, X, Y, persistent: bool = False, stream=None) -> None:
+    """Y = A X for X of shape (n_cols, k), row-major; Y of shape (n_rows, k)."""
+    _dev_check(X, "X")
+    _dev_check(Y, "Y")
+    if X.dim() == 1:
+        X, Y = X.view(-1, 1), Y.view(-1, 1)
+    if X.shape[0] != A.n_cols or Y.shape[0] != A.n_rows or X.shape[1] != Y.shape[1] or X.dtype != Y.dtype:
+        raise ValueError("X/Y shape or dtype mismatch")
+    k = X.shape[1]
+    _lib.call("rgcsr_spmv_batched", A.handle, k, _ptr(X), X.stride(0), _ptr(Y), Y.stride(0),
+              _code_of_tensor(X), int(persistent), _stream(stream))
+
+
+def rgcsr_spmv_transpose_grad(A: RgCSRMatrix, x, dy, dx=None, dvals=None, stream=None) -> None:
+    """dx = A^T dy and dvals[k] = dy[row(k)] * x[col(k)] (CSR order)."""
+    _dev_check(dy, "dy")
+    for t, nm in ((x, "x"), (dx, "dx"), (dvals, "dvals")):
+        if t is not None:
+            _dev_check(t, nm)
+    _lib.call("rgcsr_spmv_transpose_grad", A.handle, _ptr(x), _ptr(dy), _ptr(dx), _ptr(dvals),
+              _code_of_tensor(dy), _stream(stream))
+
+
+def rgcsr_set_values(A: RgCSRMatrix, vals, stream=None) -> None:
+    """Overwrite stored values from CSR-ordered values (device tensor or numpy array)."""
+    if isinstance(vals, np.ndarray):
+        v = np.ascontiguousarray(vals)
+        _lib.call("rgcsr_set_values", A.handle, _ptr(v), _code_of_numpy(v), 0, _stream(stream))
+    else:
+        _dev_check(vals, "vals")
+        _lib.call("rgcsr_set_values", A.handle, _ptr(vals), _code_of_tensor(vals), 1, _stream(stream))
+
+
+def rgcsr_export(A: RgCSRMatrix, stream=None) -> dict:
+    i = A.info
+    vt = _np_of_code(A.value_dtype)
+    out = dict(gp=np.zeros(i["n_groups"] + 1, np.int64), short_len=np.zeros(i["n_short"], np.int32),
+               short_row=np.zeros(i["n_short"], np.int32), slot_val=np.zeros(i["slots"], vt),
+               slot_col=np.zeros(i["slots"], np.int32), long_row=np.zeros(i["n_long"], np.int32),
+               long_ptr=np.zeros(i["n_long"] + 1, np.int64), long_val=np.zeros(i["long_nnz"], vt),
+               long_col=np.zeros(i["long_nnz"], np.int32))
+    _lib.call("rgcsr_export", A.handle, _stream(stream),
+              *[_ptr(out[k]) for k in ("gp", "short_len", "short_row", "slot_val", "slot_col",
+                                       "long_row", "long_ptr", "long_val", "long_col")])
+    return out
+
+
+def rgcsr_to_csr(A: RgCSRMatrix, stream=None):
+    rp = np.zeros(A.n_rows + 1, np.int64)
+    col = np.zeros(A.nnz, np.int32)
+    val = np.zeros(A.nnz, _np_of_code(A.value_dtype))
+    _lib.call("rgcsr_to_csr", A.handle, _stream(stream), _ptr(rp), _ptr(col), _ptr(val))
+    return rp, col, val
+
+
+# ----------------------------------------------------------------------------
+# Hybrid ELL + COO
+# ----------------------------------------------------------------------------
+class HybMatrix:
+    def __init__(self, handle: int):
+        self._h = ctypes.c_void_p(handle)
+        info = _lib.HybInfo()
+        _lib.call("hyb_info", self._h, ctypes.byref(info))
+        self.info = info.as_dict()
+        self.n_rows, self.n_cols = self.info["n_rows"], self.info["n_cols"]
+        self.value_dtype = self.info["value_dtype"]
+
+    @property
+    def handle(self):
+        return self._h
+
+    def close(self):
+        if self._h is not None and self._h.value:
+            _lib.call("hyb_destroy", self._h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def spmv(self, x, y=None, stream=None):
+        torch = _torch()
+        if y is None:
+            y = torch.empty(self.n_rows, dtype=x.dtype, device=x.device)
+        hyb_spmv(self, x, y, stream)
+        return y
+
+    def clone(self, stream=None) -> "HybMatrix":
+        h = ctypes.c_void_p()
+        _lib.call("hyb_clone", self.handle, _stream(stream), ctypes.byref(h))
+        return HybMatrix(h.value)
+
+
+def hyb_from_csr(A, value_dtype: str = "f32", ell_width: int = -1, validate: bool = True,
+                 stream=None) -> HybMatrix:
+    rp, col, val = _csr_arrays(A)
+    h = ctypes.c_void_p()
+    _lib.call("hyb_from_csr", A.n_rows, A.n_cols, int(rp[-1]), _ptr(rp), _ptr(col), _ptr(val),
+              _code_of_numpy(val), DTYPE_CODES[value_dtype], ell_width, int(validate), _stream(stream),
+              ctypes.byref(h))
+    return HybMatrix(h.value)
+
+
+def hyb_spmv(A: HybMatrix, x, y, stream=None) -> None:
+    _dev_check(x, "x")
+    _dev_check(y, "y")
+    if x.numel() != A.n_cols or y.numel() != A.n_rows or x.dtype != y.dtype:
+        raise ValueError("x/y shape or dtype mismatch")
+    _lib.call("hyb_spmv", A.handle, _ptr(x), _ptr(y), _code_of_tensor(x), _stream(stream))
+
+
+def hyb_export(A: HybMatrix, stream=None) -> dict:
+    i = A.info
+    ne = i["n_pad"] * i["ell_width"]
+    vt = _np_of_code(A.value_dtype)
+    out = dict(ell_col=np.zeros(ne, np.int32), ell_val=np.zeros(ne, vt),
+               coo_row=np.zeros(i["coo_nnz"], np.int32), coo_col=np.zeros(i["coo_nnz"], np.int32),
+               coo_val=np.zeros(i["coo_nnz"], vt))
+    _lib.call("hyb_export", A.handle, _stream(stream),
+              *[_ptr(out[k]) for k in ("ell_col", "ell_val", "coo_row", "coo_col", "coo_val")])
+    return out
+
+
+# ----------------------------------------------------------------------------
+# Conjugate gradients
+# ----------------------------------------------------------------------------
+def rgcsr_cg_solve(A_lo: RgCSRMatrix, A_hi: RgCSRMatrix, b, x, tol: float = 1e-10, inner_tol: float = 1e-4,
+                   max_outer: int = 50, max_inner: int = 500, stream=None) -> dict:
+    """Mixed-precision CG with FP64 refinement; b, x float64 device tensors."""
+    _dev_check(b, "b")
+    _dev_check(x, "x")
+    st = _lib.CGStats()
+    _lib.call("rgcsr_cg_solve", A_lo.handle, A_hi.handle, _ptr(b), _ptr(x), tol, inner_tol, max_outer,
+              max_inner, _stream(stream), ctypes.byref(st))
+    return st.as_dict()
+
+
+def rgcsr_cg_solve_f64(A: RgCSRMatrix, b, x, tol: float = 1e-10, max_iter: int = 2000, stream=None) -> dict:
+    _dev_check(b, "b")
+    _dev_check(x, "x")
+    st = _lib.CGStats()
+    _lib.call("rgcsr_cg_solve_f64", A.handle, _ptr(b), _ptr(x), tol, max_iter, _stream(stream),
+              ctypes.byref(st))
+    return st.as_dict()
+
+
+def version() -> str:
+    return _lib.load().rgcsr_version().decode()
+
+
+# ----------------------------------------------------------------------------
+# Autograd
+# ----------------------------------------------------------------------------
+def spmv_function():
+    """torch.autograd.Function computing y = A(theta) x with the hand-written
+    adjoint (rgcsr_spmv_transpose_grad).  The matrix must be built with
+    keep_csr_map or build_transpose; theta holds its values in CSR order."""
+    torch = _torch()
+
+    class SpMVFunction(torch.autograd.Function):
+        @staticmethod
+        def forward(ctx, theta, x, A):
+            rgcsr_set_values(A, theta.detach().contiguous())
+            y = torch.empty(A.n_rows, dtype=x.dtype, device=x.device)
+            rgcsr_spmv(A, x.detach().contiguous(), y)
+            ctx.A = A
+            ctx.save_for_backward(x)
+            return y
+
+        @staticmethod
+        def backward(ctx, dy):
+            (x,) = ctx.saved_tensors
+            A = ctx.A
+            dy = dy.contiguous()
+            need_theta, need_x = ctx.needs_input_grad[0], ctx.needs_input_grad[1]
+            dvals = torch.empty(A.nnz, dtype=dy.dtype, device=dy.device) if need_theta else None
+            dx = torch.empty(A.n_cols, dtype=dy.dtype, device=dy.device) if need_x else None
+            if dvals is not None or dx is not None:
+                rgcsr_spmv_transpose_grad(A, x.contiguous(), dy, dx, dvals)
+            return dvals, dx, None
+
+    return SpMVFunction

@@ -1,0 +1,64 @@
+"""Compile librgcsr.so for gfx950 in-tree with hipcc.
+
+    python -m paper_1012_2270_amd.build
+
+Every HIP source is compiled with packed-FP32 instructions disabled
+(``-Xclang -target-feature -Xclang -packed-fp32-ops``); the host pass warns
+that it does not know the feature, which is harmless.
+"""
+from __future__ import annotations
+
+import os
+import subprocess
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+CSRC = os.path.join(HERE, "csrc")
+OUT = os.path.join(HERE, "librgcsr.so")
+BUILD_DIR = os.path.join(HERE, "_build")
+SOURCES = ["host_layout.cpp", "abi.cpp", "kernels.hip"]
+ARCH = os.environ.get("RGCSR_OFFLOAD_ARCH", "gfx950")
+
+HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+CFLAGS = [f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-Wall",
+          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
+
+
+def _quiet(out: str) -> str:
+    keep = [ln for ln in out.splitlines() if "packed-fp32-ops" not in ln and ln.strip()]
+    return "\n".join(keep)
+
+
+def build(verbose: bool = False) -> str:
+    """Compile every source (always) and link the shared library."""
+    os.makedirs(BUILD_DIR, exist_ok=True)
+    procs = []
+    objs = []
+    for src in SOURCES:
+        obj = os.path.join(BUILD_DIR, src.rsplit(".", 1)[0] + ".o")
+        objs.append(obj)
+        cmd = [HIPCC, *CFLAGS, "-I", os.path.join(HERE, "..", "include"), "-c",
+               os.path.join(CSRC, src), "-o", obj]
+        procs.append((src, cmd, subprocess.Popen(cmd, stdout=subprocess.PIPE,
+                                                 stderr=subprocess.STDOUT, text=True)))
+    failed = []
+    for src, cmd, p in procs:
+        out, _ = p.communicate()
+        msg = _quiet(out)
+        if p.returncode != 0:
+            failed.append(f"{src}: {' '.join(cmd)}\n{msg}")
+        elif verbose and msg:
+            print(f"[{src}]\n{msg}", file=sys.stderr)
+    if failed:
+        raise RuntimeError("hipcc failed:\n" + "\n\n".join(failed))
+    tmp = OUT + ".tmp"
+    cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs]
+    r = subprocess.run(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True)
+    if r.returncode != 0:
+        raise RuntimeError("link failed: " + " ".join(cmd) + "\n" + r.stdout)
+    os.replace(tmp, OUT)
+    return OUT
+
+
+if __name__ == "__main__":
+    print(build(verbose=True))

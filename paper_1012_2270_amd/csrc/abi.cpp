@@ -1,0 +1,1069 @@
+// C ABI of librgcsr (declared in include/rgcsr.h): handles, conversion,
+// launches, value updates, backward pass, Hybrid and the CG drivers.
+#include <hip/hip_runtime_api.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <mutex>
+#include <new>
+#include <string>
+#include <type_traits>
+#include <vector>
+
+#include "internal.h"
+#include "kernels.h"
+
+namespace rg {
+
+static thread_local std::string g_last_error;
+void set_last_error(const std::string &msg) { g_last_error = msg; }
+
+#define HIPCHK(expr)                                                                                   \
+    do {                                                                                               \
+        hipError_t e_ = (expr);                                                                        \
+        if (e_ != hipSuccess)                                                                          \
+            ::rg::fail(e_ == hipErrorOutOfMemory ? RGCSR_ENOMEM : RGCSR_EHIP,                           \
+                       std::string(#expr) + ": " + hipGetErrorString(e_));                             \
+    } while (0)
+
+static int current_device() {
+    int d = 0;
+    HIPCHK(hipGetDevice(&d));
+    return d;
+}
+
+static int cu_count(int dev) {
+    static std::mutex mu;
+    static std::vector<int> cache;
+    std::lock_guard<std::mutex> lk(mu);
+    if ((int)cache.size() <= dev) cache.resize(dev + 1, 0);
+    if (cache[dev] == 0) {
+        int n = 0;
+        HIPCHK(hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev));
+        cache[dev] = n > 0 ? n : 256;
+    }
+    return cache[dev];
+}
+
+// One device allocation carved into 256-byte aligned arrays.
+struct Arena {
+    std::vector<std::pair<void **, size_t>> req;
+    size_t total = 0;
+    template <class T> void add(T **p, size_t count) {
+        if (count == 0) {
+            *p = nullptr;
+            return;
+        }
+        req.push_back({(void **)p, count * sizeof(T)});
+        total += (count * sizeof(T) + 255) / 256 * 256;
+    }
+    void *commit() {
+        if (total == 0) return nullptr;
+        void *base = nullptr;
+        HIPCHK(hipMalloc(&base, total));
+        size_t off = 0;
+        for (auto &r : req) {
+            *r.first = (char *)base + off;
+            off += (r.second + 255) / 256 * 256;
+        }
+        return base;
+    }
+};
+
+template <class T> static void upload(T *dst, const std::vector<T> &src, hipStream_t st) {
+    if (!src.empty() && dst) HIPCHK(hipMemcpyAsync(dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice, st));
+}
+static void upload_bytes(void *dst, const std::vector<uint8_t> &src, hipStream_t st) {
+    if (!src.empty() && dst) HIPCHK(hipMemcpyAsync(dst, src.data(), src.size(), hipMemcpyHostToDevice, st));
+}
+
+}  // namespace rg
+
+using namespace rg;
+
+struct rgcsr_matrix_s {
+    int device = 0;
+    LayoutParams prm{};
+    int vdt = RGCSR_F32, esz = 4;
+    int64_t n_rows = 0, n_cols = 0, nnz = 0, ng = 0, ns = 0, nl = 0, slots = 0, long_nnz = 0;
+    int64_t n_matrices = 1, n_work = 0, n_partials = 0;
+    bool ragged = false, perm = false;
+    int32_t wpg = 0, gpw = 0;
+    std::vector<int64_t> row_off, col_off;
+    void *mem = nullptr;
+    size_t bytes = 0;
+    int64_t *gp = nullptr;
+    int32_t *grp_row0 = nullptr, *short_len = nullptr, *short_row = nullptr, *slot_col = nullptr;
+    void *slot_val = nullptr;
+    LongItem *work = nullptr;
+    int32_t *long_row = nullptr, *long_col = nullptr;
+    int64_t *long_ptr = nullptr;
+    void *long_val = nullptr;
+    void *partial = nullptr;
+    int32_t *counter = nullptr;
+    int64_t *row_ptr = nullptr;  // CSR map, nullable
+    rgcsr_matrix_s *AT = nullptr;
+    int32_t *t_map_slot = nullptr, *t_map_long = nullptr;
+};
+
+struct hyb_matrix_s {
+    int device = 0;
+    int vdt = RGCSR_F32, esz = 4;
+    int64_t n_rows = 0, n_cols = 0, nnz = 0, n_pad = 0, K1 = 0, m = 0;
+    void *mem = nullptr;
+    size_t bytes = 0;
+    int32_t *ell_col = nullptr, *coo_row = nullptr, *coo_col = nullptr;
+    void *ell_val = nullptr, *coo_val = nullptr;
+};
+
+#define ABI_TRY try {
+#define ABI_CATCH                                                                                      \
+    }                                                                                                  \
+    catch (const rg::Error &e) {                                                                       \
+        rg::set_last_error(e.msg);                                                                     \
+        return e.st;                                                                                   \
+    }                                                                                                  \
+    catch (const std::bad_alloc &) {                                                                   \
+        rg::set_last_error("host allocation failed");                                                  \
+        return RGCSR_ENOMEM;                                                                           \
+    }                                                                                                  \
+    catch (...) {                                                                                      \
+        rg::set_last_error("unexpected internal error");                                               \
+        return RGCSR_EINVAL;                                                                           \
+    }                                                                                                  \
+    return RGCSR_OK;
+
+namespace {
+
+void check_dtype(int dt, const char *what) {
+    if (dtype_size(dt) == 0) fail(RGCSR_EINVAL, std::string("bad dtype for ") + what);
+}
+
+void check_device_geometry(const LayoutParams &p) {
+    const int64_t GT = (int64_t)p.G * p.T;
+    if (!(GT % 64 == 0 || 64 % GT == 0))
+        fail(RGCSR_EUNSUPPORTED, "device kernels need group_size * lanes_per_row to be a multiple or a divisor of 64");
+}
+
+// Host layout (+ transposed layout) for one or more CSR matrices.
+struct Built {
+    HostLayout L;
+    bool has_T = false;
+    HostLayout LT;       // layout of A^T with values
+    HostLayout LTmap;    // layout of A^T whose "values" are source indices
+    std::vector<int64_t> row_ptr;  // global CSR row pointers
+};
+
+void build_host(Built &B, const LayoutParams &p, int vdt, int32_t count, const int64_t *n_rows,
+                const int64_t *n_cols, const int64_t *const *rp, const int32_t *const *col,
+                const void *const *vals, int vals_dt, bool validate, bool keep_map, bool transpose) {
+    const int esz = dtype_size(vdt);
+    B.L.G = p.G; B.L.T = p.T; B.L.sigma = p.sigma; B.L.tau = p.tau; B.L.vdt = vdt; B.L.esz = esz;
+    B.has_T = transpose;
+    if (transpose) {
+        B.LT = B.L;
+        B.LTmap = B.L;
+        B.LTmap.esz = 4;
+    }
+    if (keep_map || transpose) B.row_ptr.assign(1, 0);
+    int64_t nnz_base = 0;
+    std::vector<uint8_t> conv;
+    for (int32_t m = 0; m < count; m++) {
+        const int64_t nr = n_rows[m], nc = n_cols[m];
+        if (nr < 0 || nc < 0) fail(RGCSR_EINVAL, "negative matrix size");
+        if (!rp[m]) fail(RGCSR_EINVAL, "row_ptr is null");
+        const int64_t nnz = rp[m][nr];
+        if (validate) validate_csr(nr, nc, nnz, rp[m], col[m]);
+        if (nnz > 0 && !vals[m]) fail(RGCSR_EINVAL, "vals is null");
+        conv.resize((size_t)nnz * esz);
+        if (nnz) convert_values(vals[m], vals_dt, conv.data(), vdt, nnz);
+        append_layout(B.L, p, nr, nc, rp[m], col[m], conv.data(), esz, 0);
+        if (!B.row_ptr.empty())
+            for (int64_t r = 0; r < nr; r++) B.row_ptr.push_back(nnz_base + rp[m][r + 1]);
+        if (transpose) {
+            std::vector<int64_t> rpT;
+            std::vector<int32_t> colT, srcT;
+            transpose_csr(nr, nc, rp[m], col[m], rpT, colT, srcT);
+            std::vector<uint8_t> valsT((size_t)nnz * esz);
+            for (int64_t k = 0; k < nnz; k++) memcpy(&valsT[(size_t)k * esz], &conv[(size_t)srcT[k] * esz], esz);
+            std::vector<int32_t> mapT(nnz);
+            if (nnz_base + nnz > INT32_MAX) fail(RGCSR_EOVERFLOW, "transpose map needs total nnz < 2^31");
+            for (int64_t k = 0; k < nnz; k++) mapT[k] = (int32_t)(srcT[k] + nnz_base);
+            append_layout(B.LT, p, nc, nr, rpT.data(), colT.data(), valsT.data(), esz, 0);
+            append_layout(B.LTmap, p, nc, nr, rpT.data(), colT.data(), (const uint8_t *)mapT.data(), 4, 0xff);
+        }
+        nnz_base += nnz;
+    }
+    build_long_work(B.L.long_ptr, B.L.work, B.L.n_partials);
+    if (transpose) build_long_work(B.LT.long_ptr, B.LT.work, B.LT.n_partials);
+}
+
+rgcsr_matrix_s *make_device(const HostLayout &L, const std::vector<int64_t> *row_ptr,
+                            const HostLayout *map, hipStream_t st) {
+    auto *h = new rgcsr_matrix_s();
+    try {
+        h->device = current_device();
+        h->prm = LayoutParams{L.G, L.T, L.sigma, L.tau};
+        h->vdt = L.vdt;
+        h->esz = L.esz;
+        h->n_rows = L.n_rows; h->n_cols = L.n_cols; h->nnz = L.nnz;
+        h->ng = L.ng; h->ns = L.ns; h->nl = L.nl; h->slots = L.slots; h->long_nnz = L.long_nnz;
+        h->n_matrices = L.n_matrices;
+        h->n_work = (int64_t)L.work.size();
+        h->n_partials = L.n_partials;
+        h->ragged = L.ragged;
+        h->perm = !L.short_identity();
+        h->row_off = L.row_off;
+        h->col_off = L.col_off;
+        const int64_t GT = (int64_t)L.G * L.T;
+        h->wpg = GT >= 64 ? (int32_t)(GT / 64) : 0;
+        h->gpw = GT < 64 ? (int32_t)(64 / GT) : 0;
+
+        Arena a;
+        a.add(&h->gp, L.gp.size());
+        a.add(&h->grp_row0, h->ragged ? L.grp_row0.size() : 0);
+        a.add(&h->short_len, L.short_len.size());
+        a.add(&h->short_row, h->perm ? L.short_row.size() : 0);
+        a.add((uint8_t **)&h->slot_val, L.slot_val.size());
+        a.add(&h->slot_col, L.slot_col.size());
+        a.add(&h->work, L.work.size());
+        a.add(&h->long_row, L.long_row.size());
+        a.add(&h->long_ptr, L.long_ptr.size());
+        a.add((uint8_t **)&h->long_val, L.long_val.size());
+        a.add(&h->long_col, L.long_col.size());
+        a.add((uint8_t **)&h->partial, (size_t)L.n_partials * 32 * sizeof(double));
+        a.add(&h->counter, (size_t)L.n_partials);
+        if (row_ptr) a.add(&h->row_ptr, row_ptr->size());
+        if (map) {
+            a.add(&h->t_map_slot, (size_t)map->slots);
+            a.add(&h->t_map_long, (size_t)map->long_nnz);
+        }
+        h->mem = a.commit();
+        h->bytes = a.total;
+        upload(h->gp, L.gp, st);
+        if (h->ragged) upload(h->grp_row0, L.grp_row0, st);
+        upload(h->short_len, L.short_len, st);
+        if (h->perm) upload(h->short_row, L.short_row, st);
+        upload_bytes(h->slot_val, L.slot_val, st);
+        upload(h->slot_col, L.slot_col, st);
+        upload(h->work, L.work, st);
+        upload(h->long_row, L.long_row, st);
+        upload(h->long_ptr, L.long_ptr, st);
+        upload_bytes(h->long_val, L.long_val, st);
+        upload(h->long_col, L.long_col, st);
+        if (h->counter) HIPCHK(hipMemsetAsync(h->counter, 0, (size_t)L.n_partials * sizeof(int32_t), st));
+        if (row_ptr) upload(h->row_ptr, *row_ptr, st);
+        if (map) {
+            if (map->slots) HIPCHK(hipMemcpyAsync(h->t_map_slot, map->slot_val.data(), (size_t)map->slots * 4, hipMemcpyHostToDevice, st));
+            if (map->long_nnz) HIPCHK(hipMemcpyAsync(h->t_map_long, map->long_val.data(), (size_t)map->long_nnz * 4, hipMemcpyHostToDevice, st));
+        }
+        HIPCHK(hipStreamSynchronize(st));
+    } catch (...) {
+        if (h->mem) (void)hipFree(h->mem);
+        delete h;
+        throw;
+    }
+    return h;
+}
+
+void free_handle(rgcsr_matrix_s *h) {
+    if (!h) return;
+    if (h->AT) free_handle(h->AT);
+    if (h->mem) (void)hipFree(h->mem);
+    delete h;
+}
+
+void check_handle(const rgcsr_matrix_s *h) {
+    if (!h) fail(RGCSR_EINVAL, "null handle");
+    if (current_device() != h->device) fail(RGCSR_EINVAL, "handle belongs to another device");
+}
+
+int32_t short_waves(const rgcsr_matrix_s *h) {
+    int64_t w = h->wpg > 0 ? h->ng * h->wpg : (h->ng + h->gpw - 1) / h->gpw;
+    if (w > INT32_MAX / 2) fail(RGCSR_EOVERFLOW, "too many wavefronts");
+    return (int32_t)w;
+}
+
+SpmvParams params_of(const rgcsr_matrix_s *h, bool per_row_long) {
+    SpmvParams P{};
+    P.gp = h->gp; P.grp_row0 = h->grp_row0; P.short_len = h->short_len; P.short_row = h->short_row;
+    P.slot_val = h->slot_val; P.slot_col = h->slot_col;
+    P.ng = h->ng; P.ns = h->ns; P.G = h->prm.G; P.wpg = h->wpg; P.gpw = h->gpw;
+    P.ragged = h->ragged; P.perm = h->perm;
+    P.work = h->work; P.long_row = h->long_row; P.long_ptr = h->long_ptr; P.long_val = h->long_val;
+    P.long_col = h->long_col; P.partial = h->partial; P.counter = h->counter;
+    const int64_t lw = per_row_long ? h->nl : h->n_work;
+    const int64_t tot = lw + short_waves(h);
+    if (tot > INT32_MAX / 2) fail(RGCSR_EOVERFLOW, "too many wavefronts");
+    P.n_long_waves = (int32_t)lw;
+    P.total_waves = (int32_t)tot;
+    return P;
+}
+
+int vec_is_f64(rgcsr_dtype vt) {
+    if (vt == RGCSR_F64) return 1;
+    if (vt == RGCSR_F32) return 0;
+    fail(RGCSR_EUNSUPPORTED, "vectors must be F32 or F64");
+}
+
+void spmv_launch(const rgcsr_matrix_s *h, int K, const void *X, int64_t ldx, void *Y, int64_t ldy, int f64,
+                 bool persistent, hipStream_t st) {
+    if (h->n_rows == 0) return;
+    SpmvParams P = params_of(h, false);
+    P.x = X; P.y = Y; P.ldx = ldx; P.ldy = ldy;
+    int64_t nwg = (P.total_waves + 3) / 4;
+    if (persistent) nwg = std::min<int64_t>(nwg, (int64_t)cu_count(h->device) * 8);
+    if (nwg == 0) return;
+    const int vd = h->vdt;
+    if (f64 && !(vd == RGCSR_F64 || vd == RGCSR_F32))
+        fail(RGCSR_EUNSUPPORTED, "F64 vectors need F64 or F32 stored values");
+    if (!f64 && vd == RGCSR_F64) fail(RGCSR_EUNSUPPORTED, "F64 stored values need F64 vectors");
+    if (K > 1 && (vd == RGCSR_F16 || vd == RGCSR_BF16))
+        fail(RGCSR_EUNSUPPORTED, "several right-hand sides need F32 or F64 stored values");
+    hipError_t e = launch_spmv(P, vd, f64, h->prm.T, K, (int)nwg, st);
+    if (e != hipSuccess) fail(RGCSR_EHIP, std::string("spmv launch: ") + hipGetErrorString(e));
+}
+
+int64_t nblocks_vec(int64_t n) { return std::max<int64_t>(1, std::min<int64_t>(512, (n + 255) / 256)); }
+
+}  // namespace
+
+extern "C" {
+
+void rgcsr_default_opts(rgcsr_opts *o) {
+    if (!o) return;
+    o->group_size = 64;
+    o->lanes_per_row = 1;
+    o->sort_window = 1;
+    o->long_row_threshold = -1;
+    o->value_dtype = RGCSR_F32;
+    o->keep_csr_map = 0;
+    o->build_transpose = 0;
+    o->validate = 1;
+}
+
+const char *rgcsr_status_string(rgcsr_status s) {
+    switch (s) {
+    case RGCSR_OK: return "ok";
+    case RGCSR_EINVAL: return "invalid argument";
+    case RGCSR_ECSR: return "malformed CSR input";
+    case RGCSR_ENOMEM: return "out of memory";
+    case RGCSR_EOVERFLOW: return "size overflow";
+    case RGCSR_EHIP: return "HIP runtime error";
+    case RGCSR_EUNSUPPORTED: return "unsupported";
+    }
+    return "unknown status";
+}
+
+const char *rgcsr_last_error(void) { return g_last_error.c_str(); }
+
+const char *rgcsr_version(void) { return "rgcsr 0.1 gfx950"; }
+
+rgcsr_status rgcsr_layout_sizes(int64_t n_rows, int64_t n_cols, int64_t nnz, const int64_t *row_ptr,
+                                const int32_t *col_idx, const rgcsr_opts *opts, rgcsr_info_t *out) {
+    ABI_TRY
+    if (!out) fail(RGCSR_EINVAL, "out is null");
+    const LayoutParams p = resolve_opts(opts);
+    const bool validate = opts ? opts->validate != 0 : true;
+    if (validate) validate_csr(n_rows, n_cols, nnz, row_ptr, col_idx);
+    else if (!row_ptr) fail(RGCSR_EINVAL, "row_ptr is null");
+    std::vector<int64_t> lens;
+    int64_t ng, ns, nl, slots, lz;
+    layout_sizes(p, n_rows, row_ptr, &ng, &ns, &nl, &slots, &lz, &lens);
+    std::vector<int64_t> lp(1, 0);
+    for (int64_t l : lens) lp.push_back(lp.back() + l);
+    std::vector<LongItem> work;
+    int64_t parts = 0;
+    build_long_work(lp, work, parts);
+    *out = rgcsr_info_t{};
+    out->n_rows = n_rows; out->n_cols = n_cols; out->nnz = nnz;
+    out->n_groups = ng; out->n_short = ns; out->n_long = nl; out->slots = slots; out->long_nnz = lz;
+    out->n_matrices = 1; out->long_work = (int64_t)work.size(); out->partials = parts;
+    out->group_size = p.G; out->lanes_per_row = p.T;
+    out->value_dtype = opts ? opts->value_dtype : RGCSR_F32;
+    out->sort_window = p.sigma; out->long_row_threshold = p.tau;
+    ABI_CATCH
+}
+
+rgcsr_status rgcsr_layout_host(int64_t n_rows, int64_t n_cols, int64_t nnz, const int64_t *row_ptr,
+                               const int32_t *col_idx, const void *vals, rgcsr_dtype vals_dtype,
+                               const rgcsr_opts *opts, int64_t *gp, int32_t *short_len, int32_t *short_row,
+                               void *slot_val, int32_t *slot_col, int32_t *long_row, int64_t *long_ptr,
+                               void *long_val, int32_t *long_col) {
+    ABI_TRY
+    const LayoutParams p = resolve_opts(opts);
+    const int vdt = opts ? opts->value_dtype : RGCSR_F32;
+    check_dtype(vdt, "value_dtype");
+    check_dtype(vals_dtype, "vals");
+    const bool validate = opts ? opts->validate != 0 : true;
+    Built B;
+    const int64_t *rps[1] = {row_ptr};
+    const int32_t *cols[1] = {col_idx};
+    const void *vs[1] = {vals};
+    (void)nnz;
+    if (validate) validate_csr(n_rows, n_cols, nnz, row_ptr, col_idx);
+    build_host(B, p, vdt, 1, &n_rows, &n_cols, rps, cols, vs, vals_dtype, false, false, false);
+    const HostLayout &L = B.L;
+    auto put = [](auto *dst, const auto &v) {
+        if (dst && !v.empty()) memcpy(dst, v.data(), v.size() * sizeof(v[0]));
+    };
+    put(gp, L.gp);
+    put(short_len, L.short_len);
+    put(short_row, L.short_row);
+    put((uint8_t *)slot_val, L.slot_val);
+    put(slot_col, L.slot_col);
+    put(long_row, L.long_row);
+    put(long_ptr, L.long_ptr);
+    put((uint8_t *)long_val, L.long_val);
+    put(long_col, L.long_col);
+    ABI_CATCH
+}
+
+rgcsr_status rgcsr_from_csr(int64_t n_rows, int64_t n_cols, int64_t nnz, const int64_t *row_ptr,
+                            const int32_t *col_idx, const void *vals, rgcsr_dtype vals_dtype,
+                            const rgcsr_opts *opts, int inputs_on_device, void *stream, rgcsr_handle *out) {
+    ABI_TRY
+    if (!out) fail(RGCSR_EINVAL, "out is null");
+    *out = nullptr;
+    rgcsr_opts o;
+    if (opts) o = *opts; else rgcsr_default_opts(&o);
+    const LayoutParams p = resolve_opts(&o);
+    check_device_geometry(p);
+    check_dtype(o.value_dtype, "value_dtype");
+    check_dtype(vals_dtype, "vals");
+    if (n_rows < 0 || n_cols < 0 || nnz < 0) fail(RGCSR_EINVAL, "negative size");
+    hipStream_t st = (hipStream_t)stream;
+    std::vector<int64_t> h_rp;
+    std::vector<int32_t> h_col;
+    std::vector<uint8_t> h_val;
+    const int64_t *rp = row_ptr;
+    const int32_t *col = col_idx;
+    const void *val = vals;
+    if (inputs_on_device) {
+        if (!row_ptr) fail(RGCSR_EINVAL, "row_ptr is null");
+        h_rp.resize(n_rows + 1);
+        h_col.resize(nnz);
+        h_val.resize((size_t)nnz * dtype_size(vals_dtype));
+        HIPCHK(hipMemcpyAsync(h_rp.data(), row_ptr, (n_rows + 1) * 8, hipMemcpyDeviceToHost, st));
+        if (nnz) {
+            HIPCHK(hipMemcpyAsync(h_col.data(), col_idx, nnz * 4, hipMemcpyDeviceToHost, st));
+            HIPCHK(hipMemcpyAsync(h_val.data(), vals, h_val.size(), hipMemcpyDeviceToHost, st));
+        }
+        HIPCHK(hipStreamSynchronize(st));
+        rp = h_rp.data();
+        col = h_col.data();
+        val = h_val.data();
+    }
+    if (!rp) fail(RGCSR_EINVAL, "row_ptr is null");
+    if (!o.validate && rp[n_rows] != nnz) fail(RGCSR_ECSR, "row_ptr[n_rows] != nnz");
+    Built B;
+    const bool keep = o.keep_csr_map != 0, tr = o.build_transpose != 0;
+    build_host(B, p, o.value_dtype, 1, &n_rows, &n_cols, &rp, &col, &val, vals_dtype, o.validate != 0, keep, tr);
+    rgcsr_matrix_s *h = make_device(B.L, (keep || tr) ? &B.row_ptr : nullptr, nullptr, st);
+    if (tr) {
+        try {
+            h->AT = make_device(B.LT, nullptr, &B.LTmap, st);
+        } catch (...) {
+            free_handle(h);
+            throw;
+        }
+    }
+    *out = h;
+    ABI_CATCH
+}
+
+rgcsr_status rgcsr_from_csr_batch(int32_t count, const int64_t *n_rows, const int64_t *n_cols,
+                                  const int64_t *const *row_ptr, const int32_t *const *col_idx,
+                                  const void *const *vals, rgcsr_dtype vals_dtype, const rgcsr_opts *opts,
+                                  void *stream, rgcsr_handle *out) {
+    ABI_TRY
+    if (!out) fail(RGCSR_EINVAL, "out is null");
+    *out = nullptr;
+    if (count < 1 || !n_rows || !n_cols || !row_ptr || !col_idx || !vals) fail(RGCSR_EINVAL, "bad batch arrays");
+    rgcsr_opts o;
+    if (opts) o = *opts; else rgcsr_default_opts(&o);
+    const LayoutParams p = resolve_opts(&o);
+    check_device_geometry(p);
+    check_dtype(o.value_dtype, "value_dtype");
+    check_dtype(vals_dtype, "vals");
+    hipStream_t st = (hipStream_t)stream;
+    Built B;
+    const bool keep = o.keep_csr_map != 0, tr = o.build_transpose != 0;
+    build_host(B, p, o.value_dtype, count, n_rows, n_cols, row_ptr, col_idx, vals, vals_dtype, o.validate != 0,
+               keep, tr);
+    rgcsr_matrix_s *h = make_device(B.L, (keep || tr) ? &B.row_ptr : nullptr, nullptr, st);
+    if (tr) {
+        try {
+            h->AT = make_device(B.LT, nullptr, &B.LTmap, st);
+        } catch (...) {
+            free_handle(h);
+            throw;
+        }
+    }
+    *out = h;
+    ABI_CATCH
+}
+
+rgcsr_status rgcsr_batch_offsets(rgcsr_handle A, int64_t *row_off, int64_t *col_off) {
+    ABI_TRY
+    if (!A) fail(RGCSR_EINVAL, "null handle");
+    if (row_off) std::copy(A->row_off.begin(), A->row_off.end(), row_off);
+    if (col_off) std::copy(A->col_off.begin(), A->col_off.end(), col_off);
+    ABI_CATCH
+}
+
+rgcsr_status rgcsr_spmv(rgcsr_handle A, const void *x, void *y, rgcsr_dtype vec_dtype, void *stream) {
+    ABI_TRY
+    check_handle(A);
+    if ((!x && A->n_cols) || (!y && A->n_rows)) fail(RGCSR_EINVAL, "null vector");
+    const int f64 = vec_is_f64(vec_dtype);
+    spmv_launch(A, 1, x, 1, y, 1, f64, false, (hipStream_t)stream);
+    ABI_CATCH
+}
+
+rgcsr_status rgcsr_spmv_batched(rgcsr_handle A, int32_t k, const void *X, int64_t ldx, void *Y, int64_t ldy,
+                                rgcsr_dtype vec_dtype, int32_t persistent, void *stream) {
+    ABI_TRY
+    check_handle(A);
+    if (k < 1) fail(RGCSR_EINVAL, "k must be >= 1");
+    if (ldx < k || ldy < k) fail(RGCSR_EINVAL, "ldx and ldy must be >= k");
+    if ((!X && A->n_cols) || (!Y && A->n_rows)) fail(RGCSR_EINVAL, "null vector");
+    const int f64 = vec_is_f64(vec_dtype);
+    const int esz = f64 ? 8 : 4, vw = f64 ? 2 : 4;
+    int32_t done = 0;
+    while (done < k) {
+        int32_t kb = 1;
+        for (int32_t c : {32, 16, 8, 4, 2, 1})
+            if (c <= k - done) {
+                kb = c;
+                break;
+            }
+        const char *xp = (const char *)X + (size_t)done * esz;
+        char *yp = (char *)Y + (size_t)done * esz;
+        if (kb % vw == 0) {  // kernels use 16-byte vector accesses on X and Y rows
+            const bool vec_ok = ((uintptr_t)xp % 16 == 0) && ((uintptr_t)yp % 16 == 0) && (ldx % vw == 0) &&
+                                (ldy % vw == 0);
+            if (!vec_ok)
+                fail(RGCSR_EINVAL, "k > 1 needs 16-byte aligned X, Y and ldx, ldy multiples of the vector width");
+        }
+        spmv_launch(A, kb, xp, ldx, yp, ldy, f64, persistent != 0, (hipStream_t)stream);
+        done += kb;
+    }
+    ABI_CATCH
+}
+
+rgcsr_status rgcsr_spmv_transpose_grad(rgcsr_handle A, const void *x, const void *dy, void *dx, void *dvals,
+                                       rgcsr_dtype vec_dtype, void *stream) {
+    ABI_TRY
+    check_handle(A);
+    const int f64 = vec_is_f64(vec_dtype);
+    hipStream_t st = (hipStream_t)stream;
+    if (!dy && A->n_rows) fail(RGCSR_EINVAL, "dy is null");
+    if (dvals && !A->row_ptr) fail(RGCSR_EUNSUPPORTED, "dvals needs keep_csr_map or build_transpose");
+    if (dvals && !x && A->n_cols) fail(RGCSR_EINVAL, "x is null");
+    if (A->vdt == RGCSR_F64 && !f64) fail(RGCSR_EUNSUPPORTED, "F64 stored values need F64 vectors");
+    if (f64 && (A->vdt == RGCSR_F16 || A->vdt == RGCSR_BF16)) fail(RGCSR_EUNSUPPORTED, "F64 vectors need F32/F64 values");
+    const bool atomic_dx = dx && !A->AT;
+    if (dx && A->AT) spmv_launch(A->AT, 1, dy, 1, dx, 1, f64, false, st);
+    if (atomic_dx) {
+        hipError_t e = launch_zero(A->n_cols, dx, f64 ? 8 : 4, (int)nblocks_vec(A->n_cols), st);
+        if (e != hipSuccess) fail(RGCSR_EHIP, hipGetErrorString(e));
+    }
+    if ((dvals || atomic_dx) && A->n_rows) {
+        SpmvParams P = params_of(A, true);
+        P.x = x;
+        hipError_t e = launch_grad(P, A->vdt, f64, A->prm.T, dy, dvals, dx, A->row_ptr, dvals != nullptr, atomic_dx, st);
+        if (e != hipSuccess) fail(RGCSR_EHIP, std::string("grad launch: ") + hipGetErrorString(e));
+    }
+    ABI_CATCH
+}
+
+rgcsr_status rgcsr_set_values(rgcsr_handle A, const void *vals, rgcsr_dtype vals_dtype, int on_device,
+                              void *stream) {
+    ABI_TRY
+    check_handle(A);
+    if (!A->row_ptr) fail(RGCSR_EUNSUPPORTED, "set_values needs keep_csr_map or build_transpose");
+    if (!vals && A->nnz) fail(RGCSR_EINVAL, "vals is null");
+    hipStream_t st = (hipStream_t)stream;
+    const void *theta = vals;
+    int theta_f64 = 0;
+    void *tmp = nullptr;
+    if (!on_device || (vals_dtype != RGCSR_F32 && vals_dtype != RGCSR_F64)) {
+        if (on_device) fail(RGCSR_EUNSUPPORTED, "device values must be F32 or F64");
+        const int tdt = vals_dtype == RGCSR_F64 ? RGCSR_F64 : RGCSR_F32;
+        std::vector<uint8_t> conv((size_t)A->nnz * dtype_size(tdt));
+        convert_values(vals, vals_dtype, conv.data(), tdt, A->nnz);
+        HIPCHK(hipMalloc(&tmp, std::max<size_t>(conv.size(), 1)));
+        HIPCHK(hipMemcpyAsync(tmp, conv.data(), conv.size(), hipMemcpyHostToDevice, st));
+        theta = tmp;
+        theta_f64 = tdt == RGCSR_F64;
+    } else {
+        theta_f64 = vals_dtype == RGCSR_F64;
+    }
+    try {
+        if (A->n_rows) {
+            SpmvParams P = params_of(A, true);
+            hipError_t e = launch_setval(P, A->vdt, A->prm.T, theta, theta_f64, A->row_ptr, st);
+            if (e != hipSuccess) fail(RGCSR_EHIP, std::string("set_values: ") + hipGetErrorString(e));
+        }
+        if (A->AT) {
+            hipError_t e = launch_gather_map(A->AT->slots, A->vdt, A->AT->t_map_slot, theta, theta_f64, A->AT->slot_val, st);
+            if (e == hipSuccess)
+                e = launch_gather_map(A->AT->long_nnz, A->vdt, A->AT->t_map_long, theta, theta_f64, A->AT->long_val, st);
+            if (e != hipSuccess) fail(RGCSR_EHIP, std::string("set_values (transpose): ") + hipGetErrorString(e));
+        }
+        if (tmp) {
+            HIPCHK(hipStreamSynchronize(st));
+            HIPCHK(hipFree(tmp));
+            tmp = nullptr;
+        }
+    } catch (...) {
+        if (tmp) {
+            (void)hipStreamSynchronize(st);
+            (void)hipFree(tmp);
+        }
+        throw;
+    }
+    ABI_CATCH
+}
+
+rgcsr_status rgcsr_export(rgcsr_handle A, void *stream, int64_t *gp, int32_t *short_len, int32_t *short_row,
+                          void *slot_val, int32_t *slot_col, int32_t *long_row, int64_t *long_ptr, void *long_val,
+                          int32_t *long_col) {
+    ABI_TRY
+    check_handle(A);
+    hipStream_t st = (hipStream_t)stream;
+    auto get = [&](void *dst, const void *src, size_t bytes) {
+        if (dst && src && bytes) HIPCHK(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, st));
+    };
+    get(gp, A->gp, (A->ng + 1) * 8);
+    get(short_len, A->short_len, A->ns * 4);
+    if (short_row) {
+        if (A->perm) get(short_row, A->short_row, A->ns * 4);
+        else
+            for (int64_t i = 0; i < A->ns; i++) short_row[i] = (int32_t)i;
+    }
+    get(slot_val, A->slot_val, (size_t)A->slots * A->esz);
+    get(slot_col, A->slot_col, (size_t)A->slots * 4);
+    get(long_row, A->long_row, A->nl * 4);
+    get(long_ptr, A->long_ptr, (A->nl + 1) * 8);
+    get(long_val, A->long_val, (size_t)A->long_nnz * A->esz);
+    get(long_col, A->long_col, (size_t)A->long_nnz * 4);
+    HIPCHK(hipStreamSynchronize(st));
+    ABI_CATCH
+}
+
+rgcsr_status rgcsr_to_csr(rgcsr_handle A, void *stream, int64_t *row_ptr, int32_t *col_idx, void *vals) {
+    ABI_TRY
+    check_handle(A);
+    if (!row_ptr || (A->nnz && (!col_idx || !vals))) fail(RGCSR_EINVAL, "null output");
+    const int esz = A->esz;
+    std::vector<int64_t> gp(A->ng + 1), lp(A->nl + 1);
+    std::vector<int32_t> sl(A->ns), sr(A->ns), sc(A->slots), lr(A->nl), lc(A->long_nnz), g0;
+    std::vector<uint8_t> sv((size_t)A->slots * esz), lv((size_t)A->long_nnz * esz);
+    rgcsr_status s = rgcsr_export(A, stream, gp.data(), sl.data(), sr.data(), sv.data(), sc.data(), lr.data(),
+                                  lp.data(), lv.data(), lc.data());
+    if (s != RGCSR_OK) return s;
+    if (A->ragged) {
+        g0.resize(A->ng + 1);
+        HIPCHK(hipMemcpy(g0.data(), A->grp_row0, (A->ng + 1) * 4, hipMemcpyDeviceToHost));
+    }
+    std::vector<int64_t> len(A->n_rows, 0);
+    for (int64_t i = 0; i < A->ns; i++) len[sr[i]] = sl[i];
+    for (int64_t i = 0; i < A->nl; i++) len[lr[i]] = lp[i + 1] - lp[i];
+    row_ptr[0] = 0;
+    for (int64_t r = 0; r < A->n_rows; r++) row_ptr[r + 1] = row_ptr[r] + len[r];
+    const int64_t G = A->prm.G, T = A->prm.T;
+    for (int64_t g = 0; g < A->ng; g++) {
+        const int64_t r0 = A->ragged ? g0[g] : g * G;
+        const int64_t r1 = A->ragged ? g0[g + 1] : std::min<int64_t>(A->ns, r0 + G);
+        const int64_t s = r1 - r0;
+        for (int64_t t = 0; t < s; t++) {
+            const int64_t row = sr[r0 + t], L = sl[r0 + t];
+            for (int64_t j = 0; j < L; j++) {
+                const int64_t slot = gp[g] + (j / T) * (s * T) + t * T + j % T;
+                col_idx[row_ptr[row] + j] = sc[slot];
+                memcpy((uint8_t *)vals + (size_t)(row_ptr[row] + j) * esz, &sv[(size_t)slot * esz], esz);
+            }
+        }
+    }
+    for (int64_t i = 0; i < A->nl; i++) {
+        const int64_t row = lr[i];
+        for (int64_t j = 0; j < lp[i + 1] - lp[i]; j++) {
+            col_idx[row_ptr[row] + j] = lc[lp[i] + j];
+            memcpy((uint8_t *)vals + (size_t)(row_ptr[row] + j) * esz, &lv[(size_t)(lp[i] + j) * esz], esz);
+        }
+    }
+    ABI_CATCH
+}
+
+rgcsr_status rgcsr_info(rgcsr_handle A, rgcsr_info_t *out) {
+    ABI_TRY
+    if (!A || !out) fail(RGCSR_EINVAL, "null argument");
+    *out = rgcsr_info_t{};
+    out->n_rows = A->n_rows; out->n_cols = A->n_cols; out->nnz = A->nnz;
+    out->n_groups = A->ng; out->n_short = A->ns; out->n_long = A->nl; out->slots = A->slots;
+    out->long_nnz = A->long_nnz; out->n_matrices = A->n_matrices; out->long_work = A->n_work;
+    out->partials = A->n_partials; out->group_size = A->prm.G; out->lanes_per_row = A->prm.T;
+    out->value_dtype = A->vdt; out->has_transpose = A->AT != nullptr;
+    out->sort_window = A->prm.sigma; out->long_row_threshold = A->prm.tau;
+    out->device_bytes = (int64_t)A->bytes + (A->AT ? (int64_t)A->AT->bytes : 0);
+    ABI_CATCH
+}
+
+}  // extern "C"
+
+namespace {
+
+// Rebase every device pointer of a copied struct from one arena to another.
+template <class H, class... P> void rebase(H *dst, const H *src, P H::*...members) {
+    auto fix = [&](auto H::*m) {
+        auto &p = dst->*m;
+        if (p) p = (std::remove_reference_t<decltype(p)>)((char *)dst->mem + ((const char *)(src->*m) - (const char *)src->mem));
+    };
+    (fix(members), ...);
+}
+
+rgcsr_matrix_s *clone_handle(const rgcsr_matrix_s *A, hipStream_t st) {
+    auto *h = new rgcsr_matrix_s(*A);
+    h->mem = nullptr;
+    h->AT = nullptr;
+    try {
+        if (A->bytes) HIPCHK(hipMalloc(&h->mem, A->bytes));
+        if (A->bytes) HIPCHK(hipMemcpyAsync(h->mem, A->mem, A->bytes, hipMemcpyDeviceToDevice, st));
+        rebase(h, A, &rgcsr_matrix_s::gp, &rgcsr_matrix_s::grp_row0, &rgcsr_matrix_s::short_len,
+               &rgcsr_matrix_s::short_row, &rgcsr_matrix_s::slot_col, &rgcsr_matrix_s::slot_val,
+               &rgcsr_matrix_s::work, &rgcsr_matrix_s::long_row, &rgcsr_matrix_s::long_col,
+               &rgcsr_matrix_s::long_ptr, &rgcsr_matrix_s::long_val, &rgcsr_matrix_s::partial,
+               &rgcsr_matrix_s::counter, &rgcsr_matrix_s::row_ptr, &rgcsr_matrix_s::t_map_slot,
+               &rgcsr_matrix_s::t_map_long);
+        if (A->AT) h->AT = clone_handle(A->AT, st);
+        HIPCHK(hipStreamSynchronize(st));
+    } catch (...) {
+        free_handle(h);
+        throw;
+    }
+    return h;
+}
+
+}  // namespace
+
+extern "C" {
+
+rgcsr_status rgcsr_clone(rgcsr_handle A, void *stream, rgcsr_handle *out) {
+    ABI_TRY
+    check_handle(A);
+    if (!out) fail(RGCSR_EINVAL, "out is null");
+    *out = clone_handle(A, (hipStream_t)stream);
+    ABI_CATCH
+}
+
+rgcsr_status rgcsr_destroy(rgcsr_handle A) {
+    ABI_TRY
+    if (!A) return RGCSR_OK;
+    (void)hipDeviceSynchronize();
+    free_handle(A);
+    ABI_CATCH
+}
+
+// ---------------------------------------------------------------------------
+// Hybrid
+// ---------------------------------------------------------------------------
+rgcsr_status hyb_choose_width(int64_t n_rows, const int64_t *row_ptr, rgcsr_dtype value_dtype, int64_t *k1) {
+    ABI_TRY
+    if (!row_ptr || !k1 || n_rows < 0) fail(RGCSR_EINVAL, "bad argument");
+    check_dtype(value_dtype, "value_dtype");
+    *k1 = hyb_width_rule(n_rows, row_ptr, dtype_size(value_dtype));
+    ABI_CATCH
+}
+
+rgcsr_status hyb_from_csr(int64_t n_rows, int64_t n_cols, int64_t nnz, const int64_t *row_ptr,
+                          const int32_t *col_idx, const void *vals, rgcsr_dtype vals_dtype, rgcsr_dtype value_dtype,
+                          int64_t ell_width, int validate, void *stream, hyb_handle *out) {
+    ABI_TRY
+    if (!out) fail(RGCSR_EINVAL, "out is null");
+    *out = nullptr;
+    check_dtype(vals_dtype, "vals");
+    check_dtype(value_dtype, "value_dtype");
+    if (validate) validate_csr(n_rows, n_cols, nnz, row_ptr, col_idx);
+    else if (!row_ptr || row_ptr[n_rows] != nnz) fail(RGCSR_ECSR, "row_ptr[n_rows] != nnz");
+    const int esz = dtype_size(value_dtype);
+    std::vector<uint8_t> conv((size_t)nnz * esz);
+    if (nnz) convert_values(vals, vals_dtype, conv.data(), value_dtype, nnz);
+    const int64_t K1 = ell_width >= 0 ? ell_width : hyb_width_rule(n_rows, row_ptr, esz);
+    const int64_t n_pad = (n_rows + 63) / 64 * 64;
+    if (K1 > 0 && n_pad > INT64_MAX / K1) fail(RGCSR_EOVERFLOW, "ELL too large");
+    std::vector<int32_t> ecol((size_t)(n_pad * K1), -1);
+    std::vector<uint8_t> eval((size_t)(n_pad * K1) * esz, 0);
+    int64_t m = 0;
+    for (int64_t i = 0; i < n_rows; i++) m += std::max<int64_t>(0, row_ptr[i + 1] - row_ptr[i] - K1);
+    std::vector<int32_t> crow(m), ccol(m);
+    std::vector<uint8_t> cval((size_t)m * esz);
+    int64_t e = 0;
+    for (int64_t i = 0; i < n_rows; i++) {
+        const int64_t b = row_ptr[i], len = row_ptr[i + 1] - b;
+        for (int64_t j = 0; j < len; j++) {
+            if (j < K1) {
+                ecol[j * n_pad + i] = col_idx[b + j];
+                memcpy(&eval[(size_t)(j * n_pad + i) * esz], &conv[(size_t)(b + j) * esz], esz);
+            } else {
+                crow[e] = (int32_t)i;
+                ccol[e] = col_idx[b + j];
+                memcpy(&cval[(size_t)e * esz], &conv[(size_t)(b + j) * esz], esz);
+                e++;
+            }
+        }
+    }
+    auto *h = new hyb_matrix_s();
+    try {
+        h->device = current_device();
+        h->vdt = value_dtype; h->esz = esz;
+        h->n_rows = n_rows; h->n_cols = n_cols; h->nnz = nnz; h->n_pad = n_pad; h->K1 = K1; h->m = m;
+        Arena a;
+        a.add(&h->ell_col, ecol.size());
+        a.add((uint8_t **)&h->ell_val, eval.size());
+        a.add(&h->coo_row, crow.size());
+        a.add(&h->coo_col, ccol.size());
+        a.add((uint8_t **)&h->coo_val, cval.size());
+        h->mem = a.commit();
+        h->bytes = a.total;
+        hipStream_t st = (hipStream_t)stream;
+        upload(h->ell_col, ecol, st);
+        upload_bytes(h->ell_val, eval, st);
+        upload(h->coo_row, crow, st);
+        upload(h->coo_col, ccol, st);
+        upload_bytes(h->coo_val, cval, st);
+        HIPCHK(hipStreamSynchronize(st));
+    } catch (...) {
+        if (h->mem) (void)hipFree(h->mem);
+        delete h;
+        throw;
+    }
+    *out = h;
+    ABI_CATCH
+}
+
+rgcsr_status hyb_spmv(hyb_handle A, const void *x, void *y, rgcsr_dtype vec_dtype, void *stream) {
+    ABI_TRY
+    if (!A) fail(RGCSR_EINVAL, "null handle");
+    if (current_device() != A->device) fail(RGCSR_EINVAL, "handle belongs to another device");
+    if ((!x && A->n_cols) || (!y && A->n_rows)) fail(RGCSR_EINVAL, "null vector");
+    const int f64 = vec_is_f64(vec_dtype);
+    if (!f64 && A->vdt == RGCSR_F64) fail(RGCSR_EUNSUPPORTED, "F64 stored values need F64 vectors");
+    HybParams H{A->n_rows, A->n_pad, A->m, (int32_t)A->K1, A->ell_col, A->ell_val, A->coo_row, A->coo_col, A->coo_val};
+    hipError_t e = launch_hyb(H, A->vdt, f64, x, y, (hipStream_t)stream);
+    if (e != hipSuccess) fail(e == hipErrorInvalidValue ? RGCSR_EUNSUPPORTED : RGCSR_EHIP,
+                              std::string("hyb_spmv: ") + hipGetErrorString(e));
+    ABI_CATCH
+}
+
+rgcsr_status hyb_export(hyb_handle A, void *stream, int32_t *ell_col, void *ell_val, int32_t *coo_row,
+                        int32_t *coo_col, void *coo_val) {
+    ABI_TRY
+    if (!A) fail(RGCSR_EINVAL, "null handle");
+    hipStream_t st = (hipStream_t)stream;
+    const size_t ne = (size_t)(A->n_pad * A->K1);
+    auto get = [&](void *dst, const void *src, size_t bytes) {
+        if (dst && src && bytes) HIPCHK(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, st));
+    };
+    get(ell_col, A->ell_col, ne * 4);
+    get(ell_val, A->ell_val, ne * A->esz);
+    get(coo_row, A->coo_row, (size_t)A->m * 4);
+    get(coo_col, A->coo_col, (size_t)A->m * 4);
+    get(coo_val, A->coo_val, (size_t)A->m * A->esz);
+    HIPCHK(hipStreamSynchronize(st));
+    ABI_CATCH
+}
+
+rgcsr_status hyb_info(hyb_handle A, hyb_info_t *out) {
+    ABI_TRY
+    if (!A || !out) fail(RGCSR_EINVAL, "null argument");
+    *out = hyb_info_t{A->n_rows, A->n_cols, A->nnz, A->n_pad, A->K1, A->m, (int64_t)A->bytes, A->vdt};
+    ABI_CATCH
+}
+
+rgcsr_status hyb_clone(hyb_handle A, void *stream, hyb_handle *out) {
+    ABI_TRY
+    if (!A || !out) fail(RGCSR_EINVAL, "null argument");
+    if (current_device() != A->device) fail(RGCSR_EINVAL, "handle belongs to another device");
+    hipStream_t st = (hipStream_t)stream;
+    auto *h = new hyb_matrix_s(*A);
+    h->mem = nullptr;
+    try {
+        if (A->bytes) HIPCHK(hipMalloc(&h->mem, A->bytes));
+        if (A->bytes) HIPCHK(hipMemcpyAsync(h->mem, A->mem, A->bytes, hipMemcpyDeviceToDevice, st));
+        rebase(h, A, &hyb_matrix_s::ell_col, &hyb_matrix_s::coo_row, &hyb_matrix_s::coo_col,
+               &hyb_matrix_s::ell_val, &hyb_matrix_s::coo_val);
+        HIPCHK(hipStreamSynchronize(st));
+    } catch (...) {
+        if (h->mem) (void)hipFree(h->mem);
+        delete h;
+        throw;
+    }
+    *out = h;
+    ABI_CATCH
+}
+
+rgcsr_status hyb_destroy(hyb_handle A) {
+    ABI_TRY
+    if (!A) return RGCSR_OK;
+    (void)hipDeviceSynchronize();
+    if (A->mem) (void)hipFree(A->mem);
+    delete A;
+    ABI_CATCH
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Conjugate gradients
+// ---------------------------------------------------------------------------
+namespace {
+
+struct DevVec {
+    void *p = nullptr;
+    ~DevVec() {
+        if (p) (void)hipFree(p);
+    }
+    template <class T> T *alloc(int64_t n) {
+        HIPCHK(hipMalloc(&p, std::max<int64_t>(n, 1) * sizeof(T)));
+        return (T *)p;
+    }
+};
+
+void hipok(hipError_t e, const char *what) {
+    if (e != hipSuccess) fail(RGCSR_EHIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+// Declared after the workspace, so it runs first on every exit path: no
+// workspace is freed while kernels queued on the stream may still use it.
+struct SyncOnExit {
+    hipStream_t st;
+    ~SyncOnExit() { (void)hipStreamSynchronize(st); }
+};
+
+double read_scalar(const double *d, hipStream_t st) {
+    double v = 0.0;
+    HIPCHK(hipMemcpyAsync(&v, d, sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    return v;
+}
+
+}  // namespace
+
+extern "C" {
+
+rgcsr_status rgcsr_cg_solve(rgcsr_handle A_lo, rgcsr_handle A_hi, const double *b, double *x, double tol,
+                            double inner_tol, int32_t max_outer, int32_t max_inner, void *stream,
+                            rgcsr_cg_stats *stats) {
+    ABI_TRY
+    check_handle(A_lo);
+    check_handle(A_hi);
+    if (!b || !x || !stats) fail(RGCSR_EINVAL, "null argument");
+    const int64_t n = A_lo->n_rows;
+    if (A_lo->n_cols != n || A_hi->n_rows != n || A_hi->n_cols != n) fail(RGCSR_EINVAL, "matrices must be square and equal in shape");
+    if (A_lo->vdt == RGCSR_F64) fail(RGCSR_EUNSUPPORTED, "A_lo must store F32, F16 or BF16 values");
+    if (A_hi->vdt != RGCSR_F64 && A_hi->vdt != RGCSR_F32) fail(RGCSR_EUNSUPPORTED, "A_hi must store F64 or F32 values");
+    hipStream_t st = (hipStream_t)stream;
+    const auto t0 = std::chrono::steady_clock::now();
+    const int nb = (int)nblocks_vec(n);
+    DevVec m_r64, m_q64, m_r, m_p, m_q, m_d, m_part, m_scal;
+    double *r64 = m_r64.alloc<double>(n), *q64 = m_q64.alloc<double>(n);
+    float *r = m_r.alloc<float>(n), *p = m_p.alloc<float>(n), *q = m_q.alloc<float>(n), *d = m_d.alloc<float>(n);
+    double *part = m_part.alloc<double>(nb), *scal = m_scal.alloc<double>(kNumScal);
+    SyncOnExit guard{st};
+    hipok(launch_dot(n, b, b, 1, part, nb, st), "dot");
+    hipok(launch_scalar(part, nb, scal, kScalOut, st), "scalar");
+    double bnorm = std::sqrt(read_scalar(scal + kOut, st));
+    if (bnorm == 0.0) bnorm = 1.0;
+    *stats = rgcsr_cg_stats{};
+    int32_t outer = 0, inner_total = 0;
+    double relres = 0.0;
+    for (;;) {
+        spmv_launch(A_hi, 1, x, 1, q64, 1, 1, false, st);
+        hipok(launch_resid(n, b, q64, r64, part, nb, st), "resid");
+        hipok(launch_scalar(part, nb, scal, kScalOut, st), "scalar");
+        const double rr = read_scalar(scal + kOut, st);
+        relres = std::sqrt(rr) / bnorm;
+        if (relres <= tol || outer >= max_outer || rr == 0.0) break;
+        const double s = 1.0 / std::sqrt(rr);
+        hipok(launch_refine_start(n, r64, s, r, d, p, part, nb, st), "refine_start");
+        hipok(launch_scalar(part, nb, scal, kScalRRInit, st), "scalar");
+        for (int32_t it = 1; it <= max_inner; it++) {
+            spmv_launch(A_lo, 1, p, 1, q, 1, 0, false, st);
+            hipok(launch_dot(n, p, q, 0, part, nb, st), "dot");
+            hipok(launch_scalar(part, nb, scal, kScalPQ, st), "scalar");
+            hipok(launch_cg_xr(n, d, r, p, q, 0, scal, part, nb, st), "cg_xr");
+            hipok(launch_scalar(part, nb, scal, kScalRRNew, st), "scalar");
+            inner_total++;
+            bool stop = it == max_inner;
+            if (!stop && it % 4 == 0) {
+                double sc[2];
+                HIPCHK(hipMemcpyAsync(sc, scal, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
+                HIPCHK(hipStreamSynchronize(st));
+                stop = std::sqrt(sc[kRR] / sc[kRR0]) <= inner_tol;
+            }
+            if (stop) break;
+            hipok(launch_cg_p(n, p, r, 0, scal, nb, st), "cg_p");
+        }
+        hipok(launch_refine_add(n, x, d, 1.0 / s, nb, st), "refine_add");
+        outer++;
+    }
+    HIPCHK(hipStreamSynchronize(st));
+    stats->outer_iterations = outer;
+    stats->inner_iterations = inner_total;
+    stats->relres = relres;
+    stats->converged = relres <= tol;
+    stats->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    ABI_CATCH
+}
+
+rgcsr_status rgcsr_cg_solve_f64(rgcsr_handle A, const double *b, double *x, double tol, int32_t max_iter,
+                                void *stream, rgcsr_cg_stats *stats) {
+    ABI_TRY
+    check_handle(A);
+    if (!b || !x || !stats) fail(RGCSR_EINVAL, "null argument");
+    const int64_t n = A->n_rows;
+    if (A->n_cols != n) fail(RGCSR_EINVAL, "matrix must be square");
+    if (A->vdt != RGCSR_F64 && A->vdt != RGCSR_F32) fail(RGCSR_EUNSUPPORTED, "A must store F64 or F32 values");
+    hipStream_t st = (hipStream_t)stream;
+    const auto t0 = std::chrono::steady_clock::now();
+    const int nb = (int)nblocks_vec(n);
+    DevVec m_r, m_p, m_q, m_part, m_scal;
+    double *r = m_r.alloc<double>(n), *p = m_p.alloc<double>(n), *q = m_q.alloc<double>(n);
+    double *part = m_part.alloc<double>(nb), *scal = m_scal.alloc<double>(kNumScal);
+    SyncOnExit guard{st};
+    hipok(launch_dot(n, b, b, 1, part, nb, st), "dot");
+    hipok(launch_scalar(part, nb, scal, kScalOut, st), "scalar");
+    double bnorm = std::sqrt(read_scalar(scal + kOut, st));
+    if (bnorm == 0.0) bnorm = 1.0;
+    spmv_launch(A, 1, x, 1, q, 1, 1, false, st);
+    hipok(launch_resid(n, b, q, r, part, nb, st), "resid");
+    hipok(launch_scalar(part, nb, scal, kScalRRInit, st), "scalar");
+    hipok(launch_copy(n, r, p, 1, nb, st), "copy");
+    int32_t it = 0;
+    *stats = rgcsr_cg_stats{};
+    double rr = read_scalar(scal + kRR, st);
+    while (it < max_iter && std::sqrt(rr) / bnorm > tol) {
+        spmv_launch(A, 1, p, 1, q, 1, 1, false, st);
+        hipok(launch_dot(n, p, q, 1, part, nb, st), "dot");
+        hipok(launch_scalar(part, nb, scal, kScalPQ, st), "scalar");
+        hipok(launch_cg_xr(n, x, r, p, q, 1, scal, part, nb, st), "cg_xr");
+        hipok(launch_scalar(part, nb, scal, kScalRRNew, st), "scalar");
+        hipok(launch_cg_p(n, p, r, 1, scal, nb, st), "cg_p");
+        it++;
+        if (it % 4 == 0 || it == max_iter) rr = read_scalar(scal + kRR, st);
+    }
+    spmv_launch(A, 1, x, 1, q, 1, 1, false, st);
+    hipok(launch_resid(n, b, q, r, part, nb, st), "resid");
+    hipok(launch_scalar(part, nb, scal, kScalOut, st), "scalar");
+    stats->relres = std::sqrt(read_scalar(scal + kOut, st)) / bnorm;
+    stats->inner_iterations = it;
+    stats->outer_iterations = 1;
+    stats->converged = stats->relres <= tol;
+    stats->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    ABI_CATCH
+}
+
+}  // extern "C"

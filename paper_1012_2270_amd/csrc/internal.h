@@ -1,0 +1,172 @@
+// Internal declarations shared by the host format library, the kernels and
+// the C ABI of librgcsr.  Nothing here is part of the public interface.
+#pragma once
+
+#include <cstdint>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/rgcsr.h"
+
+#if defined(__HIPCC__)
+#define RG_HD __host__ __device__
+#else
+#define RG_HD
+#endif
+
+namespace rg {
+
+// ---------------------------------------------------------------------------
+// Errors: internal code throws rg::Error; every ABI entry point catches it and
+// turns it into a status code plus the thread-local message.
+// ---------------------------------------------------------------------------
+struct Error {
+    rgcsr_status st;
+    std::string msg;
+};
+[[noreturn]] void fail(rgcsr_status st, const std::string &msg);
+void set_last_error(const std::string &msg);
+
+inline int dtype_size(int dt) {
+    switch (dt) {
+    case RGCSR_F64: return 8;
+    case RGCSR_F32: return 4;
+    case RGCSR_F16: return 2;
+    case RGCSR_BF16: return 2;
+    default: return 0;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Round-to-nearest-even conversions to the 16-bit storage types (bit level so
+// host and device give identical bits).  A NaN stays a NaN with its sign and
+// the leading payload bits, quiet bit set.
+// ---------------------------------------------------------------------------
+RG_HD inline uint32_t f32_bits(float f) {
+    uint32_t u;
+    __builtin_memcpy(&u, &f, 4);
+    return u;
+}
+RG_HD inline float bits_f32(uint32_t u) {
+    float f;
+    __builtin_memcpy(&f, &u, 4);
+    return f;
+}
+
+RG_HD inline uint16_t f32_to_bf16_rne(float f) {
+    uint32_t u = f32_bits(f);
+    if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x0040u);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+
+RG_HD inline uint16_t f32_to_f16_rne(float f) {
+    uint32_t u = f32_bits(f);
+    uint32_t sign = (u >> 16) & 0x8000u;
+    uint32_t a = u & 0x7fffffffu;
+    if (a > 0x7f800000u) return (uint16_t)(sign | 0x7e00u | ((a >> 13) & 0x3ffu));  // NaN
+    if (a >= 0x477ff000u) return (uint16_t)(sign | 0x7c00u);  // rounds to +-inf
+    if (a >= 0x38800000u) {                                   // normal half
+        uint32_t h = (a - 0x38000000u) >> 13;
+        uint32_t rem = a & 0x1fffu;
+        if (rem > 0x1000u || (rem == 0x1000u && (h & 1u))) h++;
+        return (uint16_t)(sign | h);
+    }
+    if (a <= 0x33000000u) return (uint16_t)sign;  // |f| <= 2^-25 rounds to 0
+    // subnormal half: value = m * 2^(e-150), unit 2^-24 -> shift by 126-e
+    uint32_t e = a >> 23;
+    uint32_t m = (a & 0x7fffffu) | 0x800000u;
+    uint32_t s = 126u - e;
+    uint32_t h = m >> s;
+    uint32_t rem = m & ((1u << s) - 1u);
+    uint32_t half = 1u << (s - 1u);
+    if (rem > half || (rem == half && (h & 1u))) h++;
+    return (uint16_t)(sign | h);
+}
+
+RG_HD inline float bf16_to_f32(uint16_t b) { return bits_f32((uint32_t)b << 16); }
+
+// Convert n values from src dtype to dst dtype (host).  float64 to a 16-bit
+// type goes through float32 first.
+void convert_values(const void *src, int src_dt, void *dst, int dst_dt, int64_t n);
+
+// ---------------------------------------------------------------------------
+// Long-row work items.  One wavefront per item.
+//   MULTI : c > 0.  Rows a .. a+b-1 of the long list, c lanes per row
+//           (c a power of two <= 64, b <= 64 / c).
+//   CHUNK : c <= 0. Row a of the long list, chunk b of -c chunks of
+//           kLongChunk nonzeros; d = first partial-sum slot of the row
+//           (also the index of the row's arrival counter).
+// ---------------------------------------------------------------------------
+struct LongItem {
+    int32_t a, b, c, d;
+};
+constexpr int kLongUnroll = 8;                  // nonzeros per lane per item
+constexpr int kLongChunk = 64 * kLongUnroll;    // nonzeros per CHUNK item
+
+// ---------------------------------------------------------------------------
+// Host layout of one matrix or of a block-diagonal batch.
+// ---------------------------------------------------------------------------
+struct HostLayout {
+    int64_t n_rows = 0, n_cols = 0, nnz = 0;
+    int32_t G = 64, T = 1;
+    int64_t sigma = 1, tau = -1;
+    int vdt = RGCSR_F32, esz = 4;
+    int64_t ng = 0, ns = 0, nl = 0, slots = 0, long_nnz = 0;
+    int64_t n_matrices = 0;
+    bool ragged = false;  // some group other than the last has fewer than G rows
+    std::vector<int64_t> gp{0};
+    std::vector<int32_t> grp_row0{0};
+    std::vector<int32_t> short_len, short_row;
+    std::vector<uint8_t> slot_val;
+    std::vector<int32_t> slot_col;
+    std::vector<int32_t> long_row;
+    std::vector<int64_t> long_ptr{0};
+    std::vector<uint8_t> long_val;
+    std::vector<int32_t> long_col;
+    std::vector<LongItem> work;
+    int64_t n_partials = 0;
+    std::vector<int64_t> row_off{0}, col_off{0};  // per-matrix offsets (batch)
+    bool short_identity() const;
+};
+
+struct LayoutParams {
+    int32_t G, T;
+    int64_t sigma, tau;
+};
+
+LayoutParams resolve_opts(const rgcsr_opts *opts);
+
+// Checks the CSR convention of Section 3.1; throws RGCSR_ECSR with the
+// offending row on failure.
+void validate_csr(int64_t n_rows, int64_t n_cols, int64_t nnz, const int64_t *rp,
+                  const int32_t *col);
+
+// Appends the layout of one CSR matrix (values already in the storage dtype,
+// esz bytes each; pad_bytes fills artificial zeros) to L, offsetting rows by
+// L.n_rows and columns by L.n_cols.  When vals is null only sizes and index
+// arrays are produced.
+void append_layout(HostLayout &L, const LayoutParams &p, int64_t n_rows, int64_t n_cols,
+                   const int64_t *rp, const int32_t *col, const uint8_t *vals, int esz,
+                   uint8_t pad_byte);
+
+// Sizes only (no arrays), for rgcsr_layout_sizes.
+void layout_sizes(const LayoutParams &p, int64_t n_rows, const int64_t *rp, int64_t *ng,
+                  int64_t *ns, int64_t *nl, int64_t *slots, int64_t *long_nnz,
+                  std::vector<int64_t> *long_lens_sorted);
+
+// Work items of the long-row path from the long list's row lengths.
+void build_long_work(const std::vector<int64_t> &long_ptr, std::vector<LongItem> &work,
+                     int64_t &n_partials);
+
+// Transpose of a CSR pattern with, for every entry of A^T, the index of the
+// entry of A it came from.
+void transpose_csr(int64_t n_rows, int64_t n_cols, const int64_t *rp, const int32_t *col,
+                   std::vector<int64_t> &rpT, std::vector<int32_t> &colT,
+                   std::vector<int32_t> &srcT);
+
+// Hybrid ELL width rule and arrays.
+int64_t hyb_width_rule(int64_t n_rows, const int64_t *rp, int s_v);
+
+}  // namespace rg

@@ -1,0 +1,75 @@
+// Kernel launch interface used by the C ABI (abi.cpp).  Internal.
+#pragma once
+
+#include <hip/hip_runtime_api.h>
+
+#include "internal.h"
+
+namespace rg {
+
+// Everything one SpMV launch reads.  Device pointers.
+struct SpmvParams {
+    // grouped (short) rows
+    const int64_t *gp;         // [ng+1] group pointers (slot offsets)
+    const int32_t *grp_row0;   // [ng+1] first short row of each group (ragged only)
+    const int32_t *short_len;  // [ns] row lengths
+    const int32_t *short_row;  // [ns] output row of each short row (perm only)
+    const void *slot_val;      // [slots] storage dtype
+    const int32_t *slot_col;   // [slots]
+    int64_t ng, ns;
+    int32_t G;
+    int32_t wpg;               // wavefronts per group when G*T >= 64, else 0
+    int32_t gpw;               // groups per wavefront when G*T < 64, else 0
+    int32_t ragged, perm;
+    // long rows
+    const LongItem *work;
+    const int32_t *long_row;
+    const int64_t *long_ptr;
+    const void *long_val;
+    const int32_t *long_col;
+    void *partial;             // chunk partial sums (accumulator type, K per chunk)
+    int32_t *counter;          // arrival counters, zero between launches
+    int32_t n_long_waves;      // wavefronts before the grouped part starts
+    int32_t total_waves;
+    // vectors
+    const void *x;
+    void *y;
+    int64_t ldx, ldy;
+};
+
+struct HybParams {
+    int64_t n, n_pad, m;
+    int32_t K1;
+    const int32_t *ell_col;
+    const void *ell_val;
+    const int32_t *coo_row, *coo_col;
+    const void *coo_val;
+};
+
+// CG scalar slots and finishing modes.
+enum { kRR = 0, kRR0 = 1, kPQ = 2, kAlpha = 3, kBeta = 4, kOut = 5, kNumScal = 8 };
+enum { kScalPQ = 0, kScalRRNew = 1, kScalRRInit = 2, kScalOut = 3 };
+
+hipError_t launch_spmv(const SpmvParams &P, int vdt, int vec_f64, int T, int K, int nwg, hipStream_t st);
+hipError_t launch_setval(const SpmvParams &P, int vdt, int T, const void *theta, int theta_f64,
+                         const int64_t *row_ptr, hipStream_t st);
+hipError_t launch_gather_map(int64_t n, int vdt, const int32_t *map, const void *theta, int theta_f64,
+                             void *dst, hipStream_t st);
+hipError_t launch_grad(const SpmvParams &P, int vdt, int vec_f64, int T, const void *dy, void *dvals, void *dx,
+                       const int64_t *row_ptr, bool want_dvals, bool atomic_dx, hipStream_t st);
+hipError_t launch_hyb(const HybParams &H, int vdt, int vec_f64, const void *x, void *y, hipStream_t st);
+
+hipError_t launch_dot(int64_t n, const void *a, const void *b, int f64, double *part, int nb, hipStream_t st);
+hipError_t launch_scalar(const double *part, int nb, double *scal, int mode, hipStream_t st);
+hipError_t launch_cg_xr(int64_t n, void *x, void *r, const void *p, const void *q, int f64, const double *scal,
+                        double *part, int nb, hipStream_t st);
+hipError_t launch_cg_p(int64_t n, void *p, const void *r, int f64, const double *scal, int nb, hipStream_t st);
+hipError_t launch_resid(int64_t n, const double *b, const double *q, double *r, double *part, int nb,
+                        hipStream_t st);
+hipError_t launch_refine_start(int64_t n, const double *r64, double s, float *r, float *d, float *p,
+                               double *part, int nb, hipStream_t st);
+hipError_t launch_refine_add(int64_t n, double *x, const float *d, double inv_s, int nb, hipStream_t st);
+hipError_t launch_copy(int64_t n, const void *a, void *b, int f64, int nb, hipStream_t st);
+hipError_t launch_zero(int64_t n, void *a, int esz, int nb, hipStream_t st);
+
+}  // namespace rg

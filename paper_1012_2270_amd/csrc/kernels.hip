@@ -1,0 +1,856 @@
+// HIP kernels of librgcsr for gfx950 (MI355X: 256 CUs in 8 XCDs, wave64).
+//
+// SpMV is memory bound (Section 1: one multiply and one add per nonzero,
+// arithmetic intensity below one flop per byte), so nothing here uses MFMA:
+// the kernels are about coalesced value/column streams, keeping x in cache
+// and enough independent loads in flight per wavefront.
+//
+//   rgcsr_spmv_k   RgCSR SpMV/SpMM (Section 3.4).  Wavefronts [0, n_long)
+//                  run long-row work items, the rest run row groups.  In a
+//                  group the lanes walk rows with the group's row count as
+//                  stride and stop after rowLength steps, so padding is never
+//                  multiplied; loads of up to 8 steps are issued before the
+//                  dependent x gathers.  Value and column streams use
+//                  nontemporal loads so x keeps the caches.
+//   hyb_ell_k /    Hybrid ELL + COO (Section 3.3): ELL writes every row, COO
+//   hyb_coo_k      adds the remaining entries per row run.
+//   setval_k,      value update and backward pass over the same walk.
+//   grad_k
+//   dot/axpy       conjugate-gradient vector kernels (FP64 dot accumulation).
+#include <hip/hip_runtime.h>
+
+#include "internal.h"
+#include "kernels.h"
+
+namespace rg {
+
+// ---------------------------------------------------------------------------
+// helpers
+// ---------------------------------------------------------------------------
+
+// Workgroups are dispatched round robin over the 8 XCDs; remap so each XCD
+// gets a contiguous range of logical blocks and neighbouring row groups share
+// that XCD's L2 (the x windows of banded matrices then hit in L2).
+__device__ __forceinline__ int xcd_remap(int bid, int nwg) {
+    const int xcd = bid & 7, idx = bid >> 3;
+    const int per = nwg >> 3, rem = nwg & 7;
+    return (xcd < rem ? xcd * (per + 1) : rem * (per + 1) + (xcd - rem) * per) + idx;
+}
+
+template <int VD> struct Val;
+template <> struct Val<RGCSR_F64> {
+    using S = double;
+    template <class A> __device__ static A cvt(S v) { return (A)v; }
+};
+template <> struct Val<RGCSR_F32> {
+    using S = float;
+    template <class A> __device__ static A cvt(S v) { return (A)v; }
+};
+template <> struct Val<RGCSR_F16> {
+    using S = uint16_t;
+    template <class A> __device__ static A cvt(S v) { return (A)(float)__builtin_bit_cast(_Float16, v); }
+};
+template <> struct Val<RGCSR_BF16> {
+    using S = uint16_t;
+    template <class A> __device__ static A cvt(S v) { return (A)bf16_to_f32(v); }
+};
+
+template <class T> __device__ __forceinline__ T ldnt(const T *p) { return __builtin_nontemporal_load(p); }
+
+// K consecutive vector entries starting at p (16-byte aligned when K > 1 is a
+// multiple of the vector width; checked on the host).
+template <class A, int K> __device__ __forceinline__ void load_row(const A *p, A (&v)[K]) {
+    if constexpr (K == 1) {
+        v[0] = p[0];
+    } else if constexpr (sizeof(A) == 4 && K % 4 == 0) {
+#pragma unroll
+        for (int i = 0; i < K / 4; i++) {
+            const float4 t = reinterpret_cast<const float4 *>(p)[i];
+            v[4 * i] = t.x; v[4 * i + 1] = t.y; v[4 * i + 2] = t.z; v[4 * i + 3] = t.w;
+        }
+    } else if constexpr (sizeof(A) == 8 && K % 2 == 0) {
+#pragma unroll
+        for (int i = 0; i < K / 2; i++) {
+            const double2 t = reinterpret_cast<const double2 *>(p)[i];
+            v[2 * i] = t.x; v[2 * i + 1] = t.y;
+        }
+    } else {
+#pragma unroll
+        for (int i = 0; i < K; i++) v[i] = p[i];
+    }
+}
+
+template <class A, int K> __device__ __forceinline__ void store_row(A *p, const A (&v)[K]) {
+    if constexpr (sizeof(A) == 4 && K % 4 == 0) {
+#pragma unroll
+        for (int i = 0; i < K / 4; i++)
+            reinterpret_cast<float4 *>(p)[i] = make_float4(v[4 * i], v[4 * i + 1], v[4 * i + 2], v[4 * i + 3]);
+    } else if constexpr (sizeof(A) == 8 && K % 2 == 0) {
+#pragma unroll
+        for (int i = 0; i < K / 2; i++) reinterpret_cast<double2 *>(p)[i] = make_double2(v[2 * i], v[2 * i + 1]);
+    } else {
+#pragma unroll
+        for (int i = 0; i < K; i++) p[i] = v[i];
+    }
+}
+
+__device__ __forceinline__ float fmaA(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fmaA(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
+// Geometry of the row a lane owns in the grouped part.
+struct LaneRow {
+    int64_t i;       // index into short_len / short_row
+    int64_t base;    // first slot of this lane
+    int64_t stride;  // slots between this lane's consecutive elements
+    int len;         // row length
+    int q;           // sub-lane within the row (0 .. T-1)
+    bool ok;
+};
+
+template <int T>
+__device__ __forceinline__ LaneRow lane_row(const SpmvParams &P, int32_t w, int lane) {
+    LaneRow L;
+    int64_t g;
+    int lr;
+    if (P.wpg > 0) {  // G*T >= 64: wpg wavefronts per group
+        g = w / P.wpg;
+        lr = (w - (int32_t)g * P.wpg) * 64 + lane;
+    } else {          // G*T divides 64: gpw groups per wavefront
+        const int GT = P.G * T;
+        g = (int64_t)w * P.gpw + lane / GT;
+        lr = lane % GT;
+    }
+    const int t = lr / T;
+    L.q = lr % T;
+    int64_t row0 = 0;
+    int sg = 0;
+    if (g < P.ng) {
+        if (P.ragged) {
+            row0 = P.grp_row0[g];
+            sg = P.grp_row0[g + 1] - (int32_t)row0;
+        } else {
+            row0 = g * P.G;
+            sg = (int)min((int64_t)P.G, P.ns - row0);
+        }
+    }
+    L.ok = t < sg;
+    L.i = row0 + t;
+    L.len = L.ok ? P.short_len[L.i] : 0;
+    L.base = L.ok ? P.gp[g] + (int64_t)t * T + L.q : 0;
+    L.stride = (int64_t)sg * T;
+    return L;
+}
+
+// ---------------------------------------------------------------------------
+// RgCSR SpMV / SpMM
+// ---------------------------------------------------------------------------
+template <int VD, class A, int K, int T>
+__device__ __forceinline__ void spmv_short(const SpmvParams &P, int32_t w, int lane) {
+    using V = Val<VD>;
+    using S = typename V::S;
+    const S *vals = (const S *)P.slot_val;
+    const A *X = (const A *)P.x;
+    A *Y = (A *)P.y;
+    const LaneRow L = lane_row<T>(P, w, lane);
+    const int n = L.len > L.q ? (L.len - L.q + T - 1) / T : 0;
+    A acc[K];
+#pragma unroll
+    for (int k = 0; k < K; k++) acc[k] = A(0);
+    constexpr int U = K == 1 ? 8 : (K <= 4 ? 4 : 2);
+    for (int c0 = 0; c0 < n; c0 += U) {
+        S v[U];
+        int32_t ci[U];
+#pragma unroll
+        for (int u = 0; u < U; u++) {
+            if (c0 + u < n) {
+                const int64_t s = L.base + (int64_t)(c0 + u) * L.stride;
+                v[u] = ldnt(vals + s);
+                ci[u] = ldnt(P.slot_col + s);
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < U; u++) {
+            if (c0 + u < n) {
+                const A a = V::template cvt<A>(v[u]);
+                A xv[K];
+                load_row<A, K>(X + (int64_t)ci[u] * P.ldx, xv);
+#pragma unroll
+                for (int k = 0; k < K; k++) acc[k] = fmaA(a, xv[k], acc[k]);
+            }
+        }
+    }
+    if constexpr (T > 1) {
+#pragma unroll
+        for (int off = T / 2; off > 0; off >>= 1)
+#pragma unroll
+            for (int k = 0; k < K; k++) acc[k] += __shfl_xor(acc[k], off);
+    }
+    if (L.ok && L.q == 0) {
+        const int64_t row = P.perm ? (int64_t)P.short_row[L.i] : L.i;
+        store_row<A, K>(Y + row * P.ldy, acc);
+    }
+}
+
+template <int VD, class A, int K>
+__device__ __forceinline__ void spmv_long(const SpmvParams &P, int32_t w, int lane) {
+    using V = Val<VD>;
+    using S = typename V::S;
+    const S *vals = (const S *)P.long_val;
+    const A *X = (const A *)P.x;
+    A *Y = (A *)P.y;
+    const LongItem it = P.work[w];
+    A acc[K];
+#pragma unroll
+    for (int k = 0; k < K; k++) acc[k] = A(0);
+    if (it.c > 0) {
+        // MULTI: it.b rows with it.c lanes each
+        const int TL = it.c;
+        const int sh = 31 - __builtin_clz(TL);
+        const int r = lane >> sh, q = lane & (TL - 1);
+        const bool ok = r < it.b;
+        const int64_t li = (int64_t)it.a + r;
+        const int64_t beg = ok ? P.long_ptr[li] : 0, end = ok ? P.long_ptr[li + 1] : 0;
+        constexpr int U = K == 1 ? kLongUnroll : (K <= 4 ? 4 : 2);
+        for (int64_t e0 = beg + q; e0 < end; e0 += (int64_t)TL * U) {
+            S v[U];
+            int32_t ci[U];
+#pragma unroll
+            for (int u = 0; u < U; u++) {
+                const int64_t e = e0 + (int64_t)u * TL;
+                if (e < end) {
+                    v[u] = ldnt(vals + e);
+                    ci[u] = ldnt(P.long_col + e);
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < U; u++) {
+                if (e0 + (int64_t)u * TL < end) {
+                    const A a = V::template cvt<A>(v[u]);
+                    A xv[K];
+                    load_row<A, K>(X + (int64_t)ci[u] * P.ldx, xv);
+#pragma unroll
+                    for (int k = 0; k < K; k++) acc[k] = fmaA(a, xv[k], acc[k]);
+                }
+            }
+        }
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1)
+            if (off < TL)
+#pragma unroll
+                for (int k = 0; k < K; k++) acc[k] += __shfl_xor(acc[k], off);
+        if (ok && q == 0) store_row<A, K>(Y + (int64_t)P.long_row[li] * P.ldy, acc);
+        return;
+    }
+    // CHUNK: kLongChunk consecutive nonzeros of one row
+    const int nch = -it.c;
+    const int64_t li = it.a;
+    const int64_t beg = P.long_ptr[li] + (int64_t)it.b * kLongChunk;
+    const int64_t end = min(P.long_ptr[li + 1], beg + kLongChunk);
+    {
+        S v[kLongUnroll];
+        int32_t ci[kLongUnroll];
+#pragma unroll
+        for (int u = 0; u < kLongUnroll; u++) {
+            const int64_t e = beg + u * 64 + lane;
+            if (e < end) {
+                v[u] = ldnt(vals + e);
+                ci[u] = ldnt(P.long_col + e);
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < kLongUnroll; u++) {
+            if (beg + u * 64 + lane < end) {
+                const A a = V::template cvt<A>(v[u]);
+                A xv[K];
+                load_row<A, K>(X + (int64_t)ci[u] * P.ldx, xv);
+#pragma unroll
+                for (int k = 0; k < K; k++) acc[k] = fmaA(a, xv[k], acc[k]);
+            }
+        }
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1)
+#pragma unroll
+        for (int k = 0; k < K; k++) acc[k] += __shfl_xor(acc[k], off);
+    if (lane != 0) return;
+    const int64_t row = P.long_row[li];
+    if (nch == 1) {
+        store_row<A, K>(Y + row * P.ldy, acc);
+        return;
+    }
+    // Several wavefronts share the row: publish this chunk's partial sum; the
+    // last to arrive adds the partials in chunk order (deterministic) and
+    // re-arms the counter for the next launch.
+    A *part = (A *)P.partial;
+#pragma unroll
+    for (int k = 0; k < K; k++) part[((int64_t)it.d + it.b) * K + k] = acc[k];
+    const int old = __hip_atomic_fetch_add(P.counter + it.d, 1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+    if (old != nch - 1) return;
+    A tot[K];
+#pragma unroll
+    for (int k = 0; k < K; k++) tot[k] = A(0);
+    for (int c = 0; c < nch; c++)
+#pragma unroll
+        for (int k = 0; k < K; k++) tot[k] += part[((int64_t)it.d + c) * K + k];
+    store_row<A, K>(Y + row * P.ldy, tot);
+    __hip_atomic_store(P.counter + it.d, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+template <int VD, class A, int K, int T, bool LONG>
+__global__ __launch_bounds__(256) void rgcsr_spmv_k(SpmvParams P) {
+    const int lane = threadIdx.x & 63;
+    const int nwg = gridDim.x;
+    const int b = xcd_remap(blockIdx.x, nwg);
+    const int32_t stride = nwg * 4;
+    for (int32_t w = __builtin_amdgcn_readfirstlane(b * 4 + (int)(threadIdx.x >> 6)); w < P.total_waves;
+         w += stride) {
+        if (LONG && w < P.n_long_waves)
+            spmv_long<VD, A, K>(P, w, lane);
+        else
+            spmv_short<VD, A, K, T>(P, w - (LONG ? P.n_long_waves : 0), lane);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Value update: slots <- convert(theta[csr index]) for A, then A^T by map
+// ---------------------------------------------------------------------------
+template <int VD, class SRC>
+__device__ __forceinline__ typename Val<VD>::S to_store(SRC v) {
+    if constexpr (VD == RGCSR_F64) return (double)v;
+    else if constexpr (VD == RGCSR_F32) return (float)v;
+    else if constexpr (VD == RGCSR_F16) return f32_to_f16_rne((float)v);
+    else return f32_to_bf16_rne((float)v);
+}
+
+template <int VD, class SRC, int T>
+__global__ __launch_bounds__(256) void setval_k(SpmvParams P, const SRC *theta, const int64_t *row_ptr) {
+    using S = typename Val<VD>::S;
+    const int lane = threadIdx.x & 63;
+    const int32_t w = blockIdx.x * 4 + (int)(threadIdx.x >> 6);
+    if (w >= P.total_waves) return;
+    if (w < P.n_long_waves) {
+        // long rows: one wavefront per long row, contiguous copy
+        const int64_t li = w;
+        const int64_t row = P.long_row[li];
+        const int64_t beg = P.long_ptr[li], end = P.long_ptr[li + 1];
+        const int64_t k0 = row_ptr[row] - beg;
+        S *lv = (S *)P.long_val;
+        for (int64_t e = beg + lane; e < end; e += 64) lv[e] = to_store<VD>(theta[k0 + e]);
+        return;
+    }
+    const LaneRow L = lane_row<T>(P, w - P.n_long_waves, lane);
+    if (!L.ok) return;
+    S *sv = (S *)const_cast<void *>(P.slot_val);
+    const int64_t row = P.perm ? (int64_t)P.short_row[L.i] : L.i;
+    const int64_t k0 = row_ptr[row];
+    for (int j = L.q, c = 0; j < L.len; j += T, c++) sv[L.base + (int64_t)c * L.stride] = to_store<VD>(theta[k0 + j]);
+}
+
+template <int VD, class SRC>
+__global__ __launch_bounds__(256) void gather_map_k(int64_t n, const int32_t *map, const SRC *theta, void *dst) {
+    using S = typename Val<VD>::S;
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    const int32_t m = map[i];
+    ((S *)dst)[i] = m >= 0 ? to_store<VD>(theta[m]) : S(0);
+}
+
+// ---------------------------------------------------------------------------
+// Backward: dvals[k] = dy[row(k)] * x[col(k)]; optionally dx += v * dy (atomic)
+// ---------------------------------------------------------------------------
+template <int VD, class A, int T, bool DVALS, bool ATOMIC_DX>
+__global__ __launch_bounds__(256) void grad_k(SpmvParams P, const A *dy, A *dvals, A *dx, const int64_t *row_ptr) {
+    using V = Val<VD>;
+    using S = typename V::S;
+    const int lane = threadIdx.x & 63;
+    const int32_t w = blockIdx.x * 4 + (int)(threadIdx.x >> 6);
+    if (w >= P.total_waves) return;
+    const A *X = (const A *)P.x;
+    if (w < P.n_long_waves) {
+        const int64_t li = w;
+        const int64_t row = P.long_row[li];
+        const int64_t beg = P.long_ptr[li], end = P.long_ptr[li + 1];
+        const A d = dy[row];
+        const S *lv = (const S *)P.long_val;
+        const int64_t k0 = DVALS ? row_ptr[row] - beg : 0;
+        for (int64_t e = beg + lane; e < end; e += 64) {
+            const int32_t c = P.long_col[e];
+            if constexpr (DVALS) dvals[k0 + e] = d * X[c];
+            if constexpr (ATOMIC_DX) atomicAdd(dx + c, V::template cvt<A>(lv[e]) * d);
+        }
+        return;
+    }
+    const LaneRow L = lane_row<T>(P, w - P.n_long_waves, lane);
+    if (!L.ok) return;
+    const S *sv = (const S *)P.slot_val;
+    const int64_t row = P.perm ? (int64_t)P.short_row[L.i] : L.i;
+    const A d = dy[row];
+    const int64_t k0 = DVALS ? row_ptr[row] : 0;
+    for (int j = L.q, c = 0; j < L.len; j += T, c++) {
+        const int64_t s = L.base + (int64_t)c * L.stride;
+        const int32_t col = P.slot_col[s];
+        if constexpr (DVALS) dvals[k0 + j] = d * X[col];
+        if constexpr (ATOMIC_DX) atomicAdd(dx + col, V::template cvt<A>(sv[s]) * d);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Hybrid ELL + COO
+// ---------------------------------------------------------------------------
+template <int VD, class A>
+__global__ __launch_bounds__(256) void hyb_ell_k(int64_t n, int64_t n_pad, int32_t K1, const int32_t *ecol,
+                                                 const void *evals, const A *x, A *y) {
+    using V = Val<VD>;
+    using S = typename V::S;
+    const int64_t i = (int64_t)xcd_remap(blockIdx.x, gridDim.x) * 256 + threadIdx.x;
+    if (i >= n) return;
+    const S *ev = (const S *)evals;
+    A acc = A(0);
+    constexpr int U = 8;
+    for (int j0 = 0; j0 < K1; j0 += U) {
+        S v[U];
+        int32_t c[U];
+#pragma unroll
+        for (int u = 0; u < U; u++) {
+            if (j0 + u < K1) {
+                const int64_t e = (int64_t)(j0 + u) * n_pad + i;
+                c[u] = ldnt(ecol + e);
+                v[u] = ldnt(ev + e);
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < U; u++)
+            if (j0 + u < K1 && c[u] >= 0) acc = fmaA(V::template cvt<A>(v[u]), x[c[u]], acc);
+    }
+    y[i] = acc;
+}
+
+// Each wavefront owns 512 consecutive COO entries, 8 per lane.  A lane sums
+// runs of equal row; runs strictly inside the lane's 8 entries belong to no
+// other lane and are added with a plain read-modify-write, runs touching the
+// lane's first or last entry are added atomically.  A wavefront whose 512
+// entries all belong to one row reduces across lanes first and adds once.
+template <int VD, class A>
+__global__ __launch_bounds__(256) void hyb_coo_k(int64_t m, const int32_t *crow, const int32_t *ccol,
+                                                 const void *cvals, const A *x, A *y) {
+    using V = Val<VD>;
+    using S = typename V::S;
+    const S *cv = (const S *)cvals;
+    const int lane = threadIdx.x & 63;
+    const int64_t wave = (int64_t)xcd_remap(blockIdx.x, gridDim.x) * 4 + (threadIdx.x >> 6);
+    const int64_t base = wave * 512;
+    if (base >= m) return;
+    const int64_t e0 = base + (int64_t)lane * 8;
+    A p[8];
+    int32_t r[8];
+#pragma unroll
+    for (int u = 0; u < 8; u++) {
+        const int64_t e = e0 + u;
+        if (e < m) {
+            r[u] = ldnt(crow + e);
+            const int32_t c = ldnt(ccol + e);
+            p[u] = V::template cvt<A>(ldnt(cv + e)) * x[c];
+        } else {
+            r[u] = -1;
+            p[u] = A(0);
+        }
+    }
+    const int64_t last = min(m, base + 512) - 1;
+    const int32_t r_first = __builtin_amdgcn_readfirstlane(crow[base]);
+    const int32_t r_last = __builtin_amdgcn_readfirstlane(crow[last]);
+    if (r_first == r_last) {
+        A s = A(0);
+#pragma unroll
+        for (int u = 0; u < 8; u++) s += p[u];
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
+        if (lane == 0) atomicAdd(y + r_first, s);
+        return;
+    }
+    if (e0 >= m) return;
+    int32_t cur = r[0];
+    A run = p[0];
+    bool head = true;
+#pragma unroll
+    for (int u = 1; u < 8; u++) {
+        if (r[u] < 0) break;
+        if (r[u] != cur) {
+            if (head) atomicAdd(y + cur, run);
+            else y[cur] += run;
+            head = false;
+            cur = r[u];
+            run = A(0);
+        }
+        run += p[u];
+    }
+    atomicAdd(y + cur, run);
+}
+
+// ---------------------------------------------------------------------------
+// Conjugate-gradient vector kernels.  Dot products accumulate in FP64 into a
+// fixed number of block partials and are finished by one block, so every
+// reduction has a fixed order (bit-reproducible runs).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double block_sum(double v, double *sh) {
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    const int wv = threadIdx.x >> 6;
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) sh[wv] = v;
+    __syncthreads();
+    double t = 0.0;
+    if (threadIdx.x == 0)
+        for (int i = 0; i < (int)(blockDim.x >> 6); i++) t += sh[i];
+    return t;
+}
+
+template <class TA, class TB>
+__global__ __launch_bounds__(256) void dot_partial_k(int64_t n, const TA *a, const TB *b, double *part) {
+    __shared__ double sh[4];
+    double acc = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
+        acc += (double)a[i] * (double)b[i];
+    const double t = block_sum(acc, sh);
+    if (threadIdx.x == 0) part[blockIdx.x] = t;
+}
+
+// One block: sum the partials, then apply `mode` to the scalar slots.
+__global__ __launch_bounds__(256) void cg_scalar_k(const double *part, int nb, double *scal, int mode) {
+    __shared__ double sh[4];
+    double acc = 0.0;
+    for (int i = threadIdx.x; i < nb; i += 256) acc += part[i];
+    const double s = block_sum(acc, sh);
+    if (threadIdx.x != 0) return;
+    switch (mode) {
+    case kScalPQ: scal[kPQ] = s; scal[kAlpha] = scal[kRR] / s; break;
+    case kScalRRNew: scal[kBeta] = s / scal[kRR]; scal[kRR] = s; break;
+    case kScalRRInit: scal[kRR] = s; scal[kRR0] = s; break;
+    default: scal[kOut] = s; break;
+    }
+}
+
+// x += alpha p ; r -= alpha q ; partial sums of r.r
+template <class VT>
+__global__ __launch_bounds__(256) void cg_xr_k(int64_t n, VT *x, VT *r, const VT *p, const VT *q,
+                                               const double *scal, double *part) {
+    __shared__ double sh[4];
+    const VT alpha = (VT)scal[kAlpha];
+    double acc = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+        x[i] += alpha * p[i];
+        const VT ri = r[i] - alpha * q[i];
+        r[i] = ri;
+        acc += (double)ri * (double)ri;
+    }
+    const double t = block_sum(acc, sh);
+    if (threadIdx.x == 0) part[blockIdx.x] = t;
+}
+
+// p = r + beta p
+template <class VT>
+__global__ __launch_bounds__(256) void cg_p_k(int64_t n, VT *p, const VT *r, const double *scal) {
+    const VT beta = (VT)scal[kBeta];
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
+        p[i] = r[i] + beta * p[i];
+}
+
+// r64 = b - q64 ; partial sums of r64.r64
+__global__ __launch_bounds__(256) void resid_k(int64_t n, const double *b, const double *q, double *r, double *part) {
+    __shared__ double sh[4];
+    double acc = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+        const double ri = b[i] - q[i];
+        r[i] = ri;
+        acc += ri * ri;
+    }
+    const double t = block_sum(acc, sh);
+    if (threadIdx.x == 0) part[blockIdx.x] = t;
+}
+
+// r32 = r64 * s ; d32 = 0 ; p32 = r32 ; partial sums of r32.r32
+__global__ __launch_bounds__(256) void refine_start_k(int64_t n, const double *r64, double s, float *r, float *d,
+                                                      float *p, double *part) {
+    __shared__ double sh[4];
+    double acc = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+        const float ri = (float)(r64[i] * s);
+        r[i] = ri;
+        p[i] = ri;
+        d[i] = 0.0f;
+        acc += (double)ri * (double)ri;
+    }
+    const double t = block_sum(acc, sh);
+    if (threadIdx.x == 0) part[blockIdx.x] = t;
+}
+
+// x64 += d32 * inv_s
+__global__ __launch_bounds__(256) void refine_add_k(int64_t n, double *x, const float *d, double inv_s) {
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
+        x[i] += (double)d[i] * inv_s;
+}
+
+template <class VT>
+__global__ __launch_bounds__(256) void copy_k(int64_t n, const VT *a, VT *b) {
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) b[i] = a[i];
+}
+
+template <class VT>
+__global__ __launch_bounds__(256) void fill_k(int64_t n, VT *a, VT v) {
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) a[i] = v;
+}
+
+// ---------------------------------------------------------------------------
+// Launchers
+// ---------------------------------------------------------------------------
+static hipError_t check_launch() { return hipGetLastError(); }
+
+template <int VD, class A, int K, int T>
+static hipError_t launch_spmv_t(const SpmvParams &P, int nwg, hipStream_t st) {
+    if (P.n_long_waves > 0)
+        hipLaunchKernelGGL((rgcsr_spmv_k<VD, A, K, T, true>), dim3(nwg), dim3(256), 0, st, P);
+    else
+        hipLaunchKernelGGL((rgcsr_spmv_k<VD, A, K, T, false>), dim3(nwg), dim3(256), 0, st, P);
+    return check_launch();
+}
+
+template <int VD, class A, int K>
+static hipError_t launch_spmv_k(const SpmvParams &P, int T, int nwg, hipStream_t st) {
+    switch (T) {
+    case 1: return launch_spmv_t<VD, A, K, 1>(P, nwg, st);
+    case 2: return launch_spmv_t<VD, A, K, 2>(P, nwg, st);
+    case 4: return launch_spmv_t<VD, A, K, 4>(P, nwg, st);
+    case 8: return launch_spmv_t<VD, A, K, 8>(P, nwg, st);
+    }
+    return hipErrorInvalidValue;
+}
+
+template <int VD, class A>
+static hipError_t launch_spmv_vk(const SpmvParams &P, int T, int K, int nwg, hipStream_t st) {
+    switch (K) {
+    case 1: return launch_spmv_k<VD, A, 1>(P, T, nwg, st);
+    case 2: return launch_spmv_k<VD, A, 2>(P, T, nwg, st);
+    case 4: return launch_spmv_k<VD, A, 4>(P, T, nwg, st);
+    case 8: return launch_spmv_k<VD, A, 8>(P, T, nwg, st);
+    case 16: return launch_spmv_k<VD, A, 16>(P, T, nwg, st);
+    case 32: return launch_spmv_k<VD, A, 32>(P, T, nwg, st);
+    }
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_spmv(const SpmvParams &P, int vdt, int vec_f64, int T, int K, int nwg, hipStream_t st) {
+    if (vec_f64) {
+        if (vdt == RGCSR_F64) return launch_spmv_vk<RGCSR_F64, double>(P, T, K, nwg, st);
+        if (vdt == RGCSR_F32) return launch_spmv_vk<RGCSR_F32, double>(P, T, K, nwg, st);
+    } else {
+        if (vdt == RGCSR_F32) return launch_spmv_vk<RGCSR_F32, float>(P, T, K, nwg, st);
+        if (K == 1 && vdt == RGCSR_F16) return launch_spmv_k<RGCSR_F16, float, 1>(P, T, nwg, st);
+        if (K == 1 && vdt == RGCSR_BF16) return launch_spmv_k<RGCSR_BF16, float, 1>(P, T, nwg, st);
+    }
+    return hipErrorInvalidValue;
+}
+
+template <int VD, class SRC>
+static hipError_t launch_setval_s(const SpmvParams &P, int T, const SRC *theta, const int64_t *rp, hipStream_t st) {
+    const int nwg = (P.total_waves + 3) / 4;
+    if (nwg == 0) return hipSuccess;
+    switch (T) {
+    case 1: hipLaunchKernelGGL((setval_k<VD, SRC, 1>), dim3(nwg), dim3(256), 0, st, P, theta, rp); break;
+    case 2: hipLaunchKernelGGL((setval_k<VD, SRC, 2>), dim3(nwg), dim3(256), 0, st, P, theta, rp); break;
+    case 4: hipLaunchKernelGGL((setval_k<VD, SRC, 4>), dim3(nwg), dim3(256), 0, st, P, theta, rp); break;
+    case 8: hipLaunchKernelGGL((setval_k<VD, SRC, 8>), dim3(nwg), dim3(256), 0, st, P, theta, rp); break;
+    default: return hipErrorInvalidValue;
+    }
+    return check_launch();
+}
+
+template <class SRC>
+static hipError_t launch_setval_src(const SpmvParams &P, int vdt, int T, const SRC *theta, const int64_t *rp,
+                                    hipStream_t st) {
+    switch (vdt) {
+    case RGCSR_F64: return launch_setval_s<RGCSR_F64, SRC>(P, T, theta, rp, st);
+    case RGCSR_F32: return launch_setval_s<RGCSR_F32, SRC>(P, T, theta, rp, st);
+    case RGCSR_F16: return launch_setval_s<RGCSR_F16, SRC>(P, T, theta, rp, st);
+    case RGCSR_BF16: return launch_setval_s<RGCSR_BF16, SRC>(P, T, theta, rp, st);
+    }
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_setval(const SpmvParams &P, int vdt, int T, const void *theta, int theta_f64, const int64_t *rp,
+                         hipStream_t st) {
+    if (theta_f64) return launch_setval_src<double>(P, vdt, T, (const double *)theta, rp, st);
+    return launch_setval_src<float>(P, vdt, T, (const float *)theta, rp, st);
+}
+
+template <class SRC>
+static hipError_t launch_gather_src(int64_t n, int vdt, const int32_t *map, const SRC *theta, void *dst, hipStream_t st) {
+    if (n == 0) return hipSuccess;
+    const int nwg = (int)((n + 255) / 256);
+    switch (vdt) {
+    case RGCSR_F64: hipLaunchKernelGGL((gather_map_k<RGCSR_F64, SRC>), dim3(nwg), dim3(256), 0, st, n, map, theta, dst); break;
+    case RGCSR_F32: hipLaunchKernelGGL((gather_map_k<RGCSR_F32, SRC>), dim3(nwg), dim3(256), 0, st, n, map, theta, dst); break;
+    case RGCSR_F16: hipLaunchKernelGGL((gather_map_k<RGCSR_F16, SRC>), dim3(nwg), dim3(256), 0, st, n, map, theta, dst); break;
+    case RGCSR_BF16: hipLaunchKernelGGL((gather_map_k<RGCSR_BF16, SRC>), dim3(nwg), dim3(256), 0, st, n, map, theta, dst); break;
+    default: return hipErrorInvalidValue;
+    }
+    return check_launch();
+}
+
+hipError_t launch_gather_map(int64_t n, int vdt, const int32_t *map, const void *theta, int theta_f64, void *dst,
+                             hipStream_t st) {
+    if (theta_f64) return launch_gather_src<double>(n, vdt, map, (const double *)theta, dst, st);
+    return launch_gather_src<float>(n, vdt, map, (const float *)theta, dst, st);
+}
+
+template <int VD, class A, int T>
+static hipError_t launch_grad_t(const SpmvParams &P, const A *dy, A *dvals, A *dx, const int64_t *rp, bool want_dvals,
+                                bool atomic_dx, hipStream_t st) {
+    const int nwg = (P.total_waves + 3) / 4;
+    if (nwg == 0) return hipSuccess;
+    if (want_dvals && atomic_dx)
+        hipLaunchKernelGGL((grad_k<VD, A, T, true, true>), dim3(nwg), dim3(256), 0, st, P, dy, dvals, dx, rp);
+    else if (want_dvals)
+        hipLaunchKernelGGL((grad_k<VD, A, T, true, false>), dim3(nwg), dim3(256), 0, st, P, dy, dvals, dx, rp);
+    else if (atomic_dx)
+        hipLaunchKernelGGL((grad_k<VD, A, T, false, true>), dim3(nwg), dim3(256), 0, st, P, dy, dvals, dx, rp);
+    return check_launch();
+}
+
+template <int VD, class A>
+static hipError_t launch_grad_v(const SpmvParams &P, int T, const A *dy, A *dvals, A *dx, const int64_t *rp,
+                                bool want_dvals, bool atomic_dx, hipStream_t st) {
+    switch (T) {
+    case 1: return launch_grad_t<VD, A, 1>(P, dy, dvals, dx, rp, want_dvals, atomic_dx, st);
+    case 2: return launch_grad_t<VD, A, 2>(P, dy, dvals, dx, rp, want_dvals, atomic_dx, st);
+    case 4: return launch_grad_t<VD, A, 4>(P, dy, dvals, dx, rp, want_dvals, atomic_dx, st);
+    case 8: return launch_grad_t<VD, A, 8>(P, dy, dvals, dx, rp, want_dvals, atomic_dx, st);
+    }
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_grad(const SpmvParams &P, int vdt, int vec_f64, int T, const void *dy, void *dvals, void *dx,
+                       const int64_t *rp, bool want_dvals, bool atomic_dx, hipStream_t st) {
+    if (vec_f64) {
+        if (vdt == RGCSR_F64)
+            return launch_grad_v<RGCSR_F64, double>(P, T, (const double *)dy, (double *)dvals, (double *)dx, rp,
+                                                    want_dvals, atomic_dx, st);
+        if (vdt == RGCSR_F32)
+            return launch_grad_v<RGCSR_F32, double>(P, T, (const double *)dy, (double *)dvals, (double *)dx, rp,
+                                                    want_dvals, atomic_dx, st);
+        return hipErrorInvalidValue;
+    }
+    switch (vdt) {
+    case RGCSR_F32:
+        return launch_grad_v<RGCSR_F32, float>(P, T, (const float *)dy, (float *)dvals, (float *)dx, rp, want_dvals,
+                                               atomic_dx, st);
+    case RGCSR_F16:
+        return launch_grad_v<RGCSR_F16, float>(P, T, (const float *)dy, (float *)dvals, (float *)dx, rp, want_dvals,
+                                               atomic_dx, st);
+    case RGCSR_BF16:
+        return launch_grad_v<RGCSR_BF16, float>(P, T, (const float *)dy, (float *)dvals, (float *)dx, rp, want_dvals,
+                                                atomic_dx, st);
+    }
+    return hipErrorInvalidValue;
+}
+
+template <int VD, class A>
+static hipError_t launch_hyb_v(const HybParams &H, const A *x, A *y, hipStream_t st) {
+    const int nwg_e = (int)((H.n + 255) / 256);
+    if (nwg_e > 0)
+        hipLaunchKernelGGL((hyb_ell_k<VD, A>), dim3(nwg_e), dim3(256), 0, st, H.n, H.n_pad, H.K1, H.ell_col,
+                           H.ell_val, x, y);
+    hipError_t e = check_launch();
+    if (e != hipSuccess) return e;
+    if (H.m > 0) {
+        const int64_t waves = (H.m + 511) / 512;
+        const int nwg_c = (int)((waves + 3) / 4);
+        hipLaunchKernelGGL((hyb_coo_k<VD, A>), dim3(nwg_c), dim3(256), 0, st, H.m, H.coo_row, H.coo_col,
+                           H.coo_val, x, y);
+        e = check_launch();
+    }
+    return e;
+}
+
+hipError_t launch_hyb(const HybParams &H, int vdt, int vec_f64, const void *x, void *y, hipStream_t st) {
+    if (vec_f64) {
+        if (vdt == RGCSR_F64) return launch_hyb_v<RGCSR_F64, double>(H, (const double *)x, (double *)y, st);
+        if (vdt == RGCSR_F32) return launch_hyb_v<RGCSR_F32, double>(H, (const double *)x, (double *)y, st);
+        return hipErrorInvalidValue;
+    }
+    switch (vdt) {
+    case RGCSR_F32: return launch_hyb_v<RGCSR_F32, float>(H, (const float *)x, (float *)y, st);
+    case RGCSR_F16: return launch_hyb_v<RGCSR_F16, float>(H, (const float *)x, (float *)y, st);
+    case RGCSR_BF16: return launch_hyb_v<RGCSR_BF16, float>(H, (const float *)x, (float *)y, st);
+    }
+    return hipErrorInvalidValue;
+}
+
+// CG helpers ---------------------------------------------------------------
+hipError_t launch_dot(int64_t n, const void *a, const void *b, int f64, double *part, int nb, hipStream_t st) {
+    if (f64)
+        hipLaunchKernelGGL((dot_partial_k<double, double>), dim3(nb), dim3(256), 0, st, n, (const double *)a,
+                           (const double *)b, part);
+    else
+        hipLaunchKernelGGL((dot_partial_k<float, float>), dim3(nb), dim3(256), 0, st, n, (const float *)a,
+                           (const float *)b, part);
+    return check_launch();
+}
+
+hipError_t launch_scalar(const double *part, int nb, double *scal, int mode, hipStream_t st) {
+    hipLaunchKernelGGL(cg_scalar_k, dim3(1), dim3(256), 0, st, part, nb, scal, mode);
+    return check_launch();
+}
+
+hipError_t launch_cg_xr(int64_t n, void *x, void *r, const void *p, const void *q, int f64, const double *scal,
+                        double *part, int nb, hipStream_t st) {
+    if (f64)
+        hipLaunchKernelGGL((cg_xr_k<double>), dim3(nb), dim3(256), 0, st, n, (double *)x, (double *)r,
+                           (const double *)p, (const double *)q, scal, part);
+    else
+        hipLaunchKernelGGL((cg_xr_k<float>), dim3(nb), dim3(256), 0, st, n, (float *)x, (float *)r,
+                           (const float *)p, (const float *)q, scal, part);
+    return check_launch();
+}
+
+hipError_t launch_cg_p(int64_t n, void *p, const void *r, int f64, const double *scal, int nb, hipStream_t st) {
+    if (f64)
+        hipLaunchKernelGGL((cg_p_k<double>), dim3(nb), dim3(256), 0, st, n, (double *)p, (const double *)r, scal);
+    else
+        hipLaunchKernelGGL((cg_p_k<float>), dim3(nb), dim3(256), 0, st, n, (float *)p, (const float *)r, scal);
+    return check_launch();
+}
+
+hipError_t launch_resid(int64_t n, const double *b, const double *q, double *r, double *part, int nb, hipStream_t st) {
+    hipLaunchKernelGGL(resid_k, dim3(nb), dim3(256), 0, st, n, b, q, r, part);
+    return check_launch();
+}
+
+hipError_t launch_refine_start(int64_t n, const double *r64, double s, float *r, float *d, float *p, double *part,
+                               int nb, hipStream_t st) {
+    hipLaunchKernelGGL(refine_start_k, dim3(nb), dim3(256), 0, st, n, r64, s, r, d, p, part);
+    return check_launch();
+}
+
+hipError_t launch_refine_add(int64_t n, double *x, const float *d, double inv_s, int nb, hipStream_t st) {
+    hipLaunchKernelGGL(refine_add_k, dim3(nb), dim3(256), 0, st, n, x, d, inv_s);
+    return check_launch();
+}
+
+hipError_t launch_copy(int64_t n, const void *a, void *b, int f64, int nb, hipStream_t st) {
+    if (f64)
+        hipLaunchKernelGGL((copy_k<double>), dim3(nb), dim3(256), 0, st, n, (const double *)a, (double *)b);
+    else
+        hipLaunchKernelGGL((copy_k<float>), dim3(nb), dim3(256), 0, st, n, (const float *)a, (float *)b);
+    return check_launch();
+}
+
+hipError_t launch_zero(int64_t n, void *a, int esz, int nb, hipStream_t st) {
+    if (n == 0) return hipSuccess;
+    if (esz == 8)
+        hipLaunchKernelGGL((fill_k<double>), dim3(nb), dim3(256), 0, st, n, (double *)a, 0.0);
+    else if (esz == 4)
+        hipLaunchKernelGGL((fill_k<float>), dim3(nb), dim3(256), 0, st, n, (float *)a, 0.0f);
+    else
+        return hipErrorInvalidValue;
+    return check_launch();
+}
+
+}  // namespace rg

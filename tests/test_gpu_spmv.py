@@ -1,0 +1,203 @@
+"""GPU parity of the RgCSR converter and SpMV against the FP64 CPU oracle,
+called through the C ABI (ctypes binding)."""
+import numpy as np
+import pytest
+
+from gpu_util import TOL_F32, TOL_F64, check_spmv, dev, host, say, storage_values
+
+import paper_1012_2270_amd as rg
+from paper_1012_2270_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    rg._lib.load()
+    return torch
+
+
+def layout_equal(got, exp):
+    for k in ("gp", "short_len", "short_row", "slot_col", "long_row", "long_ptr", "long_col"):
+        np.testing.assert_array_equal(got[k], exp[k], err_msg=k)
+    for k in ("slot_val", "long_val"):
+        np.testing.assert_array_equal(got[k].view(np.uint8), exp[k].view(np.uint8), err_msg=k)
+
+
+def test_laplace2d_fp64_paper_layout(torch_cuda, oracle):
+    """2D 5-point 64x64, float64, G = 64, paper layout."""
+    torch = torch_cuda
+    A, x = W.workload_laplace2d()
+    say("laplace2d f64 G=64")
+    M = rg.rgcsr_from_csr(A, G=64, value_dtype="f64")
+    layout_equal(M.export(), oracle.rgcsr_layout(A, 64))
+    rp, col, val = M.to_csr()
+    np.testing.assert_array_equal(rp, A.row_ptr)
+    np.testing.assert_array_equal(col, A.col)
+    np.testing.assert_array_equal(val.view(np.uint64), A.val.view(np.uint64))
+    y = host(M.spmv(dev(x)))
+    check_spmv(oracle, A, x, y, tol=TOL_F64)
+    # A * 1: 4 - number of neighbours, exact
+    ones = torch.ones(A.n_cols, dtype=torch.float64, device="cuda:0")
+    np.testing.assert_array_equal(host(M.spmv(ones)), oracle.csr_spmv(A, np.ones(A.n_cols)))
+    M.close()
+
+
+@pytest.mark.parametrize("dt", ["f32", "f64"])
+def test_identity_and_diagonal_bit_exact(torch_cuda, oracle, dt):
+    torch = torch_cuda
+    npdt = np.float64 if dt == "f64" else np.float32
+    n = 100_003
+    x = W.uniform_vector(n, 1, npdt)
+    say("identity/diagonal", dt)
+    M = rg.rgcsr_from_csr(W.identity(n, npdt), value_dtype=dt)
+    np.testing.assert_array_equal(host(M.spmv(dev(x))), x)
+    d = W.normal_vector(n, 2, npdt)
+    M = rg.rgcsr_from_csr(W.diagonal(d), value_dtype=dt)
+    np.testing.assert_array_equal(host(M.spmv(dev(x))), d * x)
+    del torch
+
+
+PARAMS = [(64, 1, 1, -1), (128, 1, 1, -1), (256, 1, 1, -1), (32, 1, 1, -1), (16, 2, 1, -1),
+          (64, 2, 1, -1), (64, 4, 1, -1), (8, 8, 1, -1), (64, 1, 1 << 40, 16), (64, 1, 1 << 40, 0),
+          (64, 1, 512, 24), (128, 2, 1 << 40, 64), (64, 8, 1 << 40, 100), (1, 1, 1, -1), (4, 1, 1, 3)]
+
+
+@pytest.mark.parametrize("G,T,sigma,tau", PARAMS)
+def test_random_matrix_fp32_all_layouts(torch_cuda, oracle, G, T, sigma, tau):
+    """Several groups, a ragged last group, empty rows, long rows of several
+    wavefront chunks; converter bit-exact and SpMV within tolerance."""
+    A = W.random_csr(3001, 2500, seed=G + 3 * T, max_len=70, empty_frac=0.2, long_rows=5,
+                     long_len=2300, dtype=np.float32)
+    x = W.uniform_vector(A.n_cols, 11, np.float32)
+    say("random fp32", G, T, sigma, tau)
+    M = rg.rgcsr_from_csr(A, G=G, T=T, sigma=sigma, tau=tau)
+    layout_equal(M.export(), oracle.rgcsr_layout(A, G, T, sigma, tau))
+    y = host(M.spmv(dev(x)))
+    check_spmv(oracle, A, x, y)
+    M.close()
+
+
+@pytest.mark.parametrize("G,T,sigma,tau", PARAMS[:6] + PARAMS[8:10])
+def test_random_matrix_fp64(torch_cuda, oracle, G, T, sigma, tau):
+    A = W.random_csr(1500, 1200, seed=G + T, max_len=50, long_rows=3, long_len=1100)
+    x = W.uniform_vector(A.n_cols, 12, np.float64)
+    say("random fp64", G, T, sigma, tau)
+    M = rg.rgcsr_from_csr(A, G=G, T=T, sigma=sigma, tau=tau, value_dtype="f64")
+    y = host(M.spmv(dev(x)))
+    check_spmv(oracle, A, x, y, tol=TOL_F64)
+
+
+@pytest.mark.parametrize("dt", ["bf16", "f16"])
+def test_low_precision_values(torch_cuda, oracle, dt):
+    A = W.random_csr(4000, 3000, seed=7, max_len=40, long_rows=2, long_len=2000, dtype=np.float32)
+    x = W.uniform_vector(A.n_cols, 13, np.float32)
+    say("low precision", dt)
+    M = rg.rgcsr_from_csr(A, G=64, sigma=4000, tau=32, value_dtype=dt)
+    y = host(M.spmv(dev(x)))
+    check_spmv(oracle, A, x, y, vals64=storage_values(oracle, A, dt))
+
+
+def test_fp32_values_fp64_vectors(torch_cuda, oracle):
+    A = W.random_csr(5000, 5000, seed=8, max_len=30, long_rows=2, long_len=3000, dtype=np.float32)
+    x = W.uniform_vector(A.n_cols, 14, np.float64)
+    say("f32 values f64 vectors")
+    M = rg.rgcsr_from_csr(A, G=64, sigma=5000, tau=20, value_dtype="f32")
+    y = host(M.spmv(dev(x)))
+    check_spmv(oracle, A, x, y, tol=TOL_F64)
+
+
+def test_zipf_sorted_with_long_rows(torch_cuda, oracle):
+    A = W.zipf_matrix(200_000, seed=3)
+    x = W.uniform_vector(A.n_cols, 15, np.float32)
+    for (G, T, sigma, tau) in [(64, 1, 200_000, 16), (64, 1, 200_000, 64), (64, 2, 4096, 32), (64, 1, 1, -1)]:
+        say("zipf 200k", G, T, sigma, tau)
+        M = rg.rgcsr_from_csr(A, G=G, T=T, sigma=sigma, tau=tau)
+        check_spmv(oracle, A, x, host(M.spmv(dev(x))))
+        M.close()
+
+
+def test_deterministic_repeat(torch_cuda, oracle):
+    """No atomics in RgCSR SpMV: repeated launches give identical bits, also
+    for rows split over several wavefronts."""
+    torch = torch_cuda
+    A = W.zipf_matrix(100_000, seed=4)
+    x = dev(W.uniform_vector(A.n_cols, 16, np.float32))
+    say("determinism")
+    M = rg.rgcsr_from_csr(A, G=64, sigma=100_000, tau=16)
+    assert M.info["partials"] > 0
+    y0 = host(M.spmv(x))
+    for _ in range(5):
+        np.testing.assert_array_equal(host(M.spmv(x)), y0)
+    del torch
+
+
+def test_edge_cases(torch_cuda, oracle):
+    torch = torch_cuda
+    say("edge: empty rows only")
+    A = W.CSR(130, 50, np.zeros(131, np.int64), np.zeros(0, np.int32), np.zeros(0, np.float32))
+    M = rg.rgcsr_from_csr(A)
+    y = torch.full((130,), 7.0, device="cuda:0")
+    M.spmv(dev(np.ones(50, np.float32)), y)
+    assert (host(y) == 0).all()
+    say("edge: n < 64, one row")
+    A = W.random_csr(1, 9, seed=1, max_len=9, empty_frac=0.0, dtype=np.float32)
+    x = W.uniform_vector(9, 1, np.float32)
+    check_spmv(oracle, A, x, host(rg.rgcsr_from_csr(A).spmv(dev(x))))
+    say("edge: one very long row split over many chunks")
+    n = 40_000
+    A = W.CSR(2, n, np.array([0, n, n + 3], np.int64),
+              np.concatenate([np.arange(n), [0, 5, 9]]).astype(np.int32),
+              W.normal_vector(n + 3, 3, np.float32))
+    x = W.uniform_vector(n, 2, np.float32)
+    for tau in (-1, 8):
+        check_spmv(oracle, A, x, host(rg.rgcsr_from_csr(A, sigma=2, tau=tau).spmv(dev(x))))
+    say("edge: zero rows")
+    A = W.CSR(0, 5, np.zeros(1, np.int64), np.zeros(0, np.int32), np.zeros(0, np.float32))
+    M = rg.rgcsr_from_csr(A)
+    M.spmv(dev(np.ones(5, np.float32)), torch.empty(0, device="cuda:0"))
+
+
+def test_device_resident_csr_input(torch_cuda, oracle):
+    torch = torch_cuda
+    A = W.random_csr(2000, 1500, seed=9, max_len=20, dtype=np.float32)
+    say("device csr input")
+    M = rg.rgcsr_from_csr_device(A.n_rows, A.n_cols, dev(A.row_ptr), dev(A.col), dev(A.val),
+                                 rg.make_opts(G=64, sigma=2000, tau=10))
+    layout_equal(M.export(), oracle.rgcsr_layout(A, 64, 1, 2000, 10))
+    del torch
+
+
+def test_errors_surface_as_status(torch_cuda):
+    torch = torch_cuda
+    A = W.random_csr(100, 100, seed=1, dtype=np.float32)
+    M = rg.rgcsr_from_csr(A)
+    X = torch.zeros(100 * 4 + 1, device="cuda:0")[1:].view(100, 4)  # rows 4 bytes off 16-byte alignment
+    Y = torch.zeros((100, 4), device="cuda:0")
+    with pytest.raises(rg.RgcsrError) as e:
+        rg.rgcsr_spmv_batched(M, X, Y)
+    assert e.value.status == 1
+    with pytest.raises(rg.RgcsrError) as e:
+        rg.rgcsr_from_csr(A, G=48)
+    assert e.value.status == 6
+    Md = rg.rgcsr_from_csr(A, value_dtype="f64")
+    with pytest.raises(rg.RgcsrError):
+        Md.spmv(torch.zeros(100, device="cuda:0"))
+
+
+@pytest.mark.slow
+def test_full_size_laplace3d_and_zipf(torch_cuda, oracle):
+    """The benchmark matrices at full size, in the benchmark's layouts."""
+    from bench import LAYOUT_STENCIL, LAYOUT_ZIPF
+    for name, mk, lay in (("laplace3d 128^3", W.workload_laplace3d, LAYOUT_STENCIL),
+                          ("zipf 1e6", W.workload_zipf, LAYOUT_ZIPF)):
+        A, x = mk()
+        say("full size", name, lay)
+        M = rg.rgcsr_from_csr(A, **lay)
+        y = host(M.spmv(dev(x)))
+        e = check_spmv(oracle, A, x, y, tol=TOL_F32)
+        say("  scaled error", e)
+        M.close()

@@ -32,7 +32,7 @@ def test_worked_example_printed_counts(oracle):
     assert oracle.artificial_zeros(L) == ex["paper"]["artificial_zeros_rgcsr"]
 
 
-@pytest.mark.parametrize("which", [0, 1, 2])
+@pytest.mark.parametrize("which", [0, 1, 2, 3])
 def test_worked_example_slot_by_slot(oracle, which):
     ex, A = worked_example()
     spec = ex["layouts"][which]
