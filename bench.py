@@ -166,6 +166,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-check", action="store_true", help="skip the oracle check of the outputs")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run a 1 GiB device copy (for scaling the HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print(json.dumps({"error": "this benchmark measures one GPU only; the single-matrix SpMV "
@@ -176,6 +178,18 @@ def main():
     import torch
     import paper_1012_2270_amd as rg
     from paper_1012_2270_amd import workloads as W
+
+    if args.calibrate_copy:
+        # A plain device copy of known size: its FETCH_SIZE / WRITE_SIZE
+        # counters give the scale from counter units to bytes.
+        n = (256 << 20)
+        src = torch.ones(n, dtype=torch.float32, device="cuda:0")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": 4 * n, "copy_bytes_written": 4 * n, "launches": 3}))
+        return
 
     rg._lib.load()
     log("generating matrices ...")

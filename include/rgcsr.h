@@ -173,8 +173,9 @@ rgcsr_status rgcsr_spmv(rgcsr_handle A, const void *x, void *y, rgcsr_dtype vec_
  * row-major with leading dimension ldx >= k, Y is n_rows x k with ldy >= k
  * (device pointers, elements of vec_dtype).  For a batch handle this is
  * Y_m = A_m X_m for every matrix m.  k in {1, 2, 4, 8, 16, 32} runs as one
- * launch; other k run as several launches over column blocks.  When k > 1,
- * X, Y must be 16-byte aligned and ldx, ldy multiples of 4 (F32) or 2 (F64).
+ * launch when X and Y are 16-byte aligned with ldx, ldy multiples of 4 (F32)
+ * or 2 (F64); other k, or unaligned blocks, run as several launches over
+ * column blocks (narrower blocks read X and Y rows with scalar accesses).
  * persistent = 1 launches a fixed grid of wavefronts that loop over the
  * work items (one resident launch); 0 launches one wavefront per item. */
 rgcsr_status rgcsr_spmv_batched(rgcsr_handle A, int32_t k, const void *X, int64_t ldx,

@@ -87,7 +87,7 @@ struct rgcsr_matrix_s {
     LayoutParams prm{};
     int vdt = RGCSR_F32, esz = 4;
     int64_t n_rows = 0, n_cols = 0, nnz = 0, ng = 0, ns = 0, nl = 0, slots = 0, long_nnz = 0;
-    int64_t n_matrices = 1, n_work = 0, n_partials = 0;
+    int64_t n_matrices = 1, n_wave_long = 0, n_block = 0, n_combine = 0, n_partials = 0;
     bool ragged = false, perm = false;
     int32_t wpg = 0, gpw = 0;
     std::vector<int64_t> row_off, col_off;
@@ -96,12 +96,11 @@ struct rgcsr_matrix_s {
     int64_t *gp = nullptr;
     int32_t *grp_row0 = nullptr, *short_len = nullptr, *short_row = nullptr, *slot_col = nullptr;
     void *slot_val = nullptr;
-    LongItem *work = nullptr;
+    LongItem *wave_work = nullptr, *block_work = nullptr, *combine = nullptr;
     int32_t *long_row = nullptr, *long_col = nullptr;
     int64_t *long_ptr = nullptr;
     void *long_val = nullptr;
     void *partial = nullptr;
-    int32_t *counter = nullptr;
     int64_t *row_ptr = nullptr;  // CSR map, nullable
     rgcsr_matrix_s *AT = nullptr;
     int32_t *t_map_slot = nullptr, *t_map_long = nullptr;
@@ -195,8 +194,8 @@ void build_host(Built &B, const LayoutParams &p, int vdt, int32_t count, const i
         }
         nnz_base += nnz;
     }
-    build_long_work(B.L.long_ptr, B.L.work, B.L.n_partials);
-    if (transpose) build_long_work(B.LT.long_ptr, B.LT.work, B.LT.n_partials);
+    build_long_work(B.L.long_ptr, B.L.work);
+    if (transpose) build_long_work(B.LT.long_ptr, B.LT.work);
 }
 
 rgcsr_matrix_s *make_device(const HostLayout &L, const std::vector<int64_t> *row_ptr,
@@ -210,8 +209,10 @@ rgcsr_matrix_s *make_device(const HostLayout &L, const std::vector<int64_t> *row
         h->n_rows = L.n_rows; h->n_cols = L.n_cols; h->nnz = L.nnz;
         h->ng = L.ng; h->ns = L.ns; h->nl = L.nl; h->slots = L.slots; h->long_nnz = L.long_nnz;
         h->n_matrices = L.n_matrices;
-        h->n_work = (int64_t)L.work.size();
-        h->n_partials = L.n_partials;
+        h->n_wave_long = (int64_t)L.work.wave.size();
+        h->n_block = (int64_t)L.work.block.size();
+        h->n_combine = (int64_t)L.work.combine.size();
+        h->n_partials = L.work.n_partials;
         h->ragged = L.ragged;
         h->perm = !L.short_identity();
         h->row_off = L.row_off;
@@ -227,13 +228,14 @@ rgcsr_matrix_s *make_device(const HostLayout &L, const std::vector<int64_t> *row
         a.add(&h->short_row, h->perm ? L.short_row.size() : 0);
         a.add((uint8_t **)&h->slot_val, L.slot_val.size());
         a.add(&h->slot_col, L.slot_col.size());
-        a.add(&h->work, L.work.size());
+        a.add(&h->wave_work, L.work.wave.size());
+        a.add(&h->block_work, L.work.block.size());
+        a.add(&h->combine, L.work.combine.size());
         a.add(&h->long_row, L.long_row.size());
         a.add(&h->long_ptr, L.long_ptr.size());
         a.add((uint8_t **)&h->long_val, L.long_val.size());
         a.add(&h->long_col, L.long_col.size());
-        a.add((uint8_t **)&h->partial, (size_t)L.n_partials * 32 * sizeof(double));
-        a.add(&h->counter, (size_t)L.n_partials);
+        a.add((uint8_t **)&h->partial, (size_t)L.work.n_partials * 32 * sizeof(double));
         if (row_ptr) a.add(&h->row_ptr, row_ptr->size());
         if (map) {
             a.add(&h->t_map_slot, (size_t)map->slots);
@@ -247,12 +249,13 @@ rgcsr_matrix_s *make_device(const HostLayout &L, const std::vector<int64_t> *row
         if (h->perm) upload(h->short_row, L.short_row, st);
         upload_bytes(h->slot_val, L.slot_val, st);
         upload(h->slot_col, L.slot_col, st);
-        upload(h->work, L.work, st);
+        upload(h->wave_work, L.work.wave, st);
+        upload(h->block_work, L.work.block, st);
+        upload(h->combine, L.work.combine, st);
         upload(h->long_row, L.long_row, st);
         upload(h->long_ptr, L.long_ptr, st);
         upload_bytes(h->long_val, L.long_val, st);
         upload(h->long_col, L.long_col, st);
-        if (h->counter) HIPCHK(hipMemsetAsync(h->counter, 0, (size_t)L.n_partials * sizeof(int32_t), st));
         if (row_ptr) upload(h->row_ptr, *row_ptr, st);
         if (map) {
             if (map->slots) HIPCHK(hipMemcpyAsync(h->t_map_slot, map->slot_val.data(), (size_t)map->slots * 4, hipMemcpyHostToDevice, st));
@@ -291,13 +294,22 @@ SpmvParams params_of(const rgcsr_matrix_s *h, bool per_row_long) {
     P.slot_val = h->slot_val; P.slot_col = h->slot_col;
     P.ng = h->ng; P.ns = h->ns; P.G = h->prm.G; P.wpg = h->wpg; P.gpw = h->gpw;
     P.ragged = h->ragged; P.perm = h->perm;
-    P.work = h->work; P.long_row = h->long_row; P.long_ptr = h->long_ptr; P.long_val = h->long_val;
-    P.long_col = h->long_col; P.partial = h->partial; P.counter = h->counter;
-    const int64_t lw = per_row_long ? h->nl : h->n_work;
-    const int64_t tot = lw + short_waves(h);
-    if (tot > INT32_MAX / 2) fail(RGCSR_EOVERFLOW, "too many wavefronts");
-    P.n_long_waves = (int32_t)lw;
+    P.wave_work = h->wave_work; P.block_work = h->block_work;
+    P.long_row = h->long_row; P.long_ptr = h->long_ptr; P.long_val = h->long_val;
+    P.long_col = h->long_col; P.partial = h->partial;
+    const int64_t sw = short_waves(h);
+    const int64_t wave_items = h->n_wave_long + sw;
+    const int64_t units = h->n_block + (wave_items + kBlockWaves - 1) / kBlockWaves;
+    const int64_t tot = h->nl + sw;
+    if (wave_items > INT32_MAX / 2 || units > INT32_MAX / 2 || tot > INT32_MAX / 2)
+        fail(RGCSR_EOVERFLOW, "too many wavefronts");
+    P.n_block_items = (int32_t)h->n_block;
+    P.n_wave_long = (int32_t)h->n_wave_long;
+    P.n_wave_items = (int32_t)wave_items;
+    P.total_units = (int32_t)units;
+    P.n_long_waves = (int32_t)h->nl;
     P.total_waves = (int32_t)tot;
+    (void)per_row_long;
     return P;
 }
 
@@ -312,8 +324,9 @@ void spmv_launch(const rgcsr_matrix_s *h, int K, const void *X, int64_t ldx, voi
     if (h->n_rows == 0) return;
     SpmvParams P = params_of(h, false);
     P.x = X; P.y = Y; P.ldx = ldx; P.ldy = ldy;
-    int64_t nwg = (P.total_waves + 3) / 4;
-    if (persistent) nwg = std::min<int64_t>(nwg, (int64_t)cu_count(h->device) * 8);
+    int64_t nwg = P.total_units;
+    // a persistent launch keeps two 1024-thread workgroups resident per CU
+    if (persistent) nwg = std::min<int64_t>(nwg, (int64_t)cu_count(h->device) * 2);
     if (nwg == 0) return;
     const int vd = h->vdt;
     if (f64 && !(vd == RGCSR_F64 || vd == RGCSR_F32))
@@ -321,8 +334,13 @@ void spmv_launch(const rgcsr_matrix_s *h, int K, const void *X, int64_t ldx, voi
     if (!f64 && vd == RGCSR_F64) fail(RGCSR_EUNSUPPORTED, "F64 stored values need F64 vectors");
     if (K > 1 && (vd == RGCSR_F16 || vd == RGCSR_BF16))
         fail(RGCSR_EUNSUPPORTED, "several right-hand sides need F32 or F64 stored values");
+    if (K > 1 && h->prm.T != 1) fail(RGCSR_EUNSUPPORTED, "several right-hand sides need lanes_per_row = 1");
     hipError_t e = launch_spmv(P, vd, f64, h->prm.T, K, (int)nwg, st);
     if (e != hipSuccess) fail(RGCSR_EHIP, std::string("spmv launch: ") + hipGetErrorString(e));
+    if (h->n_combine) {
+        e = launch_combine(h->combine, (int32_t)h->n_combine, h->long_row, h->partial, Y, ldy, f64, K, st);
+        if (e != hipSuccess) fail(RGCSR_EHIP, std::string("combine launch: ") + hipGetErrorString(e));
+    }
 }
 
 int64_t nblocks_vec(int64_t n) { return std::max<int64_t>(1, std::min<int64_t>(512, (n + 255) / 256)); }
@@ -373,13 +391,13 @@ rgcsr_status rgcsr_layout_sizes(int64_t n_rows, int64_t n_cols, int64_t nnz, con
     layout_sizes(p, n_rows, row_ptr, &ng, &ns, &nl, &slots, &lz, &lens);
     std::vector<int64_t> lp(1, 0);
     for (int64_t l : lens) lp.push_back(lp.back() + l);
-    std::vector<LongItem> work;
-    int64_t parts = 0;
-    build_long_work(lp, work, parts);
+    LongWork work;
+    build_long_work(lp, work);
     *out = rgcsr_info_t{};
     out->n_rows = n_rows; out->n_cols = n_cols; out->nnz = nnz;
     out->n_groups = ng; out->n_short = ns; out->n_long = nl; out->slots = slots; out->long_nnz = lz;
-    out->n_matrices = 1; out->long_work = (int64_t)work.size(); out->partials = parts;
+    out->n_matrices = 1; out->long_work = (int64_t)(work.wave.size() + work.block.size());
+    out->partials = work.n_partials;
     out->group_size = p.G; out->lanes_per_row = p.T;
     out->value_dtype = opts ? opts->value_dtype : RGCSR_F32;
     out->sort_window = p.sigma; out->long_row_threshold = p.tau;
@@ -531,22 +549,22 @@ rgcsr_status rgcsr_spmv_batched(rgcsr_handle A, int32_t k, const void *X, int64_
     if ((!X && A->n_cols) || (!Y && A->n_rows)) fail(RGCSR_EINVAL, "null vector");
     const int f64 = vec_is_f64(vec_dtype);
     const int esz = f64 ? 8 : 4, vw = f64 ? 2 : 4;
+    // Column blocks of 32, 16, 8, 4, 2, 1.  Blocks whose width is a multiple of
+    // the 16-byte vector width read X and Y rows with vector accesses, which
+    // needs 16-byte aligned rows; otherwise narrower blocks (scalar accesses)
+    // are used.
+    const bool aligned = ((uintptr_t)X % 16 == 0) && ((uintptr_t)Y % 16 == 0) && (ldx % vw == 0) && (ldy % vw == 0);
     int32_t done = 0;
     while (done < k) {
         int32_t kb = 1;
-        for (int32_t c : {32, 16, 8, 4, 2, 1})
-            if (c <= k - done) {
-                kb = c;
-                break;
-            }
+        for (int32_t c : {32, 16, 8, 4, 2, 1}) {
+            if (c > k - done) continue;
+            if (c % vw == 0 && (!aligned || ((size_t)done * esz) % 16 != 0)) continue;
+            kb = c;
+            break;
+        }
         const char *xp = (const char *)X + (size_t)done * esz;
         char *yp = (char *)Y + (size_t)done * esz;
-        if (kb % vw == 0) {  // kernels use 16-byte vector accesses on X and Y rows
-            const bool vec_ok = ((uintptr_t)xp % 16 == 0) && ((uintptr_t)yp % 16 == 0) && (ldx % vw == 0) &&
-                                (ldy % vw == 0);
-            if (!vec_ok)
-                fail(RGCSR_EINVAL, "k > 1 needs 16-byte aligned X, Y and ldx, ldy multiples of the vector width");
-        }
         spmv_launch(A, kb, xp, ldx, yp, ldy, f64, persistent != 0, (hipStream_t)stream);
         done += kb;
     }
@@ -704,7 +722,7 @@ rgcsr_status rgcsr_info(rgcsr_handle A, rgcsr_info_t *out) {
     *out = rgcsr_info_t{};
     out->n_rows = A->n_rows; out->n_cols = A->n_cols; out->nnz = A->nnz;
     out->n_groups = A->ng; out->n_short = A->ns; out->n_long = A->nl; out->slots = A->slots;
-    out->long_nnz = A->long_nnz; out->n_matrices = A->n_matrices; out->long_work = A->n_work;
+    out->long_nnz = A->long_nnz; out->n_matrices = A->n_matrices; out->long_work = A->n_wave_long + A->n_block;
     out->partials = A->n_partials; out->group_size = A->prm.G; out->lanes_per_row = A->prm.T;
     out->value_dtype = A->vdt; out->has_transpose = A->AT != nullptr;
     out->sort_window = A->prm.sigma; out->long_row_threshold = A->prm.tau;
@@ -734,9 +752,10 @@ rgcsr_matrix_s *clone_handle(const rgcsr_matrix_s *A, hipStream_t st) {
         if (A->bytes) HIPCHK(hipMemcpyAsync(h->mem, A->mem, A->bytes, hipMemcpyDeviceToDevice, st));
         rebase(h, A, &rgcsr_matrix_s::gp, &rgcsr_matrix_s::grp_row0, &rgcsr_matrix_s::short_len,
                &rgcsr_matrix_s::short_row, &rgcsr_matrix_s::slot_col, &rgcsr_matrix_s::slot_val,
-               &rgcsr_matrix_s::work, &rgcsr_matrix_s::long_row, &rgcsr_matrix_s::long_col,
+               &rgcsr_matrix_s::wave_work, &rgcsr_matrix_s::block_work, &rgcsr_matrix_s::combine,
+               &rgcsr_matrix_s::long_row, &rgcsr_matrix_s::long_col,
                &rgcsr_matrix_s::long_ptr, &rgcsr_matrix_s::long_val, &rgcsr_matrix_s::partial,
-               &rgcsr_matrix_s::counter, &rgcsr_matrix_s::row_ptr, &rgcsr_matrix_s::t_map_slot,
+               &rgcsr_matrix_s::row_ptr, &rgcsr_matrix_s::t_map_slot,
                &rgcsr_matrix_s::t_map_long);
         if (A->AT) h->AT = clone_handle(A->AT, st);
         HIPCHK(hipStreamSynchronize(st));

@@ -216,27 +216,29 @@ void append_layout(HostLayout &L, const LayoutParams &p, int64_t n_rows, int64_t
 }
 
 static int32_t lanes_for(int64_t len) {
-    // smallest power of two >= ceil(len / kLongUnroll), at most 64
-    int64_t need = (len + kLongUnroll - 1) / kLongUnroll;
+    // smallest power of two >= ceil(len / kWaveUnroll), at most 64
+    int64_t need = (len + kWaveUnroll - 1) / kWaveUnroll;
     int32_t t = 1;
     while (t < need && t < 64) t <<= 1;
     return t;
 }
 
-void build_long_work(const std::vector<int64_t> &long_ptr, std::vector<LongItem> &work,
-                     int64_t &n_partials) {
-    work.clear();
-    n_partials = 0;
+void build_long_work(const std::vector<int64_t> &long_ptr, LongWork &W) {
+    W = LongWork{};
     const int64_t nl = (int64_t)long_ptr.size() - 1;
     int64_t i = 0;
     while (i < nl) {
         const int64_t len = long_ptr[i + 1] - long_ptr[i];
-        if (len > kLongChunk) {
-            const int64_t nch = (len + kLongChunk - 1) / kLongChunk;
-            if (n_partials + nch > INT32_MAX) fail(RGCSR_EOVERFLOW, "too many long-row chunks");
+        if (len > kWaveRowMax) {
+            const int64_t nch = (len + kBlockChunk - 1) / kBlockChunk;
+            if (W.n_partials + nch > INT32_MAX) fail(RGCSR_EOVERFLOW, "too many long-row chunks");
+            const int32_t pbase = nch > 1 ? (int32_t)W.n_partials : 0;
             for (int64_t c = 0; c < nch; c++)
-                work.push_back(LongItem{(int32_t)i, (int32_t)c, (int32_t)-nch, (int32_t)n_partials});
-            n_partials += nch;
+                W.block.push_back(LongItem{(int32_t)i, (int32_t)c, (int32_t)nch, pbase});
+            if (nch > 1) {
+                W.combine.push_back(LongItem{(int32_t)i, 0, (int32_t)nch, pbase});
+                W.n_partials += nch;
+            }
             i++;
             continue;
         }
@@ -245,10 +247,10 @@ void build_long_work(const std::vector<int64_t> &long_ptr, std::vector<LongItem>
         int32_t cnt = 1;
         while (cnt < cap && i + cnt < nl) {
             const int64_t l2 = long_ptr[i + cnt + 1] - long_ptr[i + cnt];
-            if (l2 > kLongChunk || lanes_for(l2) != T) break;
+            if (l2 > kWaveRowMax || lanes_for(l2) != T) break;
             cnt++;
         }
-        work.push_back(LongItem{(int32_t)i, cnt, T, 0});
+        W.wave.push_back(LongItem{(int32_t)i, cnt, T, 0});
         i += cnt;
     }
 }

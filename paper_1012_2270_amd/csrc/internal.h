@@ -92,18 +92,29 @@ RG_HD inline float bf16_to_f32(uint16_t b) { return bits_f32((uint32_t)b << 16);
 void convert_values(const void *src, int src_dt, void *dst, int dst_dt, int64_t n);
 
 // ---------------------------------------------------------------------------
-// Long-row work items.  One wavefront per item.
-//   MULTI : c > 0.  Rows a .. a+b-1 of the long list, c lanes per row
-//           (c a power of two <= 64, b <= 64 / c).
-//   CHUNK : c <= 0. Row a of the long list, chunk b of -c chunks of
-//           kLongChunk nonzeros; d = first partial-sum slot of the row
-//           (also the index of the row's arrival counter).
+// Long-row work of the SpMV kernel (rows of the long-row segment).
+//   wave item  : rows a .. a+b-1 of the long list, c lanes per row (a power of
+//                two <= 64, b <= 64 / c); each row has at most kWaveRowMax
+//                nonzeros, so every lane multiplies at most kWaveUnroll of them.
+//   block item : chunk b of the c chunks of row a, kBlockChunk nonzeros per
+//                chunk, one whole workgroup; when c > 1, d is the row's first
+//                partial-sum slot.
+//   combine    : row a has c > 1 chunks whose partial sums start at slot d.
 // ---------------------------------------------------------------------------
 struct LongItem {
     int32_t a, b, c, d;
 };
-constexpr int kLongUnroll = 8;                  // nonzeros per lane per item
-constexpr int kLongChunk = 64 * kLongUnroll;    // nonzeros per CHUNK item
+constexpr int kWaveUnroll = 8;
+constexpr int kWaveRowMax = 64 * kWaveUnroll;                    // 512
+constexpr int kBlockThreads = 1024;                              // SpMV workgroup
+constexpr int kBlockWaves = kBlockThreads / 64;                  // 16
+constexpr int kBlockUnroll = 16;
+constexpr int64_t kBlockChunk = (int64_t)kBlockThreads * kBlockUnroll;  // 16384
+
+struct LongWork {
+    std::vector<LongItem> wave, block, combine;
+    int64_t n_partials = 0;
+};
 
 // ---------------------------------------------------------------------------
 // Host layout of one matrix or of a block-diagonal batch.
@@ -125,8 +136,7 @@ struct HostLayout {
     std::vector<int64_t> long_ptr{0};
     std::vector<uint8_t> long_val;
     std::vector<int32_t> long_col;
-    std::vector<LongItem> work;
-    int64_t n_partials = 0;
+    LongWork work;
     std::vector<int64_t> row_off{0}, col_off{0};  // per-matrix offsets (batch)
     bool short_identity() const;
 };
@@ -157,8 +167,7 @@ void layout_sizes(const LayoutParams &p, int64_t n_rows, const int64_t *rp, int6
                   std::vector<int64_t> *long_lens_sorted);
 
 // Work items of the long-row path from the long list's row lengths.
-void build_long_work(const std::vector<int64_t> &long_ptr, std::vector<LongItem> &work,
-                     int64_t &n_partials);
+void build_long_work(const std::vector<int64_t> &long_ptr, LongWork &work);
 
 // Transpose of a CSR pattern with, for every entry of A^T, the index of the
 // entry of A it came from.

@@ -22,14 +22,19 @@ struct SpmvParams {
     int32_t gpw;               // groups per wavefront when G*T < 64, else 0
     int32_t ragged, perm;
     // long rows
-    const LongItem *work;
+    const LongItem *wave_work;   // [n_wave_long] wave items
+    const LongItem *block_work;  // [n_block_items] block items
     const int32_t *long_row;
     const int64_t *long_ptr;
     const void *long_val;
     const int32_t *long_col;
-    void *partial;             // chunk partial sums (accumulator type, K per chunk)
-    int32_t *counter;          // arrival counters, zero between launches
-    int32_t n_long_waves;      // wavefronts before the grouped part starts
+    void *partial;               // chunk partial sums (accumulator type, K per chunk)
+    int32_t n_block_items;       // units [0, n_block_items) are block items
+    int32_t n_wave_long;         // wave items [0, n_wave_long) are long-row wave items
+    int32_t n_wave_items;        // all wave items (long-row wave items, then row groups)
+    int32_t total_units;         // n_block_items + ceil(n_wave_items / kBlockWaves)
+    // per-row long handling of setval/grad: one wavefront per long row
+    int32_t n_long_waves;
     int32_t total_waves;
     // vectors
     const void *x;
@@ -51,6 +56,8 @@ enum { kRR = 0, kRR0 = 1, kPQ = 2, kAlpha = 3, kBeta = 4, kOut = 5, kNumScal = 8
 enum { kScalPQ = 0, kScalRRNew = 1, kScalRRInit = 2, kScalOut = 3 };
 
 hipError_t launch_spmv(const SpmvParams &P, int vdt, int vec_f64, int T, int K, int nwg, hipStream_t st);
+hipError_t launch_combine(const LongItem *items, int32_t n, const int32_t *long_row, const void *partial, void *Y,
+                          int64_t ldy, int vec_f64, int K, hipStream_t st);
 hipError_t launch_setval(const SpmvParams &P, int vdt, int T, const void *theta, int theta_f64,
                          const int64_t *row_ptr, hipStream_t st);
 hipError_t launch_gather_map(int64_t n, int vdt, const int32_t *map, const void *theta, int theta_f64,

@@ -143,7 +143,15 @@ __device__ __forceinline__ LaneRow lane_row(const SpmvParams &P, int32_t w, int 
 
 // ---------------------------------------------------------------------------
 // RgCSR SpMV / SpMM
+//
+// Every loop body is split into three phases so that all loads of a phase are
+// in flight together: (1) value and column loads of U steps, (2) the x
+// gathers those columns select, (3) the multiply-adds.  Steps past a row's
+// length are neither loaded nor multiplied (the row-length bound of the RgCSR
+// kernel), and each lane keeps the paper's serial order within its row.
 // ---------------------------------------------------------------------------
+template <int K> constexpr int unroll_for() { return K == 1 ? 8 : (K <= 4 ? 4 : (K <= 8 ? 2 : 1)); }
+
 template <int VD, class A, int K, int T>
 __device__ __forceinline__ void spmv_short(const SpmvParams &P, int32_t w, int lane) {
     using V = Val<VD>;
@@ -156,10 +164,11 @@ __device__ __forceinline__ void spmv_short(const SpmvParams &P, int32_t w, int l
     A acc[K];
 #pragma unroll
     for (int k = 0; k < K; k++) acc[k] = A(0);
-    constexpr int U = K == 1 ? 8 : (K <= 4 ? 4 : 2);
+    constexpr int U = unroll_for<K>();
     for (int c0 = 0; c0 < n; c0 += U) {
         S v[U];
         int32_t ci[U];
+        A xv[U][K];
 #pragma unroll
         for (int u = 0; u < U; u++) {
             if (c0 + u < n) {
@@ -170,12 +179,14 @@ __device__ __forceinline__ void spmv_short(const SpmvParams &P, int32_t w, int l
         }
 #pragma unroll
         for (int u = 0; u < U; u++) {
+            if (c0 + u < n) load_row<A, K>(X + (int64_t)ci[u] * P.ldx, xv[u]);
+        }
+#pragma unroll
+        for (int u = 0; u < U; u++) {
             if (c0 + u < n) {
                 const A a = V::template cvt<A>(v[u]);
-                A xv[K];
-                load_row<A, K>(X + (int64_t)ci[u] * P.ldx, xv);
 #pragma unroll
-                for (int k = 0; k < K; k++) acc[k] = fmaA(a, xv[k], acc[k]);
+                for (int k = 0; k < K; k++) acc[k] = fmaA(a, xv[u][k], acc[k]);
             }
         }
     }
@@ -191,124 +202,130 @@ __device__ __forceinline__ void spmv_short(const SpmvParams &P, int32_t w, int l
     }
 }
 
-template <int VD, class A, int K>
-__device__ __forceinline__ void spmv_long(const SpmvParams &P, int32_t w, int lane) {
+// Elements beg + q, beg + q + stride, ... < end of one lane, three-phase.
+template <int VD, class A, int K, int U>
+__device__ __forceinline__ void strided_dot(const SpmvParams &P, int64_t beg, int64_t end, int64_t stride,
+                                            A (&acc)[K]) {
     using V = Val<VD>;
     using S = typename V::S;
     const S *vals = (const S *)P.long_val;
     const A *X = (const A *)P.x;
-    A *Y = (A *)P.y;
-    const LongItem it = P.work[w];
-    A acc[K];
+    for (int64_t e0 = beg; e0 < end; e0 += stride * U) {
+        S v[U];
+        int32_t ci[U];
+        A xv[U][K];
 #pragma unroll
-    for (int k = 0; k < K; k++) acc[k] = A(0);
-    if (it.c > 0) {
-        // MULTI: it.b rows with it.c lanes each
-        const int TL = it.c;
-        const int sh = 31 - __builtin_clz(TL);
-        const int r = lane >> sh, q = lane & (TL - 1);
-        const bool ok = r < it.b;
-        const int64_t li = (int64_t)it.a + r;
-        const int64_t beg = ok ? P.long_ptr[li] : 0, end = ok ? P.long_ptr[li + 1] : 0;
-        constexpr int U = K == 1 ? kLongUnroll : (K <= 4 ? 4 : 2);
-        for (int64_t e0 = beg + q; e0 < end; e0 += (int64_t)TL * U) {
-            S v[U];
-            int32_t ci[U];
-#pragma unroll
-            for (int u = 0; u < U; u++) {
-                const int64_t e = e0 + (int64_t)u * TL;
-                if (e < end) {
-                    v[u] = ldnt(vals + e);
-                    ci[u] = ldnt(P.long_col + e);
-                }
-            }
-#pragma unroll
-            for (int u = 0; u < U; u++) {
-                if (e0 + (int64_t)u * TL < end) {
-                    const A a = V::template cvt<A>(v[u]);
-                    A xv[K];
-                    load_row<A, K>(X + (int64_t)ci[u] * P.ldx, xv);
-#pragma unroll
-                    for (int k = 0; k < K; k++) acc[k] = fmaA(a, xv[k], acc[k]);
-                }
-            }
-        }
-#pragma unroll
-        for (int off = 32; off > 0; off >>= 1)
-            if (off < TL)
-#pragma unroll
-                for (int k = 0; k < K; k++) acc[k] += __shfl_xor(acc[k], off);
-        if (ok && q == 0) store_row<A, K>(Y + (int64_t)P.long_row[li] * P.ldy, acc);
-        return;
-    }
-    // CHUNK: kLongChunk consecutive nonzeros of one row
-    const int nch = -it.c;
-    const int64_t li = it.a;
-    const int64_t beg = P.long_ptr[li] + (int64_t)it.b * kLongChunk;
-    const int64_t end = min(P.long_ptr[li + 1], beg + kLongChunk);
-    {
-        S v[kLongUnroll];
-        int32_t ci[kLongUnroll];
-#pragma unroll
-        for (int u = 0; u < kLongUnroll; u++) {
-            const int64_t e = beg + u * 64 + lane;
+        for (int u = 0; u < U; u++) {
+            const int64_t e = e0 + u * stride;
             if (e < end) {
                 v[u] = ldnt(vals + e);
                 ci[u] = ldnt(P.long_col + e);
             }
         }
 #pragma unroll
-        for (int u = 0; u < kLongUnroll; u++) {
-            if (beg + u * 64 + lane < end) {
-                const A a = V::template cvt<A>(v[u]);
-                A xv[K];
-                load_row<A, K>(X + (int64_t)ci[u] * P.ldx, xv);
+        for (int u = 0; u < U; u++)
+            if (e0 + u * stride < end) load_row<A, K>(X + (int64_t)ci[u] * P.ldx, xv[u]);
 #pragma unroll
-                for (int k = 0; k < K; k++) acc[k] = fmaA(a, xv[k], acc[k]);
+        for (int u = 0; u < U; u++) {
+            if (e0 + u * stride < end) {
+                const A a = V::template cvt<A>(v[u]);
+#pragma unroll
+                for (int k = 0; k < K; k++) acc[k] = fmaA(a, xv[u][k], acc[k]);
             }
         }
     }
+}
+
+// Long rows of at most kWaveRowMax nonzeros: it.b rows with it.c lanes each.
+template <int VD, class A, int K>
+__device__ __forceinline__ void spmv_wave_long(const SpmvParams &P, int32_t w, int lane) {
+    A *Y = (A *)P.y;
+    const LongItem it = P.wave_work[w];
+    const int TL = it.c;
+    const int sh = 31 - __builtin_clz(TL);
+    const int r = lane >> sh, q = lane & (TL - 1);
+    const bool ok = r < it.b;
+    const int64_t li = (int64_t)it.a + r;
+    const int64_t beg = ok ? P.long_ptr[li] : 0, end = ok ? P.long_ptr[li + 1] : 0;
+    A acc[K];
+#pragma unroll
+    for (int k = 0; k < K; k++) acc[k] = A(0);
+    strided_dot<VD, A, K, (K == 1 ? kWaveUnroll : unroll_for<K>())>(P, beg + q, end, TL, acc);
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1)
+        if (off < TL)
+#pragma unroll
+            for (int k = 0; k < K; k++) acc[k] += __shfl_xor(acc[k], off);
+    if (ok && q == 0) store_row<A, K>(Y + (int64_t)P.long_row[li] * P.ldy, acc);
+}
+
+// One chunk of a very long row, reduced by the whole workgroup in LDS.
+template <int VD, class A, int K>
+__device__ __forceinline__ void spmv_block_item(const SpmvParams &P, int32_t u, A (*red)[K]) {
+    A *Y = (A *)P.y;
+    const LongItem it = P.block_work[u];
+    const int64_t li = it.a;
+    const int64_t beg = P.long_ptr[li] + (int64_t)it.b * kBlockChunk;
+    const int64_t end = min(P.long_ptr[li + 1], beg + kBlockChunk);
+    A acc[K];
+#pragma unroll
+    for (int k = 0; k < K; k++) acc[k] = A(0);
+    strided_dot<VD, A, K, (K == 1 ? 8 : unroll_for<K>())>(P, beg + threadIdx.x, end, kBlockThreads, acc);
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1)
 #pragma unroll
         for (int k = 0; k < K; k++) acc[k] += __shfl_xor(acc[k], off);
-    if (lane != 0) return;
-    const int64_t row = P.long_row[li];
-    if (nch == 1) {
-        store_row<A, K>(Y + row * P.ldy, acc);
-        return;
+    const int wv = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0)
+#pragma unroll
+        for (int k = 0; k < K; k++) red[wv][k] = acc[k];
+    __syncthreads();
+    if (threadIdx.x < K) {
+        const int k = threadIdx.x;
+        A tot = A(0);
+        for (int i = 0; i < kBlockWaves; i++) tot += red[i][k];
+        if (it.c == 1)
+            Y[(int64_t)P.long_row[li] * P.ldy + k] = tot;
+        else
+            ((A *)P.partial)[((int64_t)it.d + it.b) * K + k] = tot;
     }
-    // Several wavefronts share the row: publish this chunk's partial sum; the
-    // last to arrive adds the partials in chunk order (deterministic) and
-    // re-arms the counter for the next launch.
-    A *part = (A *)P.partial;
-#pragma unroll
-    for (int k = 0; k < K; k++) part[((int64_t)it.d + it.b) * K + k] = acc[k];
-    const int old = __hip_atomic_fetch_add(P.counter + it.d, 1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-    if (old != nch - 1) return;
-    A tot[K];
-#pragma unroll
-    for (int k = 0; k < K; k++) tot[k] = A(0);
-    for (int c = 0; c < nch; c++)
-#pragma unroll
-        for (int k = 0; k < K; k++) tot[k] += part[((int64_t)it.d + c) * K + k];
-    store_row<A, K>(Y + row * P.ldy, tot);
-    __hip_atomic_store(P.counter + it.d, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __syncthreads();
 }
 
 template <int VD, class A, int K, int T, bool LONG>
-__global__ __launch_bounds__(256) void rgcsr_spmv_k(SpmvParams P) {
+__global__ __launch_bounds__(kBlockThreads) void rgcsr_spmv_k(SpmvParams P) {
+    __shared__ A red[kBlockWaves][K];
     const int lane = threadIdx.x & 63;
+    const int wv = threadIdx.x >> 6;
     const int nwg = gridDim.x;
-    const int b = xcd_remap(blockIdx.x, nwg);
-    const int32_t stride = nwg * 4;
-    for (int32_t w = __builtin_amdgcn_readfirstlane(b * 4 + (int)(threadIdx.x >> 6)); w < P.total_waves;
-         w += stride) {
-        if (LONG && w < P.n_long_waves)
-            spmv_long<VD, A, K>(P, w, lane);
+    for (int32_t u = xcd_remap(blockIdx.x, nwg); u < P.total_units; u += nwg) {
+        if (LONG && u < P.n_block_items) {
+            spmv_block_item<VD, A, K>(P, u, red);
+            continue;
+        }
+        const int32_t w = __builtin_amdgcn_readfirstlane((u - (LONG ? P.n_block_items : 0)) * kBlockWaves + wv);
+        if (w >= P.n_wave_items) continue;
+        if (LONG && w < P.n_wave_long)
+            spmv_wave_long<VD, A, K>(P, w, lane);
         else
-            spmv_short<VD, A, K, T>(P, w - (LONG ? P.n_long_waves : 0), lane);
+            spmv_short<VD, A, K, T>(P, w - (LONG ? P.n_wave_long : 0), lane);
     }
+}
+
+// Rows split over several block items: add the chunk partial sums in order.
+template <class A, int K>
+__global__ __launch_bounds__(256) void combine_k(const LongItem *items, int32_t n, const int32_t *long_row,
+                                                 const A *partial, A *Y, int64_t ldy) {
+    const int32_t i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    const LongItem it = items[i];
+    A tot[K];
+#pragma unroll
+    for (int k = 0; k < K; k++) tot[k] = A(0);
+    for (int c = 0; c < it.c; c++)
+#pragma unroll
+        for (int k = 0; k < K; k++) tot[k] += partial[((int64_t)it.d + c) * K + k];
+    store_row<A, K>(Y + (int64_t)long_row[it.a] * ldy, tot);
 }
 
 // ---------------------------------------------------------------------------
@@ -425,11 +442,13 @@ __global__ __launch_bounds__(256) void hyb_ell_k(int64_t n, int64_t n_pad, int32
     y[i] = acc;
 }
 
-// Each wavefront owns 512 consecutive COO entries, 8 per lane.  A lane sums
-// runs of equal row; runs strictly inside the lane's 8 entries belong to no
-// other lane and are added with a plain read-modify-write, runs touching the
-// lane's first or last entry are added atomically.  A wavefront whose 512
-// entries all belong to one row reduces across lanes first and adds once.
+// Each wavefront owns 512 consecutive COO entries, 8 per lane (rows are
+// non-decreasing).  A lane sums its runs of equal row.  Runs strictly inside
+// a lane belong to no other lane and are added with a plain read-modify-write.
+// The lane's last run is carried across following lanes with a segmented
+// scan, so a row spanning many lanes costs one addition; that addition, and
+// the first run of lane 0, are atomic because they may meet another
+// wavefront's entries of the same row.
 template <int VD, class A>
 __global__ __launch_bounds__(256) void hyb_coo_k(int64_t m, const int32_t *crow, const int32_t *ccol,
                                                  const void *cvals, const A *x, A *y) {
@@ -441,49 +460,64 @@ __global__ __launch_bounds__(256) void hyb_coo_k(int64_t m, const int32_t *crow,
     const int64_t base = wave * 512;
     if (base >= m) return;
     const int64_t e0 = base + (int64_t)lane * 8;
-    A p[8];
-    int32_t r[8];
+    S v[8];
+    int32_t r[8], c[8];
 #pragma unroll
     for (int u = 0; u < 8; u++) {
         const int64_t e = e0 + u;
+        r[u] = -1;
         if (e < m) {
             r[u] = ldnt(crow + e);
-            const int32_t c = ldnt(ccol + e);
-            p[u] = V::template cvt<A>(ldnt(cv + e)) * x[c];
-        } else {
-            r[u] = -1;
-            p[u] = A(0);
+            c[u] = ldnt(ccol + e);
+            v[u] = ldnt(cv + e);
         }
     }
-    const int64_t last = min(m, base + 512) - 1;
-    const int32_t r_first = __builtin_amdgcn_readfirstlane(crow[base]);
-    const int32_t r_last = __builtin_amdgcn_readfirstlane(crow[last]);
-    if (r_first == r_last) {
-        A s = A(0);
+    A p[8];
 #pragma unroll
-        for (int u = 0; u < 8; u++) s += p[u];
-#pragma unroll
-        for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
-        if (lane == 0) atomicAdd(y + r_first, s);
-        return;
-    }
-    if (e0 >= m) return;
+    for (int u = 0; u < 8; u++) p[u] = r[u] >= 0 ? V::template cvt<A>(v[u]) * x[c[u]] : A(0);
+    // lane-local runs: head run, interior runs (flushed here), tail run
+    const int32_t head = r[0];
     int32_t cur = r[0];
-    A run = p[0];
-    bool head = true;
+    A run = p[0], head_sum = A(0);
+    bool single = true;
 #pragma unroll
     for (int u = 1; u < 8; u++) {
-        if (r[u] < 0) break;
-        if (r[u] != cur) {
-            if (head) atomicAdd(y + cur, run);
-            else y[cur] += run;
-            head = false;
+        if (r[u] >= 0 && r[u] != cur) {
+            if (single) head_sum = run;   // the lane's first run
+            else y[cur] += run;           // interior run: no other lane has this row
+            single = false;
             cur = r[u];
             run = A(0);
         }
-        run += p[u];
+        if (r[u] >= 0) run += p[u];
     }
-    atomicAdd(y + cur, run);
+    const int32_t tail = cur;  // -1 for a lane without entries
+    // Segmented inclusive scan of tail runs over the lanes.  A lane starts a new
+    // segment unless it is a single-run lane continuing the previous lane's tail.
+    const int32_t tail_prev = __shfl_up(tail, 1);
+    const bool have_prev = lane > 0 && head >= 0 && tail_prev == head;
+    int flag = (single && have_prev) ? 0 : 1;
+    A carry = run;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const A v_up = __shfl_up(carry, off);
+        const int f_up = __shfl_up(flag, off);
+        if (lane >= off && !flag) {
+            carry += v_up;
+            flag = f_up;
+        }
+    }
+    const A carry_prev = __shfl_up(carry, 1);
+    const int32_t head_next = __shfl_down(head, 1);
+    if (!single && head >= 0) {
+        // the head run ends inside this lane; it includes the carried run of
+        // the previous lanes when they end on the same row
+        const A tot = head_sum + (have_prev ? carry_prev : A(0));
+        if (lane == 0 || have_prev) atomicAdd(y + head, tot);
+        else y[head] += tot;
+    }
+    // the tail run ends here unless the next lane starts with the same row
+    if (tail >= 0 && (lane == 63 || head_next != tail)) atomicAdd(y + tail, carry);
 }
 
 // ---------------------------------------------------------------------------
@@ -605,10 +639,10 @@ static hipError_t check_launch() { return hipGetLastError(); }
 
 template <int VD, class A, int K, int T>
 static hipError_t launch_spmv_t(const SpmvParams &P, int nwg, hipStream_t st) {
-    if (P.n_long_waves > 0)
-        hipLaunchKernelGGL((rgcsr_spmv_k<VD, A, K, T, true>), dim3(nwg), dim3(256), 0, st, P);
+    if (P.n_block_items + P.n_wave_long > 0)
+        hipLaunchKernelGGL((rgcsr_spmv_k<VD, A, K, T, true>), dim3(nwg), dim3(kBlockThreads), 0, st, P);
     else
-        hipLaunchKernelGGL((rgcsr_spmv_k<VD, A, K, T, false>), dim3(nwg), dim3(256), 0, st, P);
+        hipLaunchKernelGGL((rgcsr_spmv_k<VD, A, K, T, false>), dim3(nwg), dim3(kBlockThreads), 0, st, P);
     return check_launch();
 }
 
@@ -623,17 +657,48 @@ static hipError_t launch_spmv_k(const SpmvParams &P, int T, int nwg, hipStream_t
     return hipErrorInvalidValue;
 }
 
+// Several right-hand sides use the paper's one-lane-per-row layout only.
 template <int VD, class A>
 static hipError_t launch_spmv_vk(const SpmvParams &P, int T, int K, int nwg, hipStream_t st) {
+    if (K == 1) return launch_spmv_k<VD, A, 1>(P, T, nwg, st);
+    if (T != 1) return hipErrorInvalidValue;
     switch (K) {
-    case 1: return launch_spmv_k<VD, A, 1>(P, T, nwg, st);
-    case 2: return launch_spmv_k<VD, A, 2>(P, T, nwg, st);
-    case 4: return launch_spmv_k<VD, A, 4>(P, T, nwg, st);
-    case 8: return launch_spmv_k<VD, A, 8>(P, T, nwg, st);
-    case 16: return launch_spmv_k<VD, A, 16>(P, T, nwg, st);
-    case 32: return launch_spmv_k<VD, A, 32>(P, T, nwg, st);
+    case 2: return launch_spmv_t<VD, A, 2, 1>(P, nwg, st);
+    case 4: return launch_spmv_t<VD, A, 4, 1>(P, nwg, st);
+    case 8: return launch_spmv_t<VD, A, 8, 1>(P, nwg, st);
+    case 16: return launch_spmv_t<VD, A, 16, 1>(P, nwg, st);
+    case 32: return launch_spmv_t<VD, A, 32, 1>(P, nwg, st);
     }
     return hipErrorInvalidValue;
+}
+
+template <class A, int K>
+static hipError_t launch_combine_k(const LongItem *items, int32_t n, const int32_t *long_row, const void *partial,
+                                   void *Y, int64_t ldy, hipStream_t st) {
+    hipLaunchKernelGGL((combine_k<A, K>), dim3((n + 255) / 256), dim3(256), 0, st, items, n, long_row,
+                       (const A *)partial, (A *)Y, ldy);
+    return check_launch();
+}
+
+template <class A>
+static hipError_t launch_combine_a(const LongItem *items, int32_t n, const int32_t *long_row, const void *partial,
+                                   void *Y, int64_t ldy, int K, hipStream_t st) {
+    switch (K) {
+    case 1: return launch_combine_k<A, 1>(items, n, long_row, partial, Y, ldy, st);
+    case 2: return launch_combine_k<A, 2>(items, n, long_row, partial, Y, ldy, st);
+    case 4: return launch_combine_k<A, 4>(items, n, long_row, partial, Y, ldy, st);
+    case 8: return launch_combine_k<A, 8>(items, n, long_row, partial, Y, ldy, st);
+    case 16: return launch_combine_k<A, 16>(items, n, long_row, partial, Y, ldy, st);
+    case 32: return launch_combine_k<A, 32>(items, n, long_row, partial, Y, ldy, st);
+    }
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_combine(const LongItem *items, int32_t n, const int32_t *long_row, const void *partial, void *Y,
+                          int64_t ldy, int vec_f64, int K, hipStream_t st) {
+    if (n == 0) return hipSuccess;
+    if (vec_f64) return launch_combine_a<double>(items, n, long_row, partial, Y, ldy, K, st);
+    return launch_combine_a<float>(items, n, long_row, partial, Y, ldy, K, st);
 }
 
 hipError_t launch_spmv(const SpmvParams &P, int vdt, int vec_f64, int T, int K, int nwg, hipStream_t st) {

@@ -1,0 +1,281 @@
+"""GPU parity of the Hybrid comparison kernel, multi-RHS SpMM, the batched
+block-diagonal form, the backward pass and the mixed-precision CG against the
+FP64 CPU oracle, through the C ABI."""
+import math
+
+import numpy as np
+import pytest
+
+from gpu_util import TOL_F32, TOL_F64, check_spmv, dev, host, say, storage_values
+
+import paper_1012_2270_amd as rg
+from paper_1012_2270_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    rg._lib.load()
+    return torch
+
+
+# ----------------------------------------------------------------------------
+# Hybrid ELL + COO
+# ----------------------------------------------------------------------------
+@pytest.mark.parametrize("mk,dt", [
+    (lambda: W.laplacian_3d_7pt(40, dtype=np.float32), "f32"),
+    (lambda: W.zipf_matrix(100_000, seed=6), "f32"),
+    (lambda: W.random_csr(5000, 4000, seed=2, max_len=60, long_rows=3, long_len=3500, dtype=np.float32), "f32"),
+    (lambda: W.random_csr(3000, 3000, seed=3, max_len=30), "f64"),
+])
+def test_hybrid_parity_and_layout(torch_cuda, oracle, mk, dt):
+    A = mk()
+    npdt = np.float64 if dt == "f64" else np.float32
+    x = W.uniform_vector(A.n_cols, 21, npdt)
+    say("hybrid", A.n_rows, A.nnz, dt)
+    H = rg.hyb_from_csr(A, value_dtype=dt)
+    K1 = H.info["ell_width"]
+    assert K1 == oracle.hyb_k1(A, 8 if dt == "f64" else 4)
+    got = rg.hyb_export(H)
+    exp = oracle.hyb_layout(A, K1)
+    for k in ("ell_col", "coo_row", "coo_col"):
+        np.testing.assert_array_equal(got[k], exp[k], err_msg=k)
+    for k in ("ell_val", "coo_val"):
+        np.testing.assert_array_equal(got[k].view(np.uint8), exp[k].view(np.uint8), err_msg=k)
+    y = host(H.spmv(dev(x)))
+    check_spmv(oracle, A, x, y, tol=TOL_F64 if dt == "f64" else TOL_F32)
+
+
+def test_hybrid_forced_widths(torch_cuda, oracle):
+    """K1 = 0 (all COO, rows spanning many lanes and wavefronts) and K1 beyond
+    the longest row (no COO)."""
+    A = W.random_csr(700, 30_000, seed=4, max_len=40, long_rows=5, long_len=25_000, dtype=np.float32)
+    x = W.uniform_vector(A.n_cols, 22, np.float32)
+    for K1 in (0, 1, 3, int(np.diff(A.row_ptr).max()) + 1):
+        say("hybrid K1", K1)
+        H = rg.hyb_from_csr(A, ell_width=K1)
+        check_spmv(oracle, A, x, host(H.spmv(dev(x))))
+
+
+# ----------------------------------------------------------------------------
+# Multi-RHS SpMM
+# ----------------------------------------------------------------------------
+@pytest.mark.parametrize("k", [1, 2, 4, 8, 16, 32, 5, 20])
+@pytest.mark.parametrize("persistent", [False, True])
+def test_spmm_columns_against_oracle(torch_cuda, oracle, k, persistent):
+    A = W.zipf_matrix(30_000, seed=7)
+    B = W.random_csr(200, 30_000, seed=8, max_len=10, long_rows=2, long_len=20_000)
+    X = W.uniform_matrix(A.n_cols, k, seed=3)
+    for M, lay in ((A, dict(sigma=1 << 40, tau=16)), (A, dict()), (B.astype(np.float32), dict(sigma=200, tau=8))):
+        say("spmm", k, persistent, lay)
+        H = rg.rgcsr_from_csr(M, **lay)
+        Y = host(H.spmm(dev(X), persistent=persistent))
+        ref = oracle.csr_spmm(M, X)
+        for c in range(k):
+            s = oracle.csr_absmv(M, X[:, c])
+            e = oracle.scaled_error(Y[:, c], ref[:, c], s)
+            assert e <= TOL_F32, (c, e)
+
+
+def test_spmm_f64_and_strided_leading_dimension(torch_cuda, oracle):
+    torch = torch_cuda
+    A = W.random_csr(3000, 2000, seed=9, max_len=25, long_rows=2, long_len=1500)
+    X = W.uniform_matrix(A.n_cols, 8, seed=4, dtype=np.float64)
+    say("spmm f64 k=4 with ldx=8")
+    M = rg.rgcsr_from_csr(A, value_dtype="f64", sigma=3000, tau=20)
+    Xd = dev(X)
+    Y = torch.zeros((A.n_rows, 8), dtype=torch.float64, device="cuda:0")
+    rg._lib.call("rgcsr_spmv_batched", M.handle, 4, Xd.data_ptr(), 8, Y.data_ptr(), 8, rg.RGCSR_F64, 0,
+                 torch.cuda.current_stream().cuda_stream)
+    Yh = host(Y)
+    ref = oracle.csr_spmm(A, X[:, :4])
+    for c in range(4):
+        assert oracle.scaled_error(Yh[:, c], ref[:, c], oracle.csr_absmv(A, X[:, c])) <= TOL_F64
+    assert (Yh[:, 4:] == 0).all()
+
+
+# ----------------------------------------------------------------------------
+# Batched block-diagonal
+# ----------------------------------------------------------------------------
+@pytest.mark.parametrize("lay", [dict(), dict(sigma=1 << 40, tau=32), dict(G=128), dict(G=32)])
+def test_batched_per_matrix_parity(torch_cuda, oracle, lay):
+    mats = W.batched_set(count=40, n_lo=30, n_hi=3000, seed=11)
+    mats.append(W.random_csr(50, 700, seed=1, max_len=5, long_rows=2, long_len=690, dtype=np.float32))
+    mats.append(W.CSR(3, 2, np.zeros(4, np.int64), np.zeros(0, np.int32), np.zeros(0, np.float32)))
+    say("batched", len(mats), lay)
+    B = rg.rgcsr_from_csr_batch(mats, **lay)
+    ro, co = B.batch_offsets()
+    xs = [W.uniform_vector(M.n_cols, 100 + i, np.float32) for i, M in enumerate(mats)]
+    for persistent in (False, True):
+        Y = host(B.spmm(dev(np.concatenate(xs)).view(-1, 1), persistent=persistent)).ravel()
+        for i, M in enumerate(mats):
+            check_spmv(oracle, M, xs[i], Y[ro[i]:ro[i + 1]])
+    # the batch decodes to the concatenation of its matrices
+    rp, col, val = B.to_csr()
+    for i, M in enumerate(mats):
+        seg = slice(rp[ro[i]], rp[ro[i + 1]])
+        np.testing.assert_array_equal(np.diff(rp[ro[i]:ro[i + 1] + 1]), np.diff(M.row_ptr))
+        np.testing.assert_array_equal(col[seg] - co[i], M.col)
+        np.testing.assert_array_equal(val[seg], M.val)
+
+
+def test_batched_multi_rhs(torch_cuda, oracle):
+    mats = W.batched_set(count=12, n_lo=50, n_hi=2000, seed=12)
+    B = rg.rgcsr_from_csr_batch(mats)
+    ro, co = B.batch_offsets()
+    X = W.uniform_matrix(int(co[-1]), 4, seed=5)
+    say("batched k=4")
+    Y = host(B.spmm(dev(X), persistent=True))
+    for i, M in enumerate(mats):
+        Xi = X[co[i]:co[i + 1]]
+        ref = oracle.csr_spmm(M, Xi)
+        for c in range(4):
+            s = oracle.csr_absmv(M, Xi[:, c])
+            assert oracle.scaled_error(Y[ro[i]:ro[i + 1], c], ref[:, c], s) <= TOL_F32
+
+
+# ----------------------------------------------------------------------------
+# Backward pass
+# ----------------------------------------------------------------------------
+def grad_tolerances(oracle, A, x, b):
+    s = oracle.csr_absmv(A, x)
+    AT = W.CSR(A.n_cols, A.n_rows, *oracle.csr_transpose(A))
+    dtheta_scale = float(np.max(s + np.abs(b))) * float(np.max(np.abs(x)))
+    dx_scale = float(np.max(oracle.csr_absmv(AT.astype(np.float64), s + np.abs(b)) if A.nnz else 0.0))
+    return dtheta_scale, dx_scale
+
+
+@pytest.mark.parametrize("transpose", [True, False])
+@pytest.mark.parametrize("lay", [dict(), dict(sigma=1 << 40, tau=16), dict(T=2)])
+def test_transpose_grad_against_oracle(torch_cuda, oracle, transpose, lay):
+    torch = torch_cuda
+    A = W.random_csr(4000, 3000, seed=13, max_len=30, long_rows=3, long_len=2500, dtype=np.float32)
+    x = W.normal_vector(A.n_cols, 5, np.float32)
+    b = W.normal_vector(A.n_rows, 6, np.float32)
+    say("grad", transpose, lay)
+    M = rg.rgcsr_from_csr(A, keep_csr_map=True, build_transpose=transpose, **lay)
+    xd, bd = dev(x), dev(b)
+    y = M.spmv(xd)
+    dy = (y - bd).contiguous()
+    dx = torch.empty(A.n_cols, device="cuda:0")
+    dv = torch.empty(A.nnz, device="cuda:0")
+    rg.rgcsr_spmv_transpose_grad(M, xd, dy, dx, dv)
+    r, dx_ref, dv_ref, _ = oracle.adjoint(A, x, b)
+    st, sx = grad_tolerances(oracle, A, x, b)
+    assert np.max(np.abs(host(dv) - dv_ref)) <= 1e-5 * st
+    assert np.max(np.abs(host(dx) - dx_ref)) <= 1e-5 * sx
+    if transpose:   # no atomics: repeatable bits
+        dx2 = torch.empty_like(dx)
+        rg.rgcsr_spmv_transpose_grad(M, xd, dy, dx2, None)
+        np.testing.assert_array_equal(host(dx2), host(dx))
+
+
+def test_set_values_updates_both_orientations(torch_cuda, oracle):
+    torch = torch_cuda
+    A = W.random_csr(2500, 2000, seed=14, max_len=20, long_rows=2, long_len=1800, dtype=np.float32)
+    theta = W.normal_vector(A.nnz, 9, np.float32)
+    say("set_values")
+    M = rg.rgcsr_from_csr(A, build_transpose=True, sigma=2500, tau=24)
+    rg.rgcsr_set_values(M, dev(theta))
+    A2 = W.CSR(A.n_rows, A.n_cols, A.row_ptr, A.col, theta)
+    exp = oracle.rgcsr_layout(A2, 64, 1, 2500, 24)
+    got = M.export()
+    np.testing.assert_array_equal(got["slot_val"].view(np.uint32), exp["slot_val"].view(np.uint32))
+    np.testing.assert_array_equal(got["long_val"].view(np.uint32), exp["long_val"].view(np.uint32))
+    x = W.uniform_vector(A.n_cols, 3, np.float32)
+    check_spmv(oracle, A2, x, host(M.spmv(dev(x))))
+    dy = W.normal_vector(A.n_rows, 4, np.float32)
+    dx = torch.empty(A.n_cols, device="cuda:0")
+    rg.rgcsr_spmv_transpose_grad(M, None, dev(dy), dx, None)
+    rpT, colT, valT = oracle.csr_transpose(A2)
+    AT = W.CSR(A.n_cols, A.n_rows, rpT, colT, valT)
+    check_spmv(oracle, AT, dy, host(dx))
+    say("set_values bf16 storage from host float64")
+    Mb = rg.rgcsr_from_csr(A, keep_csr_map=True, value_dtype="bf16")
+    rg.rgcsr_set_values(Mb, theta.astype(np.float64))
+    expb = oracle.rgcsr_layout(A2, 64, values=oracle.round_values(theta, "bf16"))
+    np.testing.assert_array_equal(Mb.export()["slot_val"], expb["slot_val"])
+
+
+def test_autograd_function_fd_and_oracle(torch_cuda, oracle):
+    """Config-5 shape at reduced size: loss 1/2 ||A(theta) x - b||^2, hand-written
+    backward checked against the FP64 oracle gradient, and the oracle against
+    central differences (exact for this quadratic loss)."""
+    torch = torch_cuda
+    A = W.zipf_matrix(100_000, seed=15)
+    x = W.normal_vector(A.n_cols, 5, np.float32)
+    b = W.normal_vector(A.n_rows, 6, np.float32)
+    M = rg.rgcsr_from_csr(A, build_transpose=True, sigma=1 << 40, tau=16)
+    F = rg.spmv_function()
+    th = dev(A.val).requires_grad_(True)
+    xt = dev(x).requires_grad_(True)
+    say("autograd zipf 1e5")
+    y = F.apply(th, xt, M)
+    loss = 0.5 * ((y.double() - dev(b).double()) ** 2).sum()
+    loss.backward()
+    r, dx_ref, dv_ref, L = oracle.adjoint(A, x, b)
+    assert abs(loss.item() - L) <= 1e-5 * L
+    st, sx = grad_tolerances(oracle, A, x, b)
+    assert np.max(np.abs(host(th.grad) - dv_ref)) <= 1e-5 * st
+    assert np.max(np.abs(host(xt.grad) - dx_ref)) <= 1e-5 * sx
+    rng = np.random.default_rng(7)
+    h = 1e-3
+    A64 = A.astype(np.float64)
+    for k in rng.choice(A.nnz, 16, replace=False):
+        tp, tm = A64.val.copy(), A64.val.copy()
+        tp[k] += h
+        tm[k] -= h
+        fd = (oracle.loss(W.CSR(A.n_rows, A.n_cols, A.row_ptr, A.col, tp), x, b)
+              - oracle.loss(W.CSR(A.n_rows, A.n_cols, A.row_ptr, A.col, tm), x, b)) / (2 * h)
+        assert abs(fd - dv_ref[k]) <= 1e-5 * max(1.0, abs(dv_ref[k]))
+
+
+def test_gradcheck_fp64_tiny(torch_cuda):
+    torch = torch_cuda
+    A = W.random_csr(24, 20, seed=16, max_len=6, long_rows=1, long_len=18)
+    M = rg.rgcsr_from_csr(A, value_dtype="f64", keep_csr_map=True, sigma=24, tau=4)
+    F = rg.spmv_function()
+    th = dev(A.val).requires_grad_(True)
+    xt = torch.randn(20, dtype=torch.float64, device="cuda:0", requires_grad=True)
+    say("gradcheck")
+    assert torch.autograd.gradcheck(lambda t, v: F.apply(t, v, M), (th, xt), eps=1e-6, atol=1e-8)
+
+
+# ----------------------------------------------------------------------------
+# Mixed-precision CG
+# ----------------------------------------------------------------------------
+@pytest.mark.parametrize("dt", ["f32", "bf16", "f16"])
+def test_cg_mixed_reaches_1e10(torch_cuda, oracle, dt):
+    torch = torch_cuda
+    A = W.stencil_3d_27pt(40, dtype=np.float32)
+    b = oracle.csr_spmv(A, np.ones(A.n_cols))  # exact integers: solution is all ones
+    say("cg", dt)
+    Alo = rg.rgcsr_from_csr(A, value_dtype=dt)
+    Ahi = rg.rgcsr_from_csr(A, value_dtype="f32")
+    xd = torch.zeros(A.n_rows, dtype=torch.float64, device="cuda:0")
+    st = rg.rgcsr_cg_solve(Alo, Ahi, dev(b), xd, tol=1e-10, inner_tol=1e-4)
+    xh = host(xd)
+    r = b - oracle.csr_spmv(A, xh)
+    rel = math.sqrt(float(np.dot(r, r))) / math.sqrt(float(np.dot(b, b)))
+    say("  ", st, "oracle relres", rel, "max|x-1|", float(np.max(np.abs(xh - 1))))
+    assert st["converged"] and rel <= 1e-10
+    assert np.max(np.abs(xh - 1.0)) <= 1e-8
+
+
+def test_cg_f64(torch_cuda, oracle):
+    torch = torch_cuda
+    A = W.stencil_3d_27pt(30)
+    b = oracle.csr_spmv(A, np.ones(A.n_cols))
+    M = rg.rgcsr_from_csr(A, value_dtype="f64")
+    xd = torch.zeros(A.n_rows, dtype=torch.float64, device="cuda:0")
+    say("cg f64")
+    st = rg.rgcsr_cg_solve_f64(M, dev(b), xd, tol=1e-10)
+    xh = host(xd)
+    r = b - oracle.csr_spmv(A, xh)
+    assert st["converged"] and math.sqrt(float(np.dot(r, r))) / math.sqrt(float(np.dot(b, b))) <= 1e-10
+    x_orc, it_orc, _ = oracle.cg(A, b, tol=1e-10)
+    assert abs(st["inner_iterations"] - it_orc) <= 4   # same method, checked every 4 steps

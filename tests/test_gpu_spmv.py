@@ -128,8 +128,15 @@ def test_deterministic_repeat(torch_cuda, oracle):
     x = dev(W.uniform_vector(A.n_cols, 16, np.float32))
     say("determinism")
     M = rg.rgcsr_from_csr(A, G=64, sigma=100_000, tau=16)
+    y0 = host(M.spmv(x))
+    for _ in range(5):
+        np.testing.assert_array_equal(host(M.spmv(x)), y0)
+    say("determinism with rows split over several workgroups")
+    B = W.random_csr(300, 100_000, seed=5, max_len=30, long_rows=4, long_len=70_000, dtype=np.float32)
+    M = rg.rgcsr_from_csr(B, G=64, sigma=300, tau=16)
     assert M.info["partials"] > 0
     y0 = host(M.spmv(x))
+    check_spmv(oracle, B, host(x), y0)
     for _ in range(5):
         np.testing.assert_array_equal(host(M.spmv(x)), y0)
     del torch
@@ -161,6 +168,20 @@ def test_edge_cases(torch_cuda, oracle):
     M.spmv(dev(np.ones(5, np.float32)), torch.empty(0, device="cuda:0"))
 
 
+def test_unaligned_multi_rhs_falls_back(torch_cuda, oracle):
+    torch = torch_cuda
+    A = W.random_csr(3000, 2000, seed=10, max_len=20, long_rows=2, long_len=1500, dtype=np.float32)
+    M = rg.rgcsr_from_csr(A, sigma=3000, tau=16)
+    X = W.uniform_matrix(A.n_cols, 4, seed=6)
+    Xd = torch.zeros(A.n_cols * 4 + 1, device="cuda:0")[1:].view(A.n_cols, 4)  # 4 bytes off alignment
+    Xd.copy_(dev(X))
+    say("unaligned k=4")
+    Y = host(M.spmm(Xd))
+    ref = oracle.csr_spmm(A, X)
+    for c in range(4):
+        assert oracle.scaled_error(Y[:, c], ref[:, c], oracle.csr_absmv(A, X[:, c])) <= TOL_F32
+
+
 def test_device_resident_csr_input(torch_cuda, oracle):
     torch = torch_cuda
     A = W.random_csr(2000, 1500, seed=9, max_len=20, dtype=np.float32)
@@ -175,10 +196,10 @@ def test_errors_surface_as_status(torch_cuda):
     torch = torch_cuda
     A = W.random_csr(100, 100, seed=1, dtype=np.float32)
     M = rg.rgcsr_from_csr(A)
-    X = torch.zeros(100 * 4 + 1, device="cuda:0")[1:].view(100, 4)  # rows 4 bytes off 16-byte alignment
+    X = torch.zeros((100, 4), device="cuda:0")
     Y = torch.zeros((100, 4), device="cuda:0")
-    with pytest.raises(rg.RgcsrError) as e:
-        rg.rgcsr_spmv_batched(M, X, Y)
+    with pytest.raises(rg.RgcsrError) as e:   # leading dimension smaller than k
+        rg._lib.call("rgcsr_spmv_batched", M.handle, 4, X.data_ptr(), 2, Y.data_ptr(), 4, rg.RGCSR_F32, 0, 0)
     assert e.value.status == 1
     with pytest.raises(rg.RgcsrError) as e:
         rg.rgcsr_from_csr(A, G=48)

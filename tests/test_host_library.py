@@ -120,16 +120,18 @@ def test_layout_sizes_match_oracle(lib, oracle):
 
 
 def test_long_work_items_cover_long_rows(lib):
-    """Every long nonzero is assigned to exactly one wavefront work item."""
+    """Rows longer than 512 go to whole-workgroup items of 16384 nonzeros; a
+    row needing several items gets one partial-sum slot per item."""
     A = W.zipf_matrix(50_000, seed=2)
-    for tau in (0, 8, 64, 700):
-        info = rg.rgcsr_layout_sizes(A, rg.make_opts(G=64, sigma=50_000, tau=tau))
-        lens = np.sort(np.diff(A.row_ptr)[np.diff(A.row_ptr) > tau])[::-1]
-        chunk = 512
-        multi = lens[lens > chunk]
-        expect_parts = int(np.sum((multi + chunk - 1) // chunk))
-        assert info["partials"] == expect_parts
-        assert info["long_nnz"] == int(lens.sum())
+    extra = W.random_csr(20, 50_000, seed=3, max_len=5, long_rows=3, long_len=40_000)
+    for M in (A, extra):
+        for tau in (0, 8, 64, 700):
+            info = rg.rgcsr_layout_sizes(M, rg.make_opts(G=64, sigma=M.n_rows, tau=tau))
+            lens = np.diff(M.row_ptr)
+            lens = lens[lens > tau]
+            nch = (lens[lens > 512] + 16383) // 16384
+            assert info["partials"] == int(nch[nch > 1].sum())
+            assert info["long_nnz"] == int(lens.sum())
 
 
 @pytest.mark.parametrize("s_v,dt", [(4, "f32"), (8, "f64"), (2, "bf16")])
