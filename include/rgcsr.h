@@ -85,10 +85,18 @@ typedef struct {
     int32_t keep_csr_map;
     int32_t build_transpose;
     int32_t validate;
+    int32_t rows_per_lane;  /* kernel schedule: rows each lane multiplies per pass over
+                               its groups, 1, 2, 4 or 8 (0 = chosen from the mean group
+                               width); only with lanes_per_row = 1 */
+    int32_t pad_loads;      /* kernel schedule: 1 = value/column loads run over the
+                               group width so they need not wait for the row length
+                               (padding is still never multiplied), 0 = loads stop at
+                               the row length, -1 = on when padding is at most 25% */
 } rgcsr_opts;
 
 /* Fills *opts with the paper's layout: G = 64, T = 1, sigma = 1, no long
- * rows, float32 storage, no CSR map, no transpose, validation on. */
+ * rows, float32 storage, no CSR map, no transpose, validation on, automatic
+ * kernel schedule (rows_per_lane = 0, pad_loads = -1). */
 void rgcsr_default_opts(rgcsr_opts *opts);
 
 typedef struct rgcsr_matrix_s *rgcsr_handle;
@@ -107,6 +115,7 @@ typedef struct {
     int32_t group_size, lanes_per_row, value_dtype, has_transpose;
     int64_t sort_window, long_row_threshold;
     int64_t device_bytes; /* device memory the handle owns */
+    int32_t rows_per_lane, pad_loads; /* kernel schedule in use */
 } rgcsr_info_t;
 
 /* ---- Host-only layout (no GPU needed; used to check the layout on CPU) ---- */

@@ -70,11 +70,13 @@ def _dev_check(t, name: str):
 
 
 def make_opts(G: int = 64, T: int = 1, sigma: int = 1, tau: int = -1, value_dtype: str = "f32",
-              keep_csr_map: bool = False, build_transpose: bool = False, validate: bool = True) -> _lib.Opts:
+              keep_csr_map: bool = False, build_transpose: bool = False, validate: bool = True,
+              rows_per_lane: int = 0, pad_loads: int = -1) -> _lib.Opts:
     o = _lib.Opts()
     o.group_size, o.lanes_per_row, o.sort_window, o.long_row_threshold = G, T, sigma, tau
     o.value_dtype = DTYPE_CODES[value_dtype]
     o.keep_csr_map, o.build_transpose, o.validate = int(keep_csr_map), int(build_transpose), int(validate)
+    o.rows_per_lane, o.pad_loads = rows_per_lane, pad_loads
     return o
 
 

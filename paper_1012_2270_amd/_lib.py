@@ -25,7 +25,8 @@ P_I32 = ctypes.POINTER(ctypes.c_int32)
 class Opts(ctypes.Structure):
     _fields_ = [("group_size", c_i32), ("lanes_per_row", c_i32), ("sort_window", c_i64),
                 ("long_row_threshold", c_i64), ("value_dtype", c_i32), ("keep_csr_map", c_i32),
-                ("build_transpose", c_i32), ("validate", c_i32)]
+                ("build_transpose", c_i32), ("validate", c_i32), ("rows_per_lane", c_i32),
+                ("pad_loads", c_i32)]
 
 
 class Info(ctypes.Structure):
@@ -34,7 +35,7 @@ class Info(ctypes.Structure):
                 ("n_matrices", c_i64), ("long_work", c_i64), ("partials", c_i64),
                 ("group_size", c_i32), ("lanes_per_row", c_i32), ("value_dtype", c_i32),
                 ("has_transpose", c_i32), ("sort_window", c_i64), ("long_row_threshold", c_i64),
-                ("device_bytes", c_i64)]
+                ("device_bytes", c_i64), ("rows_per_lane", c_i32), ("pad_loads", c_i32)]
 
     def as_dict(self) -> dict:
         return {f: getattr(self, f) for f, _ in self._fields_}

@@ -90,6 +90,7 @@ struct rgcsr_matrix_s {
     int64_t n_matrices = 1, n_wave_long = 0, n_block = 0, n_combine = 0, n_partials = 0;
     bool ragged = false, perm = false;
     int32_t wpg = 0, gpw = 0;
+    int32_t R = 1, pad = 0;  // kernel schedule: rows per lane, padded-width loads
     std::vector<int64_t> row_off, col_off;
     void *mem = nullptr;
     size_t bytes = 0;
@@ -198,8 +199,28 @@ void build_host(Built &B, const LayoutParams &p, int vdt, int32_t count, const i
     if (transpose) build_long_work(B.LT.long_ptr, B.LT.work);
 }
 
+// Kernel schedule: rows per lane from the mean group width (about 16 steps
+// in flight per lane), padded-width loads when padding is at most 25%.
+void choose_schedule(rgcsr_matrix_s *h, const HostLayout &L, int32_t rows_per_lane, int32_t pad_loads) {
+    int64_t short_nnz = 0;
+    for (int32_t v : L.short_len) short_nnz += v;
+    const int64_t pad_slots = L.slots - short_nnz;
+    if (pad_loads < 0) h->pad = pad_slots * 4 <= short_nnz ? 1 : 0;
+    else h->pad = pad_loads ? 1 : 0;
+    int32_t R = rows_per_lane;
+    if (R == 0) {
+        const double w = L.ns ? (double)L.slots / (double)L.ns : 1.0;
+        R = 1;
+        while (R < 8 && w * (2 * R) <= 16.0) R *= 2;
+    }
+    if (R != 1 && R != 2 && R != 4 && R != 8) fail(RGCSR_EINVAL, "rows_per_lane must be 0, 1, 2, 4 or 8");
+    if (L.T != 1 || h->gpw > 0) R = 1;
+    h->R = R;
+}
+
 rgcsr_matrix_s *make_device(const HostLayout &L, const std::vector<int64_t> *row_ptr,
-                            const HostLayout *map, hipStream_t st) {
+                            const HostLayout *map, hipStream_t st, int32_t rows_per_lane = 0,
+                            int32_t pad_loads = -1) {
     auto *h = new rgcsr_matrix_s();
     try {
         h->device = current_device();
@@ -220,6 +241,12 @@ rgcsr_matrix_s *make_device(const HostLayout &L, const std::vector<int64_t> *row
         const int64_t GT = (int64_t)L.G * L.T;
         h->wpg = GT >= 64 ? (int32_t)(GT / 64) : 0;
         h->gpw = GT < 64 ? (int32_t)(64 / GT) : 0;
+        choose_schedule(h, L, rows_per_lane, pad_loads);
+        // the kernels address a group's slots with 32-bit byte offsets
+        int64_t max_group = 0;
+        for (size_t g = 0; g + 1 < L.gp.size(); g++) max_group = std::max(max_group, L.gp[g + 1] - L.gp[g]);
+        if (max_group * std::max(L.esz, 4) >= (int64_t(1) << 32))
+            fail(RGCSR_EOVERFLOW, "a row group holds 4 GiB or more; use a long-row threshold");
 
         Arena a;
         a.add(&h->gp, L.gp.size());
@@ -282,25 +309,28 @@ void check_handle(const rgcsr_matrix_s *h) {
     if (current_device() != h->device) fail(RGCSR_EINVAL, "handle belongs to another device");
 }
 
-int32_t short_waves(const rgcsr_matrix_s *h) {
+int32_t short_waves(const rgcsr_matrix_s *h, bool scheduled) {
     int64_t w = h->wpg > 0 ? h->ng * h->wpg : (h->ng + h->gpw - 1) / h->gpw;
+    if (scheduled) w = (w + h->R - 1) / h->R;
     if (w > INT32_MAX / 2) fail(RGCSR_EOVERFLOW, "too many wavefronts");
     return (int32_t)w;
 }
 
-SpmvParams params_of(const rgcsr_matrix_s *h, bool per_row_long) {
+// use_rows: the launch uses the handle's rows-per-lane schedule (single
+// right-hand side); otherwise one row per lane.
+SpmvParams params_of(const rgcsr_matrix_s *h, bool use_rows) {
     SpmvParams P{};
     P.gp = h->gp; P.grp_row0 = h->grp_row0; P.short_len = h->short_len; P.short_row = h->short_row;
     P.slot_val = h->slot_val; P.slot_col = h->slot_col;
     P.ng = h->ng; P.ns = h->ns; P.G = h->prm.G; P.wpg = h->wpg; P.gpw = h->gpw;
-    P.ragged = h->ragged; P.perm = h->perm;
+    P.ragged = h->ragged; P.perm = h->perm; P.pad = h->pad;
     P.wave_work = h->wave_work; P.block_work = h->block_work;
     P.long_row = h->long_row; P.long_ptr = h->long_ptr; P.long_val = h->long_val;
     P.long_col = h->long_col; P.partial = h->partial;
-    const int64_t sw = short_waves(h);
+    const int64_t sw = short_waves(h, use_rows);
     const int64_t wave_items = h->n_wave_long + sw;
     const int64_t units = h->n_block + (wave_items + kBlockWaves - 1) / kBlockWaves;
-    const int64_t tot = h->nl + sw;
+    const int64_t tot = h->nl + short_waves(h, false);
     if (wave_items > INT32_MAX / 2 || units > INT32_MAX / 2 || tot > INT32_MAX / 2)
         fail(RGCSR_EOVERFLOW, "too many wavefronts");
     P.n_block_items = (int32_t)h->n_block;
@@ -309,7 +339,6 @@ SpmvParams params_of(const rgcsr_matrix_s *h, bool per_row_long) {
     P.total_units = (int32_t)units;
     P.n_long_waves = (int32_t)h->nl;
     P.total_waves = (int32_t)tot;
-    (void)per_row_long;
     return P;
 }
 
@@ -322,7 +351,7 @@ int vec_is_f64(rgcsr_dtype vt) {
 void spmv_launch(const rgcsr_matrix_s *h, int K, const void *X, int64_t ldx, void *Y, int64_t ldy, int f64,
                  bool persistent, hipStream_t st) {
     if (h->n_rows == 0) return;
-    SpmvParams P = params_of(h, false);
+    SpmvParams P = params_of(h, K == 1);
     P.x = X; P.y = Y; P.ldx = ldx; P.ldy = ldy;
     int64_t nwg = P.total_units;
     // a persistent launch keeps two 1024-thread workgroups resident per CU
@@ -335,7 +364,9 @@ void spmv_launch(const rgcsr_matrix_s *h, int K, const void *X, int64_t ldx, voi
     if (K > 1 && (vd == RGCSR_F16 || vd == RGCSR_BF16))
         fail(RGCSR_EUNSUPPORTED, "several right-hand sides need F32 or F64 stored values");
     if (K > 1 && h->prm.T != 1) fail(RGCSR_EUNSUPPORTED, "several right-hand sides need lanes_per_row = 1");
-    hipError_t e = launch_spmv(P, vd, f64, h->prm.T, K, (int)nwg, st);
+    if (K == 1 && h->n_cols * ldx * (f64 ? 8 : 4) >= (int64_t(1) << 32))
+        fail(RGCSR_EUNSUPPORTED, "x (n_cols * ldx elements) of 4 GiB or more");
+    hipError_t e = launch_spmv(P, vd, f64, h->prm.T, K, K == 1 ? h->R : 1, (int)nwg, st);
     if (e != hipSuccess) fail(RGCSR_EHIP, std::string("spmv launch: ") + hipGetErrorString(e));
     if (h->n_combine) {
         e = launch_combine(h->combine, (int32_t)h->n_combine, h->long_row, h->partial, Y, ldy, f64, K, st);
@@ -359,6 +390,8 @@ void rgcsr_default_opts(rgcsr_opts *o) {
     o->keep_csr_map = 0;
     o->build_transpose = 0;
     o->validate = 1;
+    o->rows_per_lane = 0;
+    o->pad_loads = -1;
 }
 
 const char *rgcsr_status_string(rgcsr_status s) {
@@ -478,10 +511,11 @@ rgcsr_status rgcsr_from_csr(int64_t n_rows, int64_t n_cols, int64_t nnz, const i
     Built B;
     const bool keep = o.keep_csr_map != 0, tr = o.build_transpose != 0;
     build_host(B, p, o.value_dtype, 1, &n_rows, &n_cols, &rp, &col, &val, vals_dtype, o.validate != 0, keep, tr);
-    rgcsr_matrix_s *h = make_device(B.L, (keep || tr) ? &B.row_ptr : nullptr, nullptr, st);
+    rgcsr_matrix_s *h = make_device(B.L, (keep || tr) ? &B.row_ptr : nullptr, nullptr, st, o.rows_per_lane,
+                                    o.pad_loads);
     if (tr) {
         try {
-            h->AT = make_device(B.LT, nullptr, &B.LTmap, st);
+            h->AT = make_device(B.LT, nullptr, &B.LTmap, st, o.rows_per_lane, o.pad_loads);
         } catch (...) {
             free_handle(h);
             throw;
@@ -510,10 +544,11 @@ rgcsr_status rgcsr_from_csr_batch(int32_t count, const int64_t *n_rows, const in
     const bool keep = o.keep_csr_map != 0, tr = o.build_transpose != 0;
     build_host(B, p, o.value_dtype, count, n_rows, n_cols, row_ptr, col_idx, vals, vals_dtype, o.validate != 0,
                keep, tr);
-    rgcsr_matrix_s *h = make_device(B.L, (keep || tr) ? &B.row_ptr : nullptr, nullptr, st);
+    rgcsr_matrix_s *h = make_device(B.L, (keep || tr) ? &B.row_ptr : nullptr, nullptr, st, o.rows_per_lane,
+                                    o.pad_loads);
     if (tr) {
         try {
-            h->AT = make_device(B.LT, nullptr, &B.LTmap, st);
+            h->AT = make_device(B.LT, nullptr, &B.LTmap, st, o.rows_per_lane, o.pad_loads);
         } catch (...) {
             free_handle(h);
             throw;
@@ -727,6 +762,8 @@ rgcsr_status rgcsr_info(rgcsr_handle A, rgcsr_info_t *out) {
     out->value_dtype = A->vdt; out->has_transpose = A->AT != nullptr;
     out->sort_window = A->prm.sigma; out->long_row_threshold = A->prm.tau;
     out->device_bytes = (int64_t)A->bytes + (A->AT ? (int64_t)A->AT->bytes : 0);
+    out->rows_per_lane = A->R;
+    out->pad_loads = A->pad;
     ABI_CATCH
 }
 

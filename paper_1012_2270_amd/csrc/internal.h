@@ -104,11 +104,11 @@ void convert_values(const void *src, int src_dt, void *dst, int dst_dt, int64_t 
 struct LongItem {
     int32_t a, b, c, d;
 };
-constexpr int kWaveUnroll = 8;
-constexpr int kWaveRowMax = 64 * kWaveUnroll;                    // 512
-constexpr int kBlockThreads = 1024;                              // SpMV workgroup
-constexpr int kBlockWaves = kBlockThreads / 64;                  // 16
-constexpr int kBlockUnroll = 16;
+constexpr int kWaveUnroll = 16;                                  // nonzeros per lane, wave items
+constexpr int kWaveRowMax = 64 * kWaveUnroll;                    // 1024
+constexpr int kBlockThreads = 256;                               // SpMV workgroup
+constexpr int kBlockWaves = kBlockThreads / 64;                  // 4
+constexpr int kBlockUnroll = 64;                                 // nonzeros per lane, block items
 constexpr int64_t kBlockChunk = (int64_t)kBlockThreads * kBlockUnroll;  // 16384
 
 struct LongWork {

@@ -21,6 +21,7 @@ struct SpmvParams {
     int32_t wpg;               // wavefronts per group when G*T >= 64, else 0
     int32_t gpw;               // groups per wavefront when G*T < 64, else 0
     int32_t ragged, perm;
+    int32_t pad;               // value/column loads run over the group width
     // long rows
     const LongItem *wave_work;   // [n_wave_long] wave items
     const LongItem *block_work;  // [n_block_items] block items
@@ -55,7 +56,7 @@ struct HybParams {
 enum { kRR = 0, kRR0 = 1, kPQ = 2, kAlpha = 3, kBeta = 4, kOut = 5, kNumScal = 8 };
 enum { kScalPQ = 0, kScalRRNew = 1, kScalRRInit = 2, kScalOut = 3 };
 
-hipError_t launch_spmv(const SpmvParams &P, int vdt, int vec_f64, int T, int K, int nwg, hipStream_t st);
+hipError_t launch_spmv(const SpmvParams &P, int vdt, int vec_f64, int T, int K, int R, int nwg, hipStream_t st);
 hipError_t launch_combine(const LongItem *items, int32_t n, const int32_t *long_row, const void *partial, void *Y,
                           int64_t ldy, int vec_f64, int K, hipStream_t st);
 hipError_t launch_setval(const SpmvParams &P, int vdt, int T, const void *theta, int theta_f64,

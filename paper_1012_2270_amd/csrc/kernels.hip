@@ -57,6 +57,26 @@ template <> struct Val<RGCSR_BF16> {
 
 template <class T> __device__ __forceinline__ T ldnt(const T *p) { return __builtin_nontemporal_load(p); }
 
+// Read-only metadata through the constant address space: with a uniform index
+// the compiler issues scalar loads, which need no vector registers and do not
+// wait on outstanding vector loads.
+typedef int i32x4 __attribute__((ext_vector_type(4)));
+
+template <class T> __device__ __forceinline__ T ldc(const T *p, int64_t i) {
+#if defined(__HIP_DEVICE_COMPILE__)
+    if constexpr (sizeof(T) == 16) {
+        const i32x4 v = ((const __attribute__((address_space(4))) i32x4 *)(p))[i];
+        T r;
+        __builtin_memcpy(&r, &v, 16);
+        return r;
+    } else {
+        return ((const __attribute__((address_space(4))) T *)(p))[i];
+    }
+#else
+    return p[i];
+#endif
+}
+
 // K consecutive vector entries starting at p (16-byte aligned when K > 1 is a
 // multiple of the vector width; checked on the host).
 template <class A, int K> __device__ __forceinline__ void load_row(const A *p, A (&v)[K]) {
@@ -104,41 +124,77 @@ struct LaneRow {
     int64_t stride;  // slots between this lane's consecutive elements
     int len;         // row length
     int q;           // sub-lane within the row (0 .. T-1)
+    int wc;          // steps of the group (its width / T); 0 when the lane has no row
     bool ok;
 };
 
-template <int T>
-__device__ __forceinline__ LaneRow lane_row(const SpmvParams &P, int32_t w, int lane) {
-    LaneRow L;
-    int64_t g;
-    int lr;
-    if (P.wpg > 0) {  // G*T >= 64: wpg wavefronts per group
-        g = w / P.wpg;
-        lr = (w - (int32_t)g * P.wpg) * 64 + lane;
-    } else {          // G*T divides 64: gpw groups per wavefront
-        const int GT = P.G * T;
-        g = (int64_t)w * P.gpw + lane / GT;
-        lr = lane % GT;
-    }
-    const int t = lr / T;
-    L.q = lr % T;
-    int64_t row0 = 0;
-    int sg = 0;
+// Group metadata of group g (row0, row count, first and end slot).
+struct GroupMeta {
+    int64_t row0, g0, g1;
+    int sg;
+};
+
+// Uniform group index: scalar loads.
+__device__ __forceinline__ GroupMeta group_meta_uniform(const SpmvParams &P, int64_t g) {
+    GroupMeta m{0, 0, 0, 0};
     if (g < P.ng) {
         if (P.ragged) {
-            row0 = P.grp_row0[g];
-            sg = P.grp_row0[g + 1] - (int32_t)row0;
+            m.row0 = ldc(P.grp_row0, g);
+            m.sg = ldc(P.grp_row0, g + 1) - (int32_t)m.row0;
         } else {
-            row0 = g * P.G;
-            sg = (int)min((int64_t)P.G, P.ns - row0);
+            m.row0 = g * P.G;
+            m.sg = (int)min((int64_t)P.G, P.ns - m.row0);
         }
+        m.g0 = ldc(P.gp, g);
+        m.g1 = ldc(P.gp, g + 1);
     }
-    L.ok = t < sg;
-    L.i = row0 + t;
+    return m;
+}
+
+// Per-lane group index (several groups per wavefront): vector loads.
+__device__ __forceinline__ GroupMeta group_meta_lane(const SpmvParams &P, int64_t g) {
+    GroupMeta m{0, 0, 0, 0};
+    if (g < P.ng) {
+        if (P.ragged) {
+            m.row0 = P.grp_row0[g];
+            m.sg = P.grp_row0[g + 1] - (int32_t)m.row0;
+        } else {
+            m.row0 = g * P.G;
+            m.sg = (int)min((int64_t)P.G, P.ns - m.row0);
+        }
+        m.g0 = P.gp[g];
+        m.g1 = P.gp[g + 1];
+    }
+    return m;
+}
+
+template <int T>
+__device__ __forceinline__ LaneRow lane_row_of(const SpmvParams &P, const GroupMeta &m, int lr) {
+    LaneRow L;
+    const int t = lr / T;
+    L.q = lr % T;
+    L.ok = t < m.sg;
+    L.i = m.row0 + t;
     L.len = L.ok ? P.short_len[L.i] : 0;
-    L.base = L.ok ? P.gp[g] + (int64_t)t * T + L.q : 0;
-    L.stride = (int64_t)sg * T;
+    L.base = L.ok ? m.g0 + (int64_t)t * T + L.q : 0;
+    L.stride = (int64_t)m.sg * T;
+    // slots of a group are fewer than 2^31 (G rows of int32 length)
+    L.wc = L.ok ? (int)((uint32_t)(m.g1 - m.g0) / (uint32_t)L.stride) : 0;
     return L;
+}
+
+// Row of wave-item w owned by this lane.
+template <int T>
+__device__ __forceinline__ LaneRow lane_row(const SpmvParams &P, int32_t w, int lane) {
+    if (P.wpg > 0) {  // G*T >= 64: wpg wavefronts per group, group index uniform
+        const int32_t g = w / P.wpg;
+        const int lr = (w - g * P.wpg) * 64 + lane;
+        return lane_row_of<T>(P, group_meta_uniform(P, g), lr);
+    }
+    // G*T divides 64: gpw groups per wavefront
+    const int GT = P.G * T;
+    const int64_t g = (int64_t)w * P.gpw + lane / GT;
+    return lane_row_of<T>(P, group_meta_lane(P, g), lane % GT);
 }
 
 // ---------------------------------------------------------------------------
@@ -152,8 +208,130 @@ __device__ __forceinline__ LaneRow lane_row(const SpmvParams &P, int32_t w, int 
 // ---------------------------------------------------------------------------
 template <int K> constexpr int unroll_for() { return K == 1 ? 8 : (K <= 4 ? 4 : (K <= 8 ? 2 : 1)); }
 
+// X[c * ldx] for one right-hand side with a 32-bit byte offset from the
+// uniform base (scalar base + vector offset addressing; the host checks
+// n_cols * ldx * size < 4 GiB for single right-hand-side launches).
+template <class A> __device__ __forceinline__ A ldx32(const A *X, int32_t c, uint32_t row_bytes) {
+    return *(const A *)((const char *)X + (uint32_t)c * row_bytes);
+}
+
+// Row groups when every lane of a wavefront belongs to the same group
+// (G*T a multiple of 64): the group pointers are scalar, value/column loads
+// use 32-bit offsets from the group's first slot.
+template <int VD, class A, int K, int T, int R, bool PAD>
+__device__ __forceinline__ void spmv_groups_uniform(const SpmvParams &P, int32_t w, int lane) {
+    using V = Val<VD>;
+    using S = typename V::S;
+    const A *X = (const A *)P.x;
+    A *Y = (A *)P.y;
+    const uint32_t xrow = (uint32_t)(P.ldx * (int64_t)sizeof(A));
+    const S *vb[R];
+    const int32_t *cb[R];
+    int32_t off0[R], stride[R], nl[R], len[R];
+    int64_t rowi[R];
+    bool ok[R];
+    int q = 0;
+    int cmax = 0;
+#pragma unroll
+    for (int r = 0; r < R; r++) {
+        const int32_t wr = w * R + r;
+        const int32_t g = __builtin_amdgcn_readfirstlane(wr / P.wpg);
+        const int lr = (wr - g * P.wpg) * 64 + lane;
+        const GroupMeta m = group_meta_uniform(P, g);
+        const int t = lr / T;
+        q = lr % T;
+        ok[r] = t < m.sg;
+        rowi[r] = m.row0 + t;
+        // unconditional load at a clamped index (no branch around it)
+        len[r] = P.short_len[ok[r] ? rowi[r] : 0];
+        stride[r] = m.sg * T;
+        const bool has = m.g1 > m.g0;
+        // a group without slots points at slot 0 (read only when the loop runs)
+        const int64_t gb = has ? m.g0 : 0;
+        vb[r] = (const S *)P.slot_val + gb;
+        cb[r] = P.slot_col + gb;
+        off0[r] = t * T + q;
+        if constexpr (PAD) {
+            const int32_t wc = has ? (int32_t)((uint32_t)(m.g1 - m.g0) / (uint32_t)stride[r]) : 0;
+            nl[r] = ok[r] ? wc : 0;
+            cmax = max(cmax, nl[r]);
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < R; r++) len[r] = ok[r] ? len[r] : 0;
+    if constexpr (!PAD) {
+        cmax = 0;
+#pragma unroll
+        for (int r = 0; r < R; r++) {
+            nl[r] = len[r] > q ? (len[r] - q + T - 1) / T : 0;
+            cmax = max(cmax, nl[r]);
+        }
+    }
+    A acc[R][K];
+#pragma unroll
+    for (int r = 0; r < R; r++)
+#pragma unroll
+        for (int k = 0; k < K; k++) acc[r][k] = A(0);
+    constexpr int U = K == 1 ? 16 / R : unroll_for<K>();
+    // Inside the unrolled body every load is issued unconditionally (steps past
+    // the bound read the group's first slot and x[0], in bounds whenever the
+    // loop runs) and results are masked with selects, so the loads of a phase
+    // are not split by branches and are in flight together.
+    for (int c0 = 0; c0 < cmax; c0 += U) {
+        S v[R][U];
+        int32_t ci[R][U];
+        A xv[R][U][K];
+#pragma unroll
+        for (int r = 0; r < R; r++)
+#pragma unroll
+            for (int u = 0; u < U; u++) {
+                const uint32_t o = c0 + u < nl[r] ? (uint32_t)(off0[r] + (c0 + u) * stride[r]) : 0u;
+                v[r][u] = ldnt((const S *)((const char *)vb[r] + o * (uint32_t)sizeof(S)));
+                ci[r][u] = ldnt((const int32_t *)((const char *)cb[r] + o * 4u));
+            }
+        int n[R];
+#pragma unroll
+        for (int r = 0; r < R; r++) n[r] = len[r] > q ? (len[r] - q + T - 1) / T : 0;
+#pragma unroll
+        for (int r = 0; r < R; r++)
+#pragma unroll
+            for (int u = 0; u < U; u++) {
+                const int32_t c = c0 + u < n[r] ? ci[r][u] : 0;
+                if constexpr (K == 1) xv[r][u][0] = ldx32(X, c, xrow);
+                else load_row<A, K>(X + (int64_t)c * P.ldx, xv[r][u]);
+            }
+#pragma unroll
+        for (int r = 0; r < R; r++)
+#pragma unroll
+            for (int u = 0; u < U; u++) {
+                const bool on = c0 + u < n[r];
+                const A a = V::template cvt<A>(v[r][u]);
+#pragma unroll
+                for (int k = 0; k < K; k++) {
+                    const A f = fmaA(a, xv[r][u][k], acc[r][k]);
+                    acc[r][k] = on ? f : acc[r][k];
+                }
+            }
+    }
+#pragma unroll
+    for (int r = 0; r < R; r++) {
+        if constexpr (T > 1) {
+#pragma unroll
+            for (int off = T / 2; off > 0; off >>= 1)
+#pragma unroll
+                for (int k = 0; k < K; k++) acc[r][k] += __shfl_xor(acc[r][k], off);
+        }
+        if (ok[r] && q == 0) {
+            const int64_t row = P.perm ? (int64_t)P.short_row[rowi[r]] : rowi[r];
+            store_row<A, K>(Y + row * P.ldy, acc[r]);
+        }
+    }
+}
+
+// Row groups of fewer than 64 lanes (several groups per wavefront): one row
+// per lane, per-lane group metadata.
 template <int VD, class A, int K, int T>
-__device__ __forceinline__ void spmv_short(const SpmvParams &P, int32_t w, int lane) {
+__device__ __forceinline__ void spmv_groups_lane(const SpmvParams &P, int32_t w, int lane) {
     using V = Val<VD>;
     using S = typename V::S;
     const S *vals = (const S *)P.slot_val;
@@ -164,29 +342,27 @@ __device__ __forceinline__ void spmv_short(const SpmvParams &P, int32_t w, int l
     A acc[K];
 #pragma unroll
     for (int k = 0; k < K; k++) acc[k] = A(0);
-    constexpr int U = unroll_for<K>();
+    constexpr int U = K == 1 ? 8 : unroll_for<K>();
     for (int c0 = 0; c0 < n; c0 += U) {
         S v[U];
         int32_t ci[U];
         A xv[U][K];
 #pragma unroll
         for (int u = 0; u < U; u++) {
-            if (c0 + u < n) {
-                const int64_t s = L.base + (int64_t)(c0 + u) * L.stride;
-                v[u] = ldnt(vals + s);
-                ci[u] = ldnt(P.slot_col + s);
-            }
+            const int64_t s = c0 + u < n ? L.base + (int64_t)(c0 + u) * L.stride : L.base;
+            v[u] = ldnt(vals + s);
+            ci[u] = ldnt(P.slot_col + s);
         }
 #pragma unroll
-        for (int u = 0; u < U; u++) {
-            if (c0 + u < n) load_row<A, K>(X + (int64_t)ci[u] * P.ldx, xv[u]);
-        }
+        for (int u = 0; u < U; u++) load_row<A, K>(X + (int64_t)ci[u] * P.ldx, xv[u]);
 #pragma unroll
         for (int u = 0; u < U; u++) {
-            if (c0 + u < n) {
-                const A a = V::template cvt<A>(v[u]);
+            const bool on = c0 + u < n;
+            const A a = V::template cvt<A>(v[u]);
 #pragma unroll
-                for (int k = 0; k < K; k++) acc[k] = fmaA(a, xv[u][k], acc[k]);
+            for (int k = 0; k < K; k++) {
+                const A f = fmaA(a, xv[u][k], acc[k]);
+                acc[k] = on ? f : acc[k];
             }
         }
     }
@@ -202,6 +378,16 @@ __device__ __forceinline__ void spmv_short(const SpmvParams &P, int32_t w, int l
     }
 }
 
+template <int VD, class A, int K, int T, int R>
+__device__ __forceinline__ void spmv_short(const SpmvParams &P, int32_t w, int lane) {
+    if (P.wpg > 0) {
+        if (P.pad) spmv_groups_uniform<VD, A, K, T, R, true>(P, w, lane);
+        else spmv_groups_uniform<VD, A, K, T, R, false>(P, w, lane);
+    } else if constexpr (R == 1) {
+        spmv_groups_lane<VD, A, K, T>(P, w, lane);
+    }
+}
+
 // Elements beg + q, beg + q + stride, ... < end of one lane, three-phase.
 template <int VD, class A, int K, int U>
 __device__ __forceinline__ void strided_dot(const SpmvParams &P, int64_t beg, int64_t end, int64_t stride,
@@ -210,27 +396,28 @@ __device__ __forceinline__ void strided_dot(const SpmvParams &P, int64_t beg, in
     using S = typename V::S;
     const S *vals = (const S *)P.long_val;
     const A *X = (const A *)P.x;
+    // branch-free body as in the row groups: out-of-range steps re-read the
+    // lane's first element (valid whenever the loop runs) and are masked
     for (int64_t e0 = beg; e0 < end; e0 += stride * U) {
         S v[U];
         int32_t ci[U];
         A xv[U][K];
 #pragma unroll
         for (int u = 0; u < U; u++) {
-            const int64_t e = e0 + u * stride;
-            if (e < end) {
-                v[u] = ldnt(vals + e);
-                ci[u] = ldnt(P.long_col + e);
-            }
+            const int64_t e = e0 + u * stride < end ? e0 + u * stride : beg;
+            v[u] = ldnt(vals + e);
+            ci[u] = ldnt(P.long_col + e);
         }
 #pragma unroll
-        for (int u = 0; u < U; u++)
-            if (e0 + u * stride < end) load_row<A, K>(X + (int64_t)ci[u] * P.ldx, xv[u]);
+        for (int u = 0; u < U; u++) load_row<A, K>(X + (int64_t)ci[u] * P.ldx, xv[u]);
 #pragma unroll
         for (int u = 0; u < U; u++) {
-            if (e0 + u * stride < end) {
-                const A a = V::template cvt<A>(v[u]);
+            const bool on = e0 + u * stride < end;
+            const A a = V::template cvt<A>(v[u]);
 #pragma unroll
-                for (int k = 0; k < K; k++) acc[k] = fmaA(a, xv[u][k], acc[k]);
+            for (int k = 0; k < K; k++) {
+                const A f = fmaA(a, xv[u][k], acc[k]);
+                acc[k] = on ? f : acc[k];
             }
         }
     }
@@ -240,7 +427,7 @@ __device__ __forceinline__ void strided_dot(const SpmvParams &P, int64_t beg, in
 template <int VD, class A, int K>
 __device__ __forceinline__ void spmv_wave_long(const SpmvParams &P, int32_t w, int lane) {
     A *Y = (A *)P.y;
-    const LongItem it = P.wave_work[w];
+    const LongItem it = ldc(P.wave_work, w);
     const int TL = it.c;
     const int sh = 31 - __builtin_clz(TL);
     const int r = lane >> sh, q = lane & (TL - 1);
@@ -263,14 +450,14 @@ __device__ __forceinline__ void spmv_wave_long(const SpmvParams &P, int32_t w, i
 template <int VD, class A, int K>
 __device__ __forceinline__ void spmv_block_item(const SpmvParams &P, int32_t u, A (*red)[K]) {
     A *Y = (A *)P.y;
-    const LongItem it = P.block_work[u];
+    const LongItem it = ldc(P.block_work, u);
     const int64_t li = it.a;
-    const int64_t beg = P.long_ptr[li] + (int64_t)it.b * kBlockChunk;
-    const int64_t end = min(P.long_ptr[li + 1], beg + kBlockChunk);
+    const int64_t beg = ldc(P.long_ptr, li) + (int64_t)it.b * kBlockChunk;
+    const int64_t end = min(ldc(P.long_ptr, li + 1), beg + kBlockChunk);
     A acc[K];
 #pragma unroll
     for (int k = 0; k < K; k++) acc[k] = A(0);
-    strided_dot<VD, A, K, (K == 1 ? 8 : unroll_for<K>())>(P, beg + threadIdx.x, end, kBlockThreads, acc);
+    strided_dot<VD, A, K, (K == 1 ? 16 : unroll_for<K>())>(P, beg + threadIdx.x, end, kBlockThreads, acc);
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1)
 #pragma unroll
@@ -292,7 +479,7 @@ __device__ __forceinline__ void spmv_block_item(const SpmvParams &P, int32_t u, 
     __syncthreads();
 }
 
-template <int VD, class A, int K, int T, bool LONG>
+template <int VD, class A, int K, int T, int R, bool LONG>
 __global__ __launch_bounds__(kBlockThreads) void rgcsr_spmv_k(SpmvParams P) {
     __shared__ A red[kBlockWaves][K];
     const int lane = threadIdx.x & 63;
@@ -308,7 +495,7 @@ __global__ __launch_bounds__(kBlockThreads) void rgcsr_spmv_k(SpmvParams P) {
         if (LONG && w < P.n_wave_long)
             spmv_wave_long<VD, A, K>(P, w, lane);
         else
-            spmv_short<VD, A, K, T>(P, w - (LONG ? P.n_wave_long : 0), lane);
+            spmv_short<VD, A, K, T, R>(P, w - (LONG ? P.n_wave_long : 0), lane);
     }
 }
 
@@ -637,37 +824,44 @@ __global__ __launch_bounds__(256) void fill_k(int64_t n, VT *a, VT v) {
 // ---------------------------------------------------------------------------
 static hipError_t check_launch() { return hipGetLastError(); }
 
-template <int VD, class A, int K, int T>
+template <int VD, class A, int K, int T, int R>
 static hipError_t launch_spmv_t(const SpmvParams &P, int nwg, hipStream_t st) {
     if (P.n_block_items + P.n_wave_long > 0)
-        hipLaunchKernelGGL((rgcsr_spmv_k<VD, A, K, T, true>), dim3(nwg), dim3(kBlockThreads), 0, st, P);
+        hipLaunchKernelGGL((rgcsr_spmv_k<VD, A, K, T, R, true>), dim3(nwg), dim3(kBlockThreads), 0, st, P);
     else
-        hipLaunchKernelGGL((rgcsr_spmv_k<VD, A, K, T, false>), dim3(nwg), dim3(kBlockThreads), 0, st, P);
+        hipLaunchKernelGGL((rgcsr_spmv_k<VD, A, K, T, R, false>), dim3(nwg), dim3(kBlockThreads), 0, st, P);
     return check_launch();
 }
 
-template <int VD, class A, int K>
-static hipError_t launch_spmv_k(const SpmvParams &P, int T, int nwg, hipStream_t st) {
-    switch (T) {
-    case 1: return launch_spmv_t<VD, A, K, 1>(P, nwg, st);
-    case 2: return launch_spmv_t<VD, A, K, 2>(P, nwg, st);
-    case 4: return launch_spmv_t<VD, A, K, 4>(P, nwg, st);
-    case 8: return launch_spmv_t<VD, A, K, 8>(P, nwg, st);
-    }
-    return hipErrorInvalidValue;
-}
-
-// Several right-hand sides use the paper's one-lane-per-row layout only.
+// One lane per row (T = 1) takes R in {1, 2, 4, 8} rows per lane; T > 1 and
+// several right-hand sides take one row per lane.
 template <int VD, class A>
-static hipError_t launch_spmv_vk(const SpmvParams &P, int T, int K, int nwg, hipStream_t st) {
-    if (K == 1) return launch_spmv_k<VD, A, 1>(P, T, nwg, st);
-    if (T != 1) return hipErrorInvalidValue;
+static hipError_t launch_spmv_vk(const SpmvParams &P, int T, int K, int R, int nwg, hipStream_t st) {
+    if (K == 1) {
+        if (T == 1) {
+            switch (R) {
+            case 1: return launch_spmv_t<VD, A, 1, 1, 1>(P, nwg, st);
+            case 2: return launch_spmv_t<VD, A, 1, 1, 2>(P, nwg, st);
+            case 4: return launch_spmv_t<VD, A, 1, 1, 4>(P, nwg, st);
+            case 8: return launch_spmv_t<VD, A, 1, 1, 8>(P, nwg, st);
+            }
+            return hipErrorInvalidValue;
+        }
+        if (R != 1) return hipErrorInvalidValue;
+        switch (T) {
+        case 2: return launch_spmv_t<VD, A, 1, 2, 1>(P, nwg, st);
+        case 4: return launch_spmv_t<VD, A, 1, 4, 1>(P, nwg, st);
+        case 8: return launch_spmv_t<VD, A, 1, 8, 1>(P, nwg, st);
+        }
+        return hipErrorInvalidValue;
+    }
+    if (T != 1 || R != 1) return hipErrorInvalidValue;
     switch (K) {
-    case 2: return launch_spmv_t<VD, A, 2, 1>(P, nwg, st);
-    case 4: return launch_spmv_t<VD, A, 4, 1>(P, nwg, st);
-    case 8: return launch_spmv_t<VD, A, 8, 1>(P, nwg, st);
-    case 16: return launch_spmv_t<VD, A, 16, 1>(P, nwg, st);
-    case 32: return launch_spmv_t<VD, A, 32, 1>(P, nwg, st);
+    case 2: return launch_spmv_t<VD, A, 2, 1, 1>(P, nwg, st);
+    case 4: return launch_spmv_t<VD, A, 4, 1, 1>(P, nwg, st);
+    case 8: return launch_spmv_t<VD, A, 8, 1, 1>(P, nwg, st);
+    case 16: return launch_spmv_t<VD, A, 16, 1, 1>(P, nwg, st);
+    case 32: return launch_spmv_t<VD, A, 32, 1, 1>(P, nwg, st);
     }
     return hipErrorInvalidValue;
 }
@@ -701,14 +895,14 @@ hipError_t launch_combine(const LongItem *items, int32_t n, const int32_t *long_
     return launch_combine_a<float>(items, n, long_row, partial, Y, ldy, K, st);
 }
 
-hipError_t launch_spmv(const SpmvParams &P, int vdt, int vec_f64, int T, int K, int nwg, hipStream_t st) {
+hipError_t launch_spmv(const SpmvParams &P, int vdt, int vec_f64, int T, int K, int R, int nwg, hipStream_t st) {
     if (vec_f64) {
-        if (vdt == RGCSR_F64) return launch_spmv_vk<RGCSR_F64, double>(P, T, K, nwg, st);
-        if (vdt == RGCSR_F32) return launch_spmv_vk<RGCSR_F32, double>(P, T, K, nwg, st);
+        if (vdt == RGCSR_F64) return launch_spmv_vk<RGCSR_F64, double>(P, T, K, R, nwg, st);
+        if (vdt == RGCSR_F32) return launch_spmv_vk<RGCSR_F32, double>(P, T, K, R, nwg, st);
     } else {
-        if (vdt == RGCSR_F32) return launch_spmv_vk<RGCSR_F32, float>(P, T, K, nwg, st);
-        if (K == 1 && vdt == RGCSR_F16) return launch_spmv_k<RGCSR_F16, float, 1>(P, T, nwg, st);
-        if (K == 1 && vdt == RGCSR_BF16) return launch_spmv_k<RGCSR_BF16, float, 1>(P, T, nwg, st);
+        if (vdt == RGCSR_F32) return launch_spmv_vk<RGCSR_F32, float>(P, T, K, R, nwg, st);
+        if (K == 1 && vdt == RGCSR_F16) return launch_spmv_vk<RGCSR_F16, float>(P, T, 1, R, nwg, st);
+        if (K == 1 && vdt == RGCSR_BF16) return launch_spmv_vk<RGCSR_BF16, float>(P, T, 1, R, nwg, st);
     }
     return hipErrorInvalidValue;
 }
