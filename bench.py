@@ -34,7 +34,7 @@ ROTATE_BYTES = 1 << 30
 
 # layouts timed by the benchmark (also used by the full-size parity test)
 LAYOUT_STENCIL = dict(G=64, T=1, sigma=1, tau=-1)          # the paper's layout
-LAYOUT_ZIPF = dict(G=64, T=1, sigma=1 << 40, tau=16)       # descending order + long-row path
+LAYOUT_ZIPF = dict(G=64, T=1, sigma=512, tau=32, rows_per_lane=4)  # descending order in windows + long-row path
 
 METRIC = "SpMV GFLOP/s and achieved HBM GB/s (% of peak), RgCSR vs Hybrid, 1 MI355X"
 
@@ -159,6 +159,186 @@ def check_outputs(cases, torch):
     return out
 
 
+# ----------------------------------------------------------------------------
+# Other forms of the hot path (one JSON line each; not the contract line)
+# ----------------------------------------------------------------------------
+def _events(torch, fn, reps):
+    torch.cuda.synchronize()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(reps + 1)]
+    ev[0].record()
+    for i in range(reps):
+        fn(i)
+        ev[i + 1].record()
+    torch.cuda.synchronize()
+    return [ev[i].elapsed_time(ev[i + 1]) for i in range(reps)]
+
+
+def bench_spmm(args, torch, rg, W):
+    """Multi-RHS SpMM on the Zipf matrix, k in {1, 4, 16, 32}, one launch per k,
+    against k sequential single-vector SpMVs."""
+    import oracle
+    A, _ = W.workload_zipf(1_000_000)
+    base = rg.rgcsr_from_csr(A, **LAYOUT_ZIPF)
+    out = {"metric": "SpMM GFLOP/s and GB/s, Zipf n=1e6, FP32", "results": []}
+    for k in (1, 4, 16, 32):
+        X0 = torch.from_numpy(W.uniform_matrix(A.n_cols, k, W.SEEDS["spmm_X"])).to("cuda:0")
+        per = base.info["device_bytes"] + 4 * k * (A.n_rows + A.n_cols)
+        copies = max(1, math.ceil(ROTATE_BYTES / per))
+        mats = [base] + [base.clone() for _ in range(copies - 1)]
+        Xs = [X0.clone() for _ in range(copies)]
+        Ys = [torch.empty((A.n_rows, k), device="cuda:0") for _ in range(copies)]
+        for i in range(args.warmup):
+            rg.rgcsr_spmv_batched(mats[i % copies], Xs[i % copies], Ys[i % copies])
+        t = _events(torch, lambda i: rg.rgcsr_spmv_batched(mats[i % copies], Xs[i % copies], Ys[i % copies]),
+                    args.steps)
+        ms = float(np.mean(t))
+        xcols = [X0[:, c].contiguous() for c in range(k)]
+        ycol = torch.empty(A.n_rows, device="cuda:0")
+        t1 = _events(torch, lambda i: [rg.rgcsr_spmv(mats[i % copies], xcols[c], ycol) for c in range(k)],
+                     max(10, args.steps // 4))
+        Y = Ys[0]
+        rg.rgcsr_spmv_batched(mats[0], Xs[0], Y)
+        torch.cuda.synchronize()
+        Xh = X0.cpu().numpy()
+        ref = oracle.csr_spmm(A, Xh)
+        err = max(oracle.scaled_error(Y[:, c].cpu().numpy(), ref[:, c], oracle.csr_absmv(A, Xh[:, c]))
+                  for c in range(k))
+        b = alg_bytes(A.nnz, A.n_rows, A.n_cols, base.info["n_groups"], k=k)
+        out["results"].append({"k": k, "us": ms * 1e3, "gflops": 2 * A.nnz * k / (ms * 1e-3) / 1e9,
+                               "gbs": b / (ms * 1e-3) / 1e9, "alg_bytes": b,
+                               "k_sequential_spmv_us": float(np.mean(t1)) * 1e3, "max_scaled_error": err,
+                               "copies_rotated": copies})
+        for m in mats[1:]:
+            m.close()
+    print(json.dumps(out), flush=True)
+
+
+def bench_batched(args, torch, rg, W):
+    """4,096 independent banded matrices in one handle, one launch (persistent
+    and one-wavefront-per-item), aggregate GB/s, per-matrix error on a sample."""
+    import oracle
+    t0 = time.time()
+    mats = W.batched_set(count=args.batch_count, seed=W.SEEDS["batched"])
+    gen_s = time.time() - t0
+    t0 = time.time()
+    B = rg.rgcsr_from_csr_batch(mats, G=64)
+    build_s = time.time() - t0
+    ro, co = B.batch_offsets()
+    xh = W.uniform_vector(int(co[-1]), 41, np.float32)
+    x = torch.from_numpy(xh).to("cuda:0")
+    y = torch.empty(int(ro[-1]), device="cuda:0")
+    nnz = sum(M.nnz for M in mats)
+    b = sum(alg_bytes(M.nnz, M.n_rows, M.n_cols, (M.n_rows + 63) // 64) for M in mats)
+    res = {}
+    for persistent in (False, True):
+        X, Y = x.view(-1, 1), y.view(-1, 1)
+        for _ in range(args.warmup):
+            rg.rgcsr_spmv_batched(B, X, Y, persistent)
+        t = _events(torch, lambda i: rg.rgcsr_spmv_batched(B, X, Y, persistent), args.steps)
+        ms = float(np.mean(t))
+        res["persistent" if persistent else "per_item"] = {"us": ms * 1e3, "gbs": b / (ms * 1e-3) / 1e9,
+                                                          "gflops": 2 * nnz / (ms * 1e-3) / 1e9}
+    yh = y.cpu().numpy()
+    rng = np.random.default_rng(0)
+    errs = []
+    for i in rng.choice(len(mats), min(64, len(mats)), replace=False):
+        M = mats[i]
+        xi = xh[co[i]:co[i + 1]]
+        errs.append(oracle.scaled_error(yh[ro[i]:ro[i + 1]], oracle.csr_spmv(M, xi), oracle.csr_absmv(M, xi)))
+    print(json.dumps({"metric": "batched SpMV GB/s, one launch", "matrices": len(mats), "rows": int(ro[-1]),
+                      "nnz": nnz, "alg_bytes": b, "results": res, "max_scaled_error_64_sampled": max(errs),
+                      "generate_s": gen_s, "build_s": build_s, "working_set_note":
+                      "3 GB working set, larger than the 256 MB cache: no rotation needed"}), flush=True)
+
+
+def bench_cg(args, torch, rg, W):
+    """Mixed-precision CG on the 27-point stencil (FP32/BF16/FP16 stored values,
+    FP32 inner CG, FP64 refinement) against all-FP64 CG on the same GPU."""
+    import oracle
+    N = args.cg_n
+    A = W.stencil_3d_27pt(N, dtype=np.float32)
+    b64 = oracle.csr_spmv(A, np.ones(A.n_cols))
+    bd = torch.from_numpy(b64).to("cuda:0")
+    Ahi = rg.rgcsr_from_csr(A, value_dtype="f32")
+    out = {"metric": "mixed-precision CG to relres 1e-10, 27-point stencil", "n": A.n_rows, "nnz": A.nnz,
+           "results": []}
+    A64 = rg.rgcsr_from_csr(A, value_dtype="f64")
+    for dt in ("f32", "bf16", "f16", "fp64-cg"):
+        Alo = Ahi if dt == "f32" else (A64 if dt == "fp64-cg" else rg.rgcsr_from_csr(A, value_dtype=dt))
+        x = torch.zeros(A.n_rows, dtype=torch.float64, device="cuda:0")
+        if dt == "fp64-cg":
+            st = rg.rgcsr_cg_solve_f64(A64, bd, x, tol=1e-10, max_iter=2000)
+        else:
+            st = rg.rgcsr_cg_solve(Alo, Ahi, bd, x, tol=1e-10, inner_tol=1e-4)
+        xh = x.cpu().numpy()
+        r = b64 - oracle.csr_spmv(A, xh)
+        rel = float(np.sqrt(np.dot(r, r)) / np.sqrt(np.dot(b64, b64)))
+        # one inner SpMV of this storage type
+        vec = torch.float64 if dt == "fp64-cg" else torch.float32
+        xv = torch.rand(A.n_cols, dtype=vec, device="cuda:0")
+        yv = torch.empty(A.n_rows, dtype=vec, device="cuda:0")
+        for _ in range(3):
+            rg.rgcsr_spmv(Alo, xv, yv)
+        t = _events(torch, lambda i: rg.rgcsr_spmv(Alo, xv, yv), 20)
+        s_v = {"f32": 4, "bf16": 2, "f16": 2, "fp64-cg": 8}[dt]
+        s_x = 8 if dt == "fp64-cg" else 4
+        bb = alg_bytes(A.nnz, A.n_rows, A.n_cols, Alo.info["n_groups"], s_v=s_v, s_x=s_x, s_y=s_x)
+        us = float(np.mean(t)) * 1e3
+        out["results"].append({"storage": dt, **st, "oracle_relres": rel,
+                               "max_abs_x_minus_1": float(np.max(np.abs(xh - 1.0))),
+                               "spmv_us": us, "spmv_gbs": bb / us / 1e3})
+    print(json.dumps(out), flush=True)
+
+
+def bench_grad(args, torch, rg, W):
+    """Forward + hand-written backward on the Zipf matrix (loss 1/2||A(theta)x-b||^2),
+    transposed-RgCSR and atomic dx, checked against the FP64 oracle and
+    central differences on 64 sampled entries."""
+    import oracle
+    A, _ = W.workload_zipf(1_000_000)
+    x = W.normal_vector(A.n_cols, W.SEEDS["grad_x"], np.float32)
+    bvec = W.normal_vector(A.n_rows, W.SEEDS["grad_b"], np.float32)
+    xd, bd = torch.from_numpy(x).to("cuda:0"), torch.from_numpy(bvec).to("cuda:0")
+    theta = torch.from_numpy(A.val).to("cuda:0")
+    r, dx_ref, dv_ref, L = oracle.adjoint(A, x, bvec)
+    out = {"metric": "SpMV forward + backward, Zipf n=1e6, FP32", "results": []}
+    for transpose in (True, False):
+        M = rg.rgcsr_from_csr(A, keep_csr_map=True, build_transpose=transpose, **LAYOUT_ZIPF)
+        y = torch.empty(A.n_rows, device="cuda:0")
+        dx = torch.empty(A.n_cols, device="cuda:0")
+        dv = torch.empty(A.nnz, device="cuda:0")
+
+        def step(i):
+            rg.rgcsr_set_values(M, theta)
+            rg.rgcsr_spmv(M, xd, y)
+            torch.sub(y, bd, out=y)
+            rg.rgcsr_spmv_transpose_grad(M, xd, y, dx, dv)
+        for i in range(args.warmup):
+            step(i)
+        t = _events(torch, step, args.steps)
+        fw = _events(torch, lambda i: rg.rgcsr_spmv(M, xd, y), args.steps)
+        s = oracle.csr_absmv(A, x)
+        st = float(np.max(s + np.abs(bvec))) * float(np.max(np.abs(x)))
+        out["results"].append({"dx": "transposed" if transpose else "atomic",
+                               "step_us": float(np.mean(t)) * 1e3, "forward_spmv_us": float(np.mean(fw)) * 1e3,
+                               "dtheta_err_scaled": float(np.max(np.abs(dv.cpu().numpy() - dv_ref))) / st,
+                               "dx_err_abs": float(np.max(np.abs(dx.cpu().numpy() - dx_ref)))})
+        M.close()
+    rng = np.random.default_rng(W.SEEDS["grad_samples"])
+    h = 1e-3
+    A64 = A.astype(np.float64)
+    worst = 0.0
+    for k in rng.choice(A.nnz, 64, replace=False):
+        tp, tm = A64.val.copy(), A64.val.copy()
+        tp[k] += h
+        tm[k] -= h
+        fd = (oracle.loss(W.CSR(A.n_rows, A.n_cols, A.row_ptr, A.col, tp), x, bvec)
+              - oracle.loss(W.CSR(A.n_rows, A.n_cols, A.row_ptr, A.col, tm), x, bvec)) / (2 * h)
+        worst = max(worst, abs(fd - dv_ref[k]) / max(1.0, abs(dv_ref[k])))
+    out["oracle_vs_central_difference_max_rel"] = worst
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -168,6 +348,10 @@ def main():
     ap.add_argument("--no-check", action="store_true", help="skip the oracle check of the outputs")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a 1 GiB device copy (for scaling the HBM byte counters)")
+    ap.add_argument("--config", default="spmv", choices=["spmv", "spmm", "batched", "cg", "grad"],
+                    help="spmv (default, the contract line) or another form of the path")
+    ap.add_argument("--batch-count", type=int, default=4096)
+    ap.add_argument("--cg-n", type=int, default=160)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print(json.dumps({"error": "this benchmark measures one GPU only; the single-matrix SpMV "
@@ -192,6 +376,10 @@ def main():
         return
 
     rg._lib.load()
+    if args.config != "spmv":
+        {"spmm": bench_spmm, "batched": bench_batched, "cg": bench_cg, "grad": bench_grad}[args.config](
+            args, torch, rg, W)
+        return
     log("generating matrices ...")
     A1, x1 = W.workload_laplace3d(128)
     A2, x2 = W.workload_zipf(1_000_000)

@@ -227,8 +227,7 @@ __device__ __forceinline__ void spmv_groups_uniform(const SpmvParams &P, int32_t
     const uint32_t xrow = (uint32_t)(P.ldx * (int64_t)sizeof(A));
     const S *vb[R];
     const int32_t *cb[R];
-    int32_t off0[R], stride[R], nl[R], len[R];
-    int64_t rowi[R];
+    int32_t off0[R], stride[R], nl[R], len[R], rowi[R];
     bool ok[R];
     int q = 0;
     int cmax = 0;
@@ -241,7 +240,7 @@ __device__ __forceinline__ void spmv_groups_uniform(const SpmvParams &P, int32_t
         const int t = lr / T;
         q = lr % T;
         ok[r] = t < m.sg;
-        rowi[r] = m.row0 + t;
+        rowi[r] = (int32_t)m.row0 + t;
         // unconditional load at a clamped index (no branch around it)
         len[r] = P.short_len[ok[r] ? rowi[r] : 0];
         stride[r] = m.sg * T;
@@ -388,31 +387,34 @@ __device__ __forceinline__ void spmv_short(const SpmvParams &P, int32_t w, int l
     }
 }
 
-// Elements beg + q, beg + q + stride, ... < end of one lane, three-phase.
+// Elements o, o + stride, ... < e of one lane, where offsets are 32-bit and
+// relative to uniform bases vb/cb (scalar base + vector offset addressing).
+// Branch-free unrolled body as in the row groups: out-of-range steps re-read
+// the lane's first element (valid whenever the loop runs) and are masked.
 template <int VD, class A, int K, int U>
-__device__ __forceinline__ void strided_dot(const SpmvParams &P, int64_t beg, int64_t end, int64_t stride,
-                                            A (&acc)[K]) {
+__device__ __forceinline__ void strided_dot32(const typename Val<VD>::S *vb, const int32_t *cb, const A *X,
+                                              int64_t ldx, uint32_t xrow, int32_t o, int32_t e, int32_t stride,
+                                              A (&acc)[K]) {
     using V = Val<VD>;
     using S = typename V::S;
-    const S *vals = (const S *)P.long_val;
-    const A *X = (const A *)P.x;
-    // branch-free body as in the row groups: out-of-range steps re-read the
-    // lane's first element (valid whenever the loop runs) and are masked
-    for (int64_t e0 = beg; e0 < end; e0 += stride * U) {
+    for (int32_t o0 = o; o0 < e; o0 += stride * U) {
         S v[U];
         int32_t ci[U];
         A xv[U][K];
 #pragma unroll
         for (int u = 0; u < U; u++) {
-            const int64_t e = e0 + u * stride < end ? e0 + u * stride : beg;
-            v[u] = ldnt(vals + e);
-            ci[u] = ldnt(P.long_col + e);
+            const uint32_t oo = (uint32_t)(o0 + u * stride < e ? o0 + u * stride : o);
+            v[u] = ldnt((const S *)((const char *)vb + oo * (uint32_t)sizeof(S)));
+            ci[u] = ldnt((const int32_t *)((const char *)cb + oo * 4u));
         }
 #pragma unroll
-        for (int u = 0; u < U; u++) load_row<A, K>(X + (int64_t)ci[u] * P.ldx, xv[u]);
+        for (int u = 0; u < U; u++) {
+            if constexpr (K == 1) xv[u][0] = ldx32(X, ci[u], xrow);
+            else load_row<A, K>(X + (int64_t)ci[u] * ldx, xv[u]);
+        }
 #pragma unroll
         for (int u = 0; u < U; u++) {
-            const bool on = e0 + u * stride < end;
+            const bool on = o0 + u * stride < e;
             const A a = V::template cvt<A>(v[u]);
 #pragma unroll
             for (int k = 0; k < K; k++) {
@@ -423,21 +425,29 @@ __device__ __forceinline__ void strided_dot(const SpmvParams &P, int64_t beg, in
     }
 }
 
-// Long rows of at most kWaveRowMax nonzeros: it.b rows with it.c lanes each.
+// Long rows of at most kWaveRowMax nonzeros: it.b consecutive rows of the
+// long list with it.c lanes each.  Their nonzeros are contiguous, so offsets
+// are taken from the item's first nonzero (a scalar load).
 template <int VD, class A, int K>
 __device__ __forceinline__ void spmv_wave_long(const SpmvParams &P, int32_t w, int lane) {
+    using S = typename Val<VD>::S;
     A *Y = (A *)P.y;
+    const A *X = (const A *)P.x;
     const LongItem it = ldc(P.wave_work, w);
     const int TL = it.c;
     const int sh = 31 - __builtin_clz(TL);
     const int r = lane >> sh, q = lane & (TL - 1);
     const bool ok = r < it.b;
-    const int64_t li = (int64_t)it.a + r;
-    const int64_t beg = ok ? P.long_ptr[li] : 0, end = ok ? P.long_ptr[li + 1] : 0;
+    const int64_t item0 = ldc(P.long_ptr, (int64_t)it.a);
+    const int64_t li = (int64_t)it.a + (ok ? r : 0);
+    const int32_t b = (int32_t)(P.long_ptr[li] - item0), e = ok ? (int32_t)(P.long_ptr[li + 1] - item0) : 0;
+    const S *vb = (const S *)P.long_val + item0;
+    const int32_t *cb = P.long_col + item0;
     A acc[K];
 #pragma unroll
     for (int k = 0; k < K; k++) acc[k] = A(0);
-    strided_dot<VD, A, K, (K == 1 ? kWaveUnroll : unroll_for<K>())>(P, beg + q, end, TL, acc);
+    constexpr int U = K == 1 ? kWaveUnroll : unroll_for<K>();
+    strided_dot32<VD, A, K, U>(vb, cb, X, P.ldx, (uint32_t)(P.ldx * (int64_t)sizeof(A)), b + q, e, TL, acc);
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1)
         if (off < TL)
@@ -446,18 +456,23 @@ __device__ __forceinline__ void spmv_wave_long(const SpmvParams &P, int32_t w, i
     if (ok && q == 0) store_row<A, K>(Y + (int64_t)P.long_row[li] * P.ldy, acc);
 }
 
-// One chunk of a very long row, reduced by the whole workgroup in LDS.
+// One chunk (at most kBlockChunk nonzeros) of a very long row, reduced by the
+// whole workgroup in LDS.
 template <int VD, class A, int K>
 __device__ __forceinline__ void spmv_block_item(const SpmvParams &P, int32_t u, A (*red)[K]) {
+    using S = typename Val<VD>::S;
     A *Y = (A *)P.y;
+    const A *X = (const A *)P.x;
     const LongItem it = ldc(P.block_work, u);
     const int64_t li = it.a;
     const int64_t beg = ldc(P.long_ptr, li) + (int64_t)it.b * kBlockChunk;
-    const int64_t end = min(ldc(P.long_ptr, li + 1), beg + kBlockChunk);
+    const int32_t n = (int32_t)min(ldc(P.long_ptr, li + 1) - beg, kBlockChunk);
     A acc[K];
 #pragma unroll
     for (int k = 0; k < K; k++) acc[k] = A(0);
-    strided_dot<VD, A, K, (K == 1 ? 16 : unroll_for<K>())>(P, beg + threadIdx.x, end, kBlockThreads, acc);
+    constexpr int U = K == 1 ? 16 : unroll_for<K>();
+    strided_dot32<VD, A, K, U>((const S *)P.long_val + beg, P.long_col + beg, X, P.ldx,
+                               (uint32_t)(P.ldx * (int64_t)sizeof(A)), (int32_t)threadIdx.x, n, kBlockThreads, acc);
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1)
 #pragma unroll
@@ -472,7 +487,7 @@ __device__ __forceinline__ void spmv_block_item(const SpmvParams &P, int32_t u, 
         A tot = A(0);
         for (int i = 0; i < kBlockWaves; i++) tot += red[i][k];
         if (it.c == 1)
-            Y[(int64_t)P.long_row[li] * P.ldy + k] = tot;
+            Y[(int64_t)ldc(P.long_row, li) * P.ldy + k] = tot;
         else
             ((A *)P.partial)[((int64_t)it.d + it.b) * K + k] = tot;
     }

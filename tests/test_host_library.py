@@ -120,7 +120,7 @@ def test_layout_sizes_match_oracle(lib, oracle):
 
 
 def test_long_work_items_cover_long_rows(lib):
-    """Rows longer than 512 go to whole-workgroup items of 16384 nonzeros; a
+    """Rows longer than 1024 go to whole-workgroup items of 16384 nonzeros; a
     row needing several items gets one partial-sum slot per item."""
     A = W.zipf_matrix(50_000, seed=2)
     extra = W.random_csr(20, 50_000, seed=3, max_len=5, long_rows=3, long_len=40_000)
@@ -129,7 +129,7 @@ def test_long_work_items_cover_long_rows(lib):
             info = rg.rgcsr_layout_sizes(M, rg.make_opts(G=64, sigma=M.n_rows, tau=tau))
             lens = np.diff(M.row_ptr)
             lens = lens[lens > tau]
-            nch = (lens[lens > 512] + 16383) // 16384
+            nch = (lens[lens > 1024] + 16383) // 16384
             assert info["partials"] == int(nch[nch > 1].sum())
             assert info["long_nnz"] == int(lens.sum())
 
