@@ -91,7 +91,8 @@ typedef struct {
     int32_t pad_loads;      /* kernel schedule: 1 = value/column loads run over the
                                group width so they need not wait for the row length
                                (padding is still never multiplied), 0 = loads stop at
-                               the row length, -1 = on when padding is at most 25% */
+                               the row length, -1 = on when padding is at most 100% of the
+                               grouped nonzeros */
 } rgcsr_opts;
 
 /* Fills *opts with the paper's layout: G = 64, T = 1, sigma = 1, no long
@@ -235,6 +236,24 @@ rgcsr_status rgcsr_clone(rgcsr_handle A, void *stream, rgcsr_handle *out);
 /* Frees the device arrays and the handle (synchronises the device first).
  * NULL is accepted. */
 rgcsr_status rgcsr_destroy(rgcsr_handle A);
+
+/* rgcsr_autotune: choose layout and kernel schedule for one host CSR matrix
+ * by timing candidates on the current device (the paper sweeps the group
+ * size by hand, Table 4).  Candidates: the paper layout with automatic and
+ * explicit rows-per-lane schedules, and long-row thresholds in {16, 32, 64,
+ * 256} (below the longest row) combined with sort windows {1, 512, 4096, n},
+ * skipping windows that do not cut padding; at most max_candidates are built
+ * and each timed over `reps` launches of y = A x (x: device, n_cols entries
+ * of vec_dtype; y: device scratch of n_rows).  Other fields of *base (value
+ * dtype, CSR map, transpose, validation) are kept.  Writes the fastest
+ * options to *best; when cands/times_us are not NULL they receive every
+ * candidate timed (max_candidates entries of room) and its mean launch time
+ * in microseconds, *n_tried their count.  Synchronises the stream. */
+rgcsr_status rgcsr_autotune(int64_t n_rows, int64_t n_cols, int64_t nnz, const int64_t *row_ptr,
+                            const int32_t *col_idx, const void *vals, rgcsr_dtype vals_dtype,
+                            const rgcsr_opts *base, const void *x, void *y, rgcsr_dtype vec_dtype,
+                            int32_t max_candidates, int32_t reps, rgcsr_opts *cands, double *times_us,
+                            int32_t *n_tried, rgcsr_opts *best, void *stream);
 
 /* ---- Hybrid ELL + COO (Section 3.3) --------------------------------------- */
 

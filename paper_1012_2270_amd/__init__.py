@@ -388,6 +388,66 @@ def rgcsr_cg_solve_f64(A: RgCSRMatrix, b, x, tol: float = 1e-10, max_iter: int =
     return st.as_dict()
 
 
+def opts_dict(o: _lib.Opts) -> dict:
+    return {f: getattr(o, f) for f, _ in _lib.Opts._fields_}
+
+
+def opts_from_dict(d: dict) -> _lib.Opts:
+    o = _lib.Opts()
+    for f, _ in _lib.Opts._fields_:
+        setattr(o, f, int(d[f]))
+    return o
+
+
+def matrix_fingerprint(A) -> str:
+    """Stable key of a matrix's sparsity pattern (sizes and a hash of the row
+    pointers and a strided sample of the column indices)."""
+    import hashlib
+    h = hashlib.sha256()
+    h.update(np.array([A.n_rows, A.n_cols, A.nnz], np.int64).tobytes())
+    h.update(np.ascontiguousarray(A.row_ptr, np.int64).tobytes())
+    step = max(1, A.nnz // 65536)
+    h.update(np.ascontiguousarray(np.asarray(A.col)[::step], np.int32).tobytes())
+    return h.hexdigest()[:24]
+
+
+def rgcsr_autotune(A, x, y, base: _lib.Opts | None = None, max_candidates: int = 16, reps: int = 20,
+                   cache_path: str | None = None, stream=None) -> tuple[_lib.Opts, list]:
+    """Pick layout and schedule for A by timing candidates on the device
+    (native search in librgcsr).  Results are cached in a JSON file keyed by
+    the matrix fingerprint and the value dtype (cache_path, default
+    $RGCSR_AUTOTUNE_CACHE if set, else no cache)."""
+    import json
+    import os
+    base = base if base is not None else make_opts()
+    path = cache_path or os.environ.get("RGCSR_AUTOTUNE_CACHE")
+    key = f"{matrix_fingerprint(A)}:{base.value_dtype}:{_code_of_tensor(x)}"
+    cache = {}
+    if path and os.path.exists(path):
+        with open(path) as f:
+            cache = json.load(f)
+        if key in cache:
+            return opts_from_dict(cache[key]["best"]), cache[key]["tried"]
+    _dev_check(x, "x")
+    _dev_check(y, "y")
+    rp, col, val = _csr_arrays(A)
+    cands = (_lib.Opts * max_candidates)()
+    times = np.zeros(max_candidates, np.float64)
+    n = ctypes.c_int32(0)
+    best = _lib.Opts()
+    _lib.call("rgcsr_autotune", A.n_rows, A.n_cols, int(rp[-1]), _ptr(rp), _ptr(col), _ptr(val),
+              _code_of_numpy(val), ctypes.byref(base), _ptr(x), _ptr(y), _code_of_tensor(x), max_candidates,
+              reps, ctypes.addressof(cands), _ptr(times), ctypes.byref(n), ctypes.byref(best), _stream(stream))
+    tried = [{"opts": opts_dict(cands[i]), "us": float(times[i])} for i in range(n.value)]
+    if path:
+        cache[key] = {"best": opts_dict(best), "tried": tried}
+        tmp = path + ".tmp"
+        with open(tmp, "w") as f:
+            json.dump(cache, f, indent=1)
+        os.replace(tmp, path)
+    return best, tried
+
+
 def version() -> str:
     return _lib.load().rgcsr_version().decode()
 

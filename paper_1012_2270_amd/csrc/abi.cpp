@@ -200,12 +200,13 @@ void build_host(Built &B, const LayoutParams &p, int vdt, int32_t count, const i
 }
 
 // Kernel schedule: rows per lane from the mean group width (about 16 steps
-// in flight per lane), padded-width loads when padding is at most 25%.
+// in flight per lane), padded-width loads when padding is at most the
+// number of grouped nonzeros.
 void choose_schedule(rgcsr_matrix_s *h, const HostLayout &L, int32_t rows_per_lane, int32_t pad_loads) {
     int64_t short_nnz = 0;
     for (int32_t v : L.short_len) short_nnz += v;
     const int64_t pad_slots = L.slots - short_nnz;
-    if (pad_loads < 0) h->pad = pad_slots * 4 <= short_nnz ? 1 : 0;
+    if (pad_loads < 0) h->pad = pad_slots <= short_nnz ? 1 : 0;
     else h->pad = pad_loads ? 1 : 0;
     int32_t R = rows_per_lane;
     if (R == 0) {

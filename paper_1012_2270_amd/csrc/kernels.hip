@@ -227,7 +227,7 @@ __device__ __forceinline__ void spmv_groups_uniform(const SpmvParams &P, int32_t
     const uint32_t xrow = (uint32_t)(P.ldx * (int64_t)sizeof(A));
     const S *vb[R];
     const int32_t *cb[R];
-    int32_t off0[R], stride[R], nl[R], len[R], rowi[R];
+    int32_t off0[R], stride[R], nl[R], len[R], rowi[R], orow[R];
     bool ok[R];
     int q = 0;
     int cmax = 0;
@@ -241,8 +241,10 @@ __device__ __forceinline__ void spmv_groups_uniform(const SpmvParams &P, int32_t
         q = lr % T;
         ok[r] = t < m.sg;
         rowi[r] = (int32_t)m.row0 + t;
-        // unconditional load at a clamped index (no branch around it)
+        // unconditional loads at a clamped index (no branch around them);
+        // the output row is fetched now so the final store does not wait
         len[r] = P.short_len[ok[r] ? rowi[r] : 0];
+        orow[r] = P.perm ? P.short_row[ok[r] ? rowi[r] : 0] : rowi[r];
         stride[r] = m.sg * T;
         const bool has = m.g1 > m.g0;
         // a group without slots points at slot 0 (read only when the loop runs)
@@ -320,10 +322,7 @@ __device__ __forceinline__ void spmv_groups_uniform(const SpmvParams &P, int32_t
 #pragma unroll
                 for (int k = 0; k < K; k++) acc[r][k] += __shfl_xor(acc[r][k], off);
         }
-        if (ok[r] && q == 0) {
-            const int64_t row = P.perm ? (int64_t)P.short_row[rowi[r]] : rowi[r];
-            store_row<A, K>(Y + row * P.ldy, acc[r]);
-        }
+        if (ok[r] && q == 0) store_row<A, K>(Y + (int64_t)orow[r] * P.ldy, acc[r]);
     }
 }
 
@@ -441,6 +440,7 @@ __device__ __forceinline__ void spmv_wave_long(const SpmvParams &P, int32_t w, i
     const int64_t item0 = ldc(P.long_ptr, (int64_t)it.a);
     const int64_t li = (int64_t)it.a + (ok ? r : 0);
     const int32_t b = (int32_t)(P.long_ptr[li] - item0), e = ok ? (int32_t)(P.long_ptr[li + 1] - item0) : 0;
+    const int32_t orow = P.long_row[li];  // fetched early, stored at the end
     const S *vb = (const S *)P.long_val + item0;
     const int32_t *cb = P.long_col + item0;
     A acc[K];
@@ -453,7 +453,7 @@ __device__ __forceinline__ void spmv_wave_long(const SpmvParams &P, int32_t w, i
         if (off < TL)
 #pragma unroll
             for (int k = 0; k < K; k++) acc[k] += __shfl_xor(acc[k], off);
-    if (ok && q == 0) store_row<A, K>(Y + (int64_t)P.long_row[li] * P.ldy, acc);
+    if (ok && q == 0) store_row<A, K>(Y + (int64_t)orow * P.ldy, acc);
 }
 
 // One chunk (at most kBlockChunk nonzeros) of a very long row, reduced by the

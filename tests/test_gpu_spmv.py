@@ -222,3 +222,20 @@ def test_full_size_laplace3d_and_zipf(torch_cuda, oracle):
         e = check_spmv(oracle, A, x, y, tol=TOL_F32)
         say("  scaled error", e)
         M.close()
+
+
+def test_autotune_picks_a_timed_candidate_and_caches(torch_cuda, oracle, tmp_path):
+    torch = torch_cuda
+    A = W.zipf_matrix(60_000, seed=8)
+    x = dev(W.uniform_vector(A.n_cols, 17, np.float32))
+    y = torch.empty(A.n_rows, device="cuda:0")
+    cache = str(tmp_path / "tune.json")
+    say("autotune")
+    best, tried = rg.rgcsr_autotune(A, x, y, max_candidates=8, reps=3, cache_path=cache)
+    assert 2 <= len(tried) <= 8
+    assert all(t["us"] > 0 for t in tried)
+    assert min(t["us"] for t in tried) == [t["us"] for t in tried if t["opts"] == rg.opts_dict(best)][0]
+    M = rg.rgcsr_from_csr(A, opts=best)
+    check_spmv(oracle, A, host(x), host(M.spmv(x)))
+    best2, tried2 = rg.rgcsr_autotune(A, x, y, cache_path=cache)   # served from the cache
+    assert rg.opts_dict(best2) == rg.opts_dict(best) and tried2 == tried
