@@ -339,6 +339,43 @@ def bench_grad(args, torch, rg, W):
     print(json.dumps(out), flush=True)
 
 
+def bench_fp64(args, torch, rg, W):
+    """The benchmark matrices in double precision (values, vectors and
+    accumulation), RgCSR vs Hybrid; the paper reports double throughout."""
+    import oracle
+    out = {"metric": "SpMV GFLOP/s and GB/s, FP64", "results": []}
+    A1, _ = W.workload_laplace3d(128)
+    A2, _ = W.workload_zipf(1_000_000)
+    for name, A, lay in (("laplace3d_7pt_128", A1, LAYOUT_STENCIL), ("zipf2_1e6", A2, LAYOUT_ZIPF)):
+        A64 = A.astype(np.float64)
+        x = W.uniform_vector(A.n_cols, 77, np.float64)
+        base = rg.rgcsr_from_csr(A64, value_dtype="f64", **lay)
+        hyb = rg.hyb_from_csr(A64, value_dtype="f64")
+        per = base.info["device_bytes"] + 8 * (A.n_rows + A.n_cols)
+        copies = max(1, math.ceil(ROTATE_BYTES / per))
+        mats = [base] + [base.clone() for _ in range(copies - 1)]
+        hybs = [hyb] + [hyb.clone() for _ in range(copies - 1)]
+        xs = [torch.from_numpy(x).to("cuda:0") for _ in range(copies)]
+        ys = [torch.empty(A.n_rows, dtype=torch.float64, device="cuda:0") for _ in range(copies)]
+        for i in range(args.warmup):
+            rg.rgcsr_spmv(mats[i % copies], xs[i % copies], ys[i % copies])
+        t = float(np.mean(_events(torch, lambda i: rg.rgcsr_spmv(mats[i % copies], xs[i % copies], ys[i % copies]),
+                                  args.steps)))
+        th = float(np.mean(_events(torch, lambda i: rg.hyb_spmv(hybs[i % copies], xs[i % copies], ys[i % copies]),
+                                   args.steps)))
+        rg.rgcsr_spmv(mats[0], xs[0], ys[0])
+        err = oracle.scaled_error(ys[0].cpu().numpy(), oracle.csr_spmv(A64, x), oracle.csr_absmv(A64, x))
+        b = alg_bytes(A.nnz, A.n_rows, A.n_cols, base.info["n_groups"], s_v=8, s_x=8, s_y=8)
+        out["results"].append({"matrix": name, "rgcsr_us": t * 1e3, "hybrid_us": th * 1e3,
+                               "rgcsr_gflops": 2 * A.nnz / (t * 1e-3) / 1e9, "rgcsr_gbs": b / (t * 1e-3) / 1e9,
+                               "rgcsr_hbm_frac": b / (t * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                               "hybrid_gflops": 2 * A.nnz / (th * 1e-3) / 1e9, "alg_bytes": b,
+                               "max_scaled_error": err, "copies_rotated": copies})
+        for m in mats[1:] + hybs[1:]:
+            m.close()
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -348,7 +385,7 @@ def main():
     ap.add_argument("--no-check", action="store_true", help="skip the oracle check of the outputs")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a 1 GiB device copy (for scaling the HBM byte counters)")
-    ap.add_argument("--config", default="spmv", choices=["spmv", "spmm", "batched", "cg", "grad"],
+    ap.add_argument("--config", default="spmv", choices=["spmv", "spmm", "batched", "cg", "grad", "fp64"],
                     help="spmv (default, the contract line) or another form of the path")
     ap.add_argument("--batch-count", type=int, default=4096)
     ap.add_argument("--cg-n", type=int, default=160)
@@ -377,7 +414,8 @@ def main():
 
     rg._lib.load()
     if args.config != "spmv":
-        {"spmm": bench_spmm, "batched": bench_batched, "cg": bench_cg, "grad": bench_grad}[args.config](
+        {"spmm": bench_spmm, "batched": bench_batched, "cg": bench_cg, "grad": bench_grad,
+         "fp64": bench_fp64}[args.config](
             args, torch, rg, W)
         return
     log("generating matrices ...")

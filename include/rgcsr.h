@@ -175,7 +175,9 @@ rgcsr_status rgcsr_batch_offsets(rgcsr_handle A, int64_t *row_off, int64_t *col_
 
 /* rgcsr_spmv: y = A x (Section 3.4 kernel semantics: every row is
  * overwritten, empty rows give 0).  x[n_cols], y[n_rows] are device pointers
- * of vec_dtype (F32 or F64); x and y must not overlap.  One kernel launch. */
+ * of vec_dtype (F32 or F64); x and y must not overlap.  One kernel launch,
+ * plus a second small one that adds chunk partial sums in a fixed order when
+ * some row has more than 16,384 nonzeros (deterministic results). */
 rgcsr_status rgcsr_spmv(rgcsr_handle A, const void *x, void *y, rgcsr_dtype vec_dtype,
                         void *stream);
 
