@@ -86,8 +86,10 @@ typedef struct {
     int32_t build_transpose;
     int32_t validate;
     int32_t rows_per_lane;  /* kernel schedule: rows each lane multiplies per pass over
-                               its groups, 1, 2, 4 or 8 (0 = chosen from the mean group
-                               width); only with lanes_per_row = 1 */
+                               its groups, 1, 2, 4 or 8; 0 = chosen per wavefront, the
+                               largest count whose widest group times the count is at
+                               most 16 (several narrow groups share a wavefront, wide
+                               ones run alone); only with lanes_per_row = 1, otherwise 1 */
     int32_t pad_loads;      /* kernel schedule: 1 = value/column loads run over the
                                group width so they need not wait for the row length
                                (padding is still never multiplied), 0 = loads stop at

@@ -90,7 +90,8 @@ struct rgcsr_matrix_s {
     int64_t n_matrices = 1, n_wave_long = 0, n_block = 0, n_combine = 0, n_partials = 0;
     bool ragged = false, perm = false;
     int32_t wpg = 0, gpw = 0;
-    int32_t R = 1, pad = 0;  // kernel schedule: rows per lane, padded-width loads
+    int32_t R = 1, pad = 0;  // kernel schedule: rows per lane (0 = per wavefront), padded-width loads
+    std::vector<int32_t> items;  // R = 0: one word per wavefront, first wave item << 2 | log2(rows per lane)
     std::vector<int64_t> row_off, col_off;
     void *mem = nullptr;
     size_t bytes = 0;
@@ -99,6 +100,7 @@ struct rgcsr_matrix_s {
     void *slot_val = nullptr;
     LongItem *wave_work = nullptr, *block_work = nullptr, *combine = nullptr;
     int32_t *long_row = nullptr, *long_col = nullptr;
+    int32_t *short_items = nullptr;
     int64_t *long_ptr = nullptr;
     void *long_val = nullptr;
     void *partial = nullptr;
@@ -199,9 +201,39 @@ void build_host(Built &B, const LayoutParams &p, int vdt, int32_t count, const i
     if (transpose) build_long_work(B.LT.long_ptr, B.LT.work);
 }
 
-// Kernel schedule: rows per lane from the mean group width (about 16 steps
-// in flight per lane), padded-width loads when padding is at most the
-// number of grouped nonzeros.
+// Runs of wave items, one per wavefront: starting at wave item j, the
+// longest run R in {8, 4, 2} whose widest group times R is at most
+// kLaneSteps, else R = 1.  A wavefront then needs a single pass over its
+// loads unless it holds one group wider than kLaneSteps.
+std::vector<int32_t> wave_runs(const HostLayout &L, int32_t wpg) {
+    const int64_t n = (int64_t)(L.gp.size() - 1) * wpg;
+    std::vector<int64_t> width(n);
+    for (int64_t j = 0; j < n; j++) {
+        const int64_t g = j / wpg;
+        const int64_t row0 = L.ragged ? L.grp_row0[g] : g * L.G;
+        const int64_t sg = L.ragged ? L.grp_row0[g + 1] - row0 : std::min<int64_t>(L.G, L.ns - row0);
+        width[j] = sg > 0 ? (L.gp[g + 1] - L.gp[g]) / (sg * L.T) : 0;
+    }
+    std::vector<int32_t> runs;
+    for (int64_t j = 0; j < n;) {
+        int lg = 3;
+        for (; lg > 0; lg--) {
+            const int64_t R = int64_t(1) << lg;
+            if (j + R > n) continue;
+            int64_t wmax = 0;
+            for (int64_t r = 0; r < R; r++) wmax = std::max(wmax, width[j + r]);
+            if (wmax * R <= kLaneSteps) break;
+        }
+        runs.push_back((int32_t)((j << 2) | lg));
+        j += int64_t(1) << lg;
+    }
+    return runs;
+}
+
+// Kernel schedule: padded-width loads when padding is at most the number of
+// grouped nonzeros; rows per lane fixed by the caller or, by default, chosen
+// per wavefront (wave_runs) when a lane owns a whole row and a group fills
+// whole wavefronts, else one.
 void choose_schedule(rgcsr_matrix_s *h, const HostLayout &L, int32_t rows_per_lane, int32_t pad_loads) {
     int64_t short_nnz = 0;
     for (int32_t v : L.short_len) short_nnz += v;
@@ -209,14 +241,13 @@ void choose_schedule(rgcsr_matrix_s *h, const HostLayout &L, int32_t rows_per_la
     if (pad_loads < 0) h->pad = pad_slots <= short_nnz ? 1 : 0;
     else h->pad = pad_loads ? 1 : 0;
     int32_t R = rows_per_lane;
-    if (R == 0) {
-        const double w = L.ns ? (double)L.slots / (double)L.ns : 1.0;
-        R = 1;
-        while (R < 8 && w * (2 * R) <= 16.0) R *= 2;
-    }
-    if (R != 1 && R != 2 && R != 4 && R != 8) fail(RGCSR_EINVAL, "rows_per_lane must be 0, 1, 2, 4 or 8");
+    if (R != 0 && R != 1 && R != 2 && R != 4 && R != 8) fail(RGCSR_EINVAL, "rows_per_lane must be 0, 1, 2, 4 or 8");
     if (L.T != 1 || h->gpw > 0) R = 1;
+    // run words hold the first wave item in 29 bits
+    if (R == 0 && (int64_t)(L.gp.size() - 1) * h->wpg >= (int64_t(1) << 29)) R = 1;
     h->R = R;
+    h->items.clear();
+    if (R == 0) h->items = wave_runs(L, h->wpg);
 }
 
 rgcsr_matrix_s *make_device(const HostLayout &L, const std::vector<int64_t> *row_ptr,
@@ -256,6 +287,7 @@ rgcsr_matrix_s *make_device(const HostLayout &L, const std::vector<int64_t> *row
         a.add(&h->short_row, h->perm ? L.short_row.size() : 0);
         a.add((uint8_t **)&h->slot_val, L.slot_val.size());
         a.add(&h->slot_col, L.slot_col.size());
+        a.add(&h->short_items, h->items.size());
         a.add(&h->wave_work, L.work.wave.size());
         a.add(&h->block_work, L.work.block.size());
         a.add(&h->combine, L.work.combine.size());
@@ -277,6 +309,7 @@ rgcsr_matrix_s *make_device(const HostLayout &L, const std::vector<int64_t> *row
         if (h->perm) upload(h->short_row, L.short_row, st);
         upload_bytes(h->slot_val, L.slot_val, st);
         upload(h->slot_col, L.slot_col, st);
+        upload(h->short_items, h->items, st);
         upload(h->wave_work, L.work.wave, st);
         upload(h->block_work, L.work.block, st);
         upload(h->combine, L.work.combine, st);
@@ -312,7 +345,7 @@ void check_handle(const rgcsr_matrix_s *h) {
 
 int32_t short_waves(const rgcsr_matrix_s *h, bool scheduled) {
     int64_t w = h->wpg > 0 ? h->ng * h->wpg : (h->ng + h->gpw - 1) / h->gpw;
-    if (scheduled) w = (w + h->R - 1) / h->R;
+    if (scheduled) w = h->R == 0 ? (int64_t)h->items.size() : (w + h->R - 1) / h->R;
     if (w > INT32_MAX / 2) fail(RGCSR_EOVERFLOW, "too many wavefronts");
     return (int32_t)w;
 }
@@ -325,6 +358,7 @@ SpmvParams params_of(const rgcsr_matrix_s *h, bool use_rows) {
     P.slot_val = h->slot_val; P.slot_col = h->slot_col;
     P.ng = h->ng; P.ns = h->ns; P.G = h->prm.G; P.wpg = h->wpg; P.gpw = h->gpw;
     P.ragged = h->ragged; P.perm = h->perm; P.pad = h->pad;
+    P.short_items = h->short_items;
     P.wave_work = h->wave_work; P.block_work = h->block_work;
     P.long_row = h->long_row; P.long_ptr = h->long_ptr; P.long_val = h->long_val;
     P.long_col = h->long_col; P.partial = h->partial;
@@ -338,6 +372,7 @@ SpmvParams params_of(const rgcsr_matrix_s *h, bool use_rows) {
     P.n_wave_long = (int32_t)h->n_wave_long;
     P.n_wave_items = (int32_t)wave_items;
     P.total_units = (int32_t)units;
+    P.n_long_units = (int32_t)(h->n_block + (h->n_wave_long + kBlockWaves - 1) / kBlockWaves);
     P.n_long_waves = (int32_t)h->nl;
     P.total_waves = (int32_t)tot;
     return P;
@@ -790,7 +825,8 @@ rgcsr_matrix_s *clone_handle(const rgcsr_matrix_s *A, hipStream_t st) {
         if (A->bytes) HIPCHK(hipMemcpyAsync(h->mem, A->mem, A->bytes, hipMemcpyDeviceToDevice, st));
         rebase(h, A, &rgcsr_matrix_s::gp, &rgcsr_matrix_s::grp_row0, &rgcsr_matrix_s::short_len,
                &rgcsr_matrix_s::short_row, &rgcsr_matrix_s::slot_col, &rgcsr_matrix_s::slot_val,
-               &rgcsr_matrix_s::wave_work, &rgcsr_matrix_s::block_work, &rgcsr_matrix_s::combine,
+               &rgcsr_matrix_s::short_items, &rgcsr_matrix_s::wave_work, &rgcsr_matrix_s::block_work,
+               &rgcsr_matrix_s::combine,
                &rgcsr_matrix_s::long_row, &rgcsr_matrix_s::long_col,
                &rgcsr_matrix_s::long_ptr, &rgcsr_matrix_s::long_val, &rgcsr_matrix_s::partial,
                &rgcsr_matrix_s::row_ptr, &rgcsr_matrix_s::t_map_slot,

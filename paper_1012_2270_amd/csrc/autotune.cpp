@@ -66,7 +66,7 @@ std::vector<Cand> candidates(int64_t n_rows, const int64_t *rp, const rgcsr_opts
             const double fill = (nnz - l2) ? (double)(s - (nnz - l2)) / (double)(nnz - l2) : 0.0;
             if (sigma > 1 && fill > 0.9 * paper_fill && paper_fill > 0) continue;  // sorting buys nothing
             add(sigma, tau, 0);
-            add(sigma, tau, 4);
+            add(sigma, tau, 2);
         }
     }
     if ((int32_t)out.size() > max_cands) out.resize(max_cands);

@@ -110,6 +110,7 @@ constexpr int kBlockThreads = 256;                               // SpMV workgro
 constexpr int kBlockWaves = kBlockThreads / 64;                  // 4
 constexpr int kBlockUnroll = 64;                                 // nonzeros per lane, block items
 constexpr int64_t kBlockChunk = (int64_t)kBlockThreads * kBlockUnroll;  // 16384
+constexpr int kLaneSteps = 16;  // loads in flight per lane that the rows-per-lane choice aims at
 
 struct LongWork {
     std::vector<LongItem> wave, block, combine;

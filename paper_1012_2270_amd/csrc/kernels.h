@@ -22,6 +22,7 @@ struct SpmvParams {
     int32_t gpw;               // groups per wavefront when G*T < 64, else 0
     int32_t ragged, perm;
     int32_t pad;               // value/column loads run over the group width
+    const int32_t *short_items;  // [waves] runs of wave items (rows-per-lane chosen per wavefront)
     // long rows
     const LongItem *wave_work;   // [n_wave_long] wave items
     const LongItem *block_work;  // [n_block_items] block items
@@ -34,6 +35,7 @@ struct SpmvParams {
     int32_t n_wave_long;         // wave items [0, n_wave_long) are long-row wave items
     int32_t n_wave_items;        // all wave items (long-row wave items, then row groups)
     int32_t total_units;         // n_block_items + ceil(n_wave_items / kBlockWaves)
+    int32_t n_long_units;        // units holding long-row work: n_block_items + ceil(n_wave_long / kBlockWaves)
     // per-row long handling of setval/grad: one wavefront per long row
     int32_t n_long_waves;
     int32_t total_waves;

@@ -37,6 +37,15 @@ __device__ __forceinline__ int xcd_remap(int bid, int nwg) {
     return (xcd < rem ? xcd * (per + 1) : rem * (per + 1) + (xcd - rem) * per) + idx;
 }
 
+// First unit of workgroup bid.  Long-row units (the first n_long of the
+// list, heaviest first) keep the dispatch order, so consecutive ones land on
+// different XCDs and their work is spread evenly over the chip; the row-group
+// units after them are remapped so each XCD gets a contiguous range.
+__device__ __forceinline__ int first_unit(int bid, int nwg, int n_long) {
+    const int h = min((n_long + 7) & ~7, nwg);
+    return bid < h ? bid : h + xcd_remap(bid - h, nwg - h);
+}
+
 template <int VD> struct Val;
 template <> struct Val<RGCSR_F64> {
     using S = double;
@@ -219,7 +228,7 @@ template <class A> __device__ __forceinline__ A ldx32(const A *X, int32_t c, uin
 // (G*T a multiple of 64): the group pointers are scalar, value/column loads
 // use 32-bit offsets from the group's first slot.
 template <int VD, class A, int K, int T, int R, bool PAD>
-__device__ __forceinline__ void spmv_groups_uniform(const SpmvParams &P, int32_t w, int lane) {
+__device__ __forceinline__ void spmv_groups_uniform(const SpmvParams &P, int32_t first, int lane) {
     using V = Val<VD>;
     using S = typename V::S;
     const A *X = (const A *)P.x;
@@ -233,7 +242,7 @@ __device__ __forceinline__ void spmv_groups_uniform(const SpmvParams &P, int32_t
     int cmax = 0;
 #pragma unroll
     for (int r = 0; r < R; r++) {
-        const int32_t wr = w * R + r;
+        const int32_t wr = first + r;
         const int32_t g = __builtin_amdgcn_readfirstlane(wr / P.wpg);
         const int lr = (wr - g * P.wpg) * 64 + lane;
         const GroupMeta m = group_meta_uniform(P, g);
@@ -377,10 +386,28 @@ __device__ __forceinline__ void spmv_groups_lane(const SpmvParams &P, int32_t w,
 }
 
 template <int VD, class A, int K, int T, int R>
+__device__ __forceinline__ void spmv_groups_fixed(const SpmvParams &P, int32_t first, int lane) {
+    if (P.pad) spmv_groups_uniform<VD, A, K, T, R, true>(P, first, lane);
+    else spmv_groups_uniform<VD, A, K, T, R, false>(P, first, lane);
+}
+
+// R > 0: every wavefront takes R consecutive wave items.  R = 0: wavefront w
+// takes the run of wave items that item word w names (first item << 2 |
+// log2 of the run length), so narrow groups are packed several to a
+// wavefront and wide ones run alone.
+template <int VD, class A, int K, int T, int R>
 __device__ __forceinline__ void spmv_short(const SpmvParams &P, int32_t w, int lane) {
-    if (P.wpg > 0) {
-        if (P.pad) spmv_groups_uniform<VD, A, K, T, R, true>(P, w, lane);
-        else spmv_groups_uniform<VD, A, K, T, R, false>(P, w, lane);
+    if constexpr (R == 0) {
+        const int32_t it = ldc(P.short_items, w);
+        const int32_t first = it >> 2;
+        switch (it & 3) {
+            case 0: spmv_groups_fixed<VD, A, K, T, 1>(P, first, lane); break;
+            case 1: spmv_groups_fixed<VD, A, K, T, 2>(P, first, lane); break;
+            case 2: spmv_groups_fixed<VD, A, K, T, 4>(P, first, lane); break;
+            default: spmv_groups_fixed<VD, A, K, T, 8>(P, first, lane); break;
+        }
+    } else if (P.wpg > 0) {
+        spmv_groups_fixed<VD, A, K, T, R>(P, w * R, lane);
     } else if constexpr (R == 1) {
         spmv_groups_lane<VD, A, K, T>(P, w, lane);
     }
@@ -500,7 +527,7 @@ __global__ __launch_bounds__(kBlockThreads) void rgcsr_spmv_k(SpmvParams P) {
     const int lane = threadIdx.x & 63;
     const int wv = threadIdx.x >> 6;
     const int nwg = gridDim.x;
-    for (int32_t u = xcd_remap(blockIdx.x, nwg); u < P.total_units; u += nwg) {
+    for (int32_t u = first_unit(blockIdx.x, nwg, P.n_long_units); u < P.total_units; u += nwg) {
         if (LONG && u < P.n_block_items) {
             spmv_block_item<VD, A, K>(P, u, red);
             continue;
@@ -848,13 +875,15 @@ static hipError_t launch_spmv_t(const SpmvParams &P, int nwg, hipStream_t st) {
     return check_launch();
 }
 
-// One lane per row (T = 1) takes R in {1, 2, 4, 8} rows per lane; T > 1 and
-// several right-hand sides take one row per lane.
+// One lane per row (T = 1) takes R in {1, 2, 4, 8} rows per lane, or R = 0
+// for rows per lane chosen per wavefront; T > 1 and several right-hand sides
+// take one row per lane.
 template <int VD, class A>
 static hipError_t launch_spmv_vk(const SpmvParams &P, int T, int K, int R, int nwg, hipStream_t st) {
     if (K == 1) {
         if (T == 1) {
             switch (R) {
+            case 0: return launch_spmv_t<VD, A, 1, 1, 0>(P, nwg, st);
             case 1: return launch_spmv_t<VD, A, 1, 1, 1>(P, nwg, st);
             case 2: return launch_spmv_t<VD, A, 1, 1, 2>(P, nwg, st);
             case 4: return launch_spmv_t<VD, A, 1, 1, 4>(P, nwg, st);

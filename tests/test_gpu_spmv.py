@@ -120,6 +120,29 @@ def test_zipf_sorted_with_long_rows(torch_cuda, oracle):
         M.close()
 
 
+@pytest.mark.parametrize("sigma,tau", [(4096, 32), (512, 16), (1, -1), (1 << 40, 24)])
+def test_rows_per_lane_schedules_agree(torch_cuda, oracle, sigma, tau):
+    """Every kernel schedule (rows per lane fixed at 1, 2, 4, 8 or chosen per
+    wavefront; loads over the group width or the row length) multiplies each
+    row in the same serial order, so all give the same bits, within tolerance
+    of the oracle."""
+    A = W.zipf_matrix(150_001, seed=9)
+    x = W.uniform_vector(A.n_cols, 16, np.float32)
+    ref = None
+    for R in (0, 1, 2, 4, 8):
+        for pad in (0, 1):
+            say("schedules zipf 150001", sigma, tau, R, pad)
+            M = rg.rgcsr_from_csr(A, G=64, sigma=sigma, tau=tau, rows_per_lane=R, pad_loads=pad)
+            assert M.info["rows_per_lane"] == R and M.info["pad_loads"] == pad
+            y = host(M.spmv(dev(x)))
+            M.close()
+            if ref is None:
+                check_spmv(oracle, A, x, y)
+                ref = y
+            else:
+                np.testing.assert_array_equal(y.view(np.uint32), ref.view(np.uint32))
+
+
 def test_deterministic_repeat(torch_cuda, oracle):
     """No atomics in RgCSR SpMV: repeated launches give identical bits, also
     for rows split over several wavefronts."""
