@@ -34,7 +34,7 @@ ROTATE_BYTES = 1 << 30
 
 # layouts timed by the benchmark (also used by the full-size parity test)
 LAYOUT_STENCIL = dict(G=64, T=1, sigma=1, tau=-1)          # the paper's layout
-LAYOUT_ZIPF = dict(G=64, T=1, sigma=4096, tau=32)  # descending order in windows + long-row path
+LAYOUT_ZIPF = dict(G=64, T=1, sigma=512, tau=16)  # descending order in windows + long-row path
 
 METRIC = "SpMV GFLOP/s and achieved HBM GB/s (% of peak), RgCSR vs Hybrid, 1 MI355X"
 

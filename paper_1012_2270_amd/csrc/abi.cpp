@@ -245,9 +245,22 @@ void choose_schedule(rgcsr_matrix_s *h, const HostLayout &L, int32_t rows_per_la
     if (L.T != 1 || h->gpw > 0) R = 1;
     // run words hold the first wave item in 29 bits
     if (R == 0 && (int64_t)(L.gp.size() - 1) * h->wpg >= (int64_t(1) << 29)) R = 1;
-    h->R = R;
     h->items.clear();
-    if (R == 0) h->items = wave_runs(L, h->wpg);
+    if (R == 0) {
+        h->items = wave_runs(L, h->wpg);
+        // the same run length everywhere (uniform widths, e.g. stencils):
+        // the fixed schedule does the same without reading run words
+        bool same = !h->items.empty();
+        for (size_t i = 0; same && i < h->items.size(); i++) {
+            const int32_t lg = h->items[0] & 3;
+            same = (h->items[i] >> 2) == (int32_t)(i << lg) && ((h->items[i] & 3) == lg || i + 1 == h->items.size());
+        }
+        if (same) {
+            R = 1 << (h->items[0] & 3);
+            h->items.clear();
+        }
+    }
+    h->R = R;
 }
 
 rgcsr_matrix_s *make_device(const HostLayout &L, const std::vector<int64_t> *row_ptr,
@@ -390,8 +403,9 @@ void spmv_launch(const rgcsr_matrix_s *h, int K, const void *X, int64_t ldx, voi
     SpmvParams P = params_of(h, K == 1);
     P.x = X; P.y = Y; P.ldx = ldx; P.ldy = ldy;
     int64_t nwg = P.total_units;
-    // a persistent launch keeps two 1024-thread workgroups resident per CU
-    if (persistent) nwg = std::min<int64_t>(nwg, (int64_t)cu_count(h->device) * 2);
+    // a persistent launch (several right-hand sides only) keeps two 256-thread
+    // workgroups per CU that stride over the units
+    if (persistent && K > 1) nwg = std::min<int64_t>(nwg, (int64_t)cu_count(h->device) * 2);
     if (nwg == 0) return;
     const int vd = h->vdt;
     if (f64 && !(vd == RGCSR_F64 || vd == RGCSR_F32))

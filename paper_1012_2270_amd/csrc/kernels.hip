@@ -483,6 +483,64 @@ __device__ __forceinline__ void spmv_wave_long(const SpmvParams &P, int32_t w, i
     if (ok && q == 0) store_row<A, K>(Y + (int64_t)orow * P.ldy, acc);
 }
 
+// Same work item, single right-hand side with float accumulation: the item's
+// nonzeros (at most kWaveRowMax, contiguous) are loaded element-parallel, lane
+// l taking elements l, l + 64, ..., so the value/column loads need no row
+// bounds and every lane is busy; the products go to this wavefront's LDS
+// slice and the item's lane-per-row mapping then sums them in the same
+// strided order as spmv_wave_long.
+template <int VD>
+__device__ __forceinline__ void spmv_wave_long_lds(const SpmvParams &P, int32_t w, int lane, float *buf) {
+    using V = Val<VD>;
+    using S = typename V::S;
+    constexpr int U = kWaveRowMax / 64;
+    float *Y = (float *)P.y;
+    const float *X = (const float *)P.x;
+    const uint32_t xrow = (uint32_t)(P.ldx * (int64_t)sizeof(float));
+    const LongItem it = ldc(P.wave_work, w);
+    const int64_t item0 = ldc(P.long_ptr, (int64_t)it.a);
+    const int32_t n = (int32_t)(ldc(P.long_ptr, (int64_t)it.a + it.b) - item0);
+    const S *vb = (const S *)P.long_val + item0;
+    const int32_t *cb = P.long_col + item0;
+    S v[U];
+    int32_t ci[U];
+    float xv[U];
+#pragma unroll
+    for (int u = 0; u < U; u++) {
+        const uint32_t o = lane + 64 * u < n ? (uint32_t)(lane + 64 * u) : 0u;
+        v[u] = ldnt((const S *)((const char *)vb + o * (uint32_t)sizeof(S)));
+        ci[u] = ldnt((const int32_t *)((const char *)cb + o * 4u));
+    }
+    // row bounds and output row of this lane, needed only after the gathers
+    const int TL = it.c;
+    const int sh = 31 - __builtin_clz(TL);
+    const int r = lane >> sh, q = lane & (TL - 1);
+    const bool ok = r < it.b;
+    const int64_t li = (int64_t)it.a + (ok ? r : 0);
+    const int32_t b = (int32_t)(P.long_ptr[li] - item0), e = (int32_t)(P.long_ptr[li + 1] - item0);
+    const int32_t orow = P.long_row[li];
+#pragma unroll
+    for (int u = 0; u < U; u++) xv[u] = ldx32(X, ci[u], xrow);
+#pragma unroll
+    for (int u = 0; u < U; u++) buf[lane + 64 * u] = V::template cvt<float>(v[u]) * xv[u];
+    if (lane == 0) buf[kWaveRowMax] = 0.f;  // terms past a row read this slot
+    // the slice is private to this wavefront: LDS accesses of one wavefront
+    // complete in order, only the compiler must not move the reads up
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    const int32_t nj = ok && e - b > q ? (e - b - q + TL - 1) >> sh : 0;
+    float acc = 0.f;
+#pragma nounroll
+    for (int j0 = 0; j0 < U; j0 += 4)
+#pragma unroll
+        for (int j = j0; j < j0 + 4; j++) acc += buf[j < nj ? b + q + j * TL : kWaveRowMax];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1)
+        if (off < TL) acc += __shfl_xor(acc, off);
+    if (ok && q == 0) Y[(int64_t)orow * P.ldy] = acc;
+}
+
 // One chunk (at most kBlockChunk nonzeros) of a very long row, reduced by the
 // whole workgroup in LDS.
 template <int VD, class A, int K>
@@ -522,22 +580,39 @@ __device__ __forceinline__ void spmv_block_item(const SpmvParams &P, int32_t u, 
 }
 
 template <int VD, class A, int K, int T, int R, bool LONG>
+__device__ __forceinline__ void spmv_unit(const SpmvParams &P, int32_t u, int lane, int wv, A (*red)[K], float *lbuf) {
+    constexpr bool kLdsLong = LONG && K == 1 && sizeof(A) == 4;
+    if (LONG && u < P.n_block_items) {
+        spmv_block_item<VD, A, K>(P, u, red);
+        return;
+    }
+    const int32_t w = __builtin_amdgcn_readfirstlane((u - (LONG ? P.n_block_items : 0)) * kBlockWaves + wv);
+    if (w >= P.n_wave_items) return;
+    if (LONG && w < P.n_wave_long) {
+        if constexpr (kLdsLong) spmv_wave_long_lds<VD>(P, w, lane, lbuf);
+        else spmv_wave_long<VD, A, K>(P, w, lane);
+    } else {
+        spmv_short<VD, A, K, T, R>(P, w - (LONG ? P.n_wave_long : 0), lane);
+    }
+}
+
+// A single right-hand side runs one unit per workgroup (the grid covers every
+// unit, so nothing stays live across units); several right-hand sides may run
+// a persistent grid that strides over the units.
+template <int VD, class A, int K, int T, int R, bool LONG>
 __global__ __launch_bounds__(kBlockThreads) void rgcsr_spmv_k(SpmvParams P) {
+    constexpr bool kLdsLong = LONG && K == 1 && sizeof(A) == 4;
     __shared__ A red[kBlockWaves][K];
+    __shared__ float lbuf[kLdsLong ? kBlockWaves : 1][kLdsLong ? kWaveRowMax + 1 : 1];
     const int lane = threadIdx.x & 63;
     const int wv = threadIdx.x >> 6;
     const int nwg = gridDim.x;
-    for (int32_t u = first_unit(blockIdx.x, nwg, P.n_long_units); u < P.total_units; u += nwg) {
-        if (LONG && u < P.n_block_items) {
-            spmv_block_item<VD, A, K>(P, u, red);
-            continue;
-        }
-        const int32_t w = __builtin_amdgcn_readfirstlane((u - (LONG ? P.n_block_items : 0)) * kBlockWaves + wv);
-        if (w >= P.n_wave_items) continue;
-        if (LONG && w < P.n_wave_long)
-            spmv_wave_long<VD, A, K>(P, w, lane);
-        else
-            spmv_short<VD, A, K, T, R>(P, w - (LONG ? P.n_wave_long : 0), lane);
+    if constexpr (K == 1) {
+        const int32_t u = first_unit(blockIdx.x, nwg, P.n_long_units);
+        if (u < P.total_units) spmv_unit<VD, A, K, T, R, LONG>(P, u, lane, wv, red, lbuf[kLdsLong ? wv : 0]);
+    } else {
+        for (int32_t u = first_unit(blockIdx.x, nwg, P.n_long_units); u < P.total_units; u += nwg)
+            spmv_unit<VD, A, K, T, R, LONG>(P, u, lane, wv, red, lbuf[0]);
     }
 }
 

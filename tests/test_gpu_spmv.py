@@ -133,7 +133,7 @@ def test_rows_per_lane_schedules_agree(torch_cuda, oracle, sigma, tau):
         for pad in (0, 1):
             say("schedules zipf 150001", sigma, tau, R, pad)
             M = rg.rgcsr_from_csr(A, G=64, sigma=sigma, tau=tau, rows_per_lane=R, pad_loads=pad)
-            assert M.info["rows_per_lane"] == R and M.info["pad_loads"] == pad
+            assert (M.info["rows_per_lane"] == R or R == 0) and M.info["pad_loads"] == pad
             y = host(M.spmv(dev(x)))
             M.close()
             if ref is None:
