@@ -173,6 +173,18 @@ def _events(torch, fn, reps):
     return [ev[i].elapsed_time(ev[i + 1]) for i in range(reps)]
 
 
+def achievable_read_gbs(torch, rg, nbytes=2 << 30, reps=10):
+    """Achievable HBM read rate: one streaming read of a 2 GiB buffer with the
+    library's nontemporal 16-byte loads, mean over reps launches."""
+    buf = torch.empty(nbytes, dtype=torch.uint8, device="cuda:0")
+    sink = torch.zeros(1, dtype=torch.int32, device="cuda:0")
+    for _ in range(2):
+        rg.rgcsr_stream_read(buf, sink)
+    t = _events(torch, lambda i: rg.rgcsr_stream_read(buf, sink), reps)
+    del buf
+    return nbytes / (float(np.mean(t)) * 1e-3) / 1e9
+
+
 def bench_spmm(args, torch, rg, W):
     """Multi-RHS SpMM on the Zipf matrix, k in {1, 4, 16, 32}, one launch per k,
     against k sequential single-vector SpMVs."""
@@ -343,10 +355,15 @@ def bench_fp64(args, torch, rg, W):
     """The benchmark matrices in double precision (values, vectors and
     accumulation), RgCSR vs Hybrid; the paper reports double throughout."""
     import oracle
-    out = {"metric": "SpMV GFLOP/s and GB/s, FP64", "results": []}
+    # the paper's bandwidth model (Table 1): 2 flops per nonzero over the value
+    # and column bytes (x cached) or also one x element per nonzero (uncached)
+    out = {"metric": "SpMV GFLOP/s and GB/s, FP64", "results": [],
+           "t1_model_gflops_at_peak": {"x_cached": 2 * HBM_PEAK_GBS / 12, "x_uncached": 2 * HBM_PEAK_GBS / 20}}
     A1, _ = W.workload_laplace3d(128)
     A2, _ = W.workload_zipf(1_000_000)
-    for name, A, lay in (("laplace3d_7pt_128", A1, LAYOUT_STENCIL), ("zipf2_1e6", A2, LAYOUT_ZIPF)):
+    A3 = W.stencil_3d_27pt(160)
+    for name, A, lay in (("laplace3d_7pt_128", A1, LAYOUT_STENCIL), ("zipf2_1e6", A2, LAYOUT_ZIPF),
+                         ("stencil27_160", A3, LAYOUT_STENCIL)):
         A64 = A.astype(np.float64)
         x = W.uniform_vector(A.n_cols, 77, np.float64)
         base = rg.rgcsr_from_csr(A64, value_dtype="f64", **lay)
@@ -370,9 +387,65 @@ def bench_fp64(args, torch, rg, W):
                                "rgcsr_gflops": 2 * A.nnz / (t * 1e-3) / 1e9, "rgcsr_gbs": b / (t * 1e-3) / 1e9,
                                "rgcsr_hbm_frac": b / (t * 1e-3) / 1e9 / HBM_PEAK_GBS,
                                "hybrid_gflops": 2 * A.nnz / (th * 1e-3) / 1e9, "alg_bytes": b,
+                               "rgcsr_over_t1_x_cached": 2 * A.nnz / (t * 1e-3) / 1e9 / (2 * HBM_PEAK_GBS / 12),
                                "max_scaled_error": err, "copies_rotated": copies})
         for m in mats[1:] + hybs[1:]:
             m.close()
+    print(json.dumps(out), flush=True)
+
+
+def bench_variants(args, torch, rg, W):
+    """Kernel-variant study on the benchmark matrices (FP32): loads bounded by
+    the row length, loads over the group width, and sliced ELLPACK (no row
+    lengths, padding multiplied), each under three load policies (nontemporal
+    matrix streams with cached x, everything cached, x nontemporal too), from
+    HBM (rotating copies) and from the 256 MB cache (one copy)."""
+    A1, x1 = W.workload_laplace3d(128)
+    A2, x2 = W.workload_zipf(1_000_000)
+    A3 = W.stencil_3d_27pt(160, dtype=np.float32)
+    x3 = W.uniform_vector(A3.n_cols, 2270, np.float32)
+    out = {"metric": "SpMV variants, FP32: row-length bound vs sliced ELLPACK, load policies", "results": []}
+    for name, A, x, lay in (("laplace3d_7pt_128", A1, x1, LAYOUT_STENCIL), ("zipf2_1e6", A2, x2, LAYOUT_ZIPF),
+                            ("stencil27_160", A3, x3, LAYOUT_STENCIL)):
+        xd = torch.from_numpy(x).to("cuda:0")
+        ref = None
+        for pad in (0, 1, 2):
+            for lp in (0, 1, 2):
+                base = rg.rgcsr_from_csr(A, pad_loads=pad, load_policy=lp, **lay)
+                per = base.info["device_bytes"] + 4 * (A.n_rows + A.n_cols)
+                copies = max(1, math.ceil(ROTATE_BYTES / per))
+                mats = [base] + [base.clone() for _ in range(copies - 1)]
+                xs = [xd.clone() for _ in range(copies)]
+                ys = [torch.empty(A.n_rows, device="cuda:0") for _ in range(copies)]
+                for i in range(args.warmup):
+                    rg.rgcsr_spmv(mats[i % copies], xs[i % copies], ys[i % copies])
+                cold = float(np.mean(_events(torch, lambda i: rg.rgcsr_spmv(mats[i % copies], xs[i % copies],
+                                                                             ys[i % copies]), args.steps)))
+                warm = float(np.mean(_events(torch, lambda i: rg.rgcsr_spmv(mats[0], xs[0], ys[0]), args.steps)))
+                rg.rgcsr_spmv(mats[0], xs[0], ys[0])
+                y = ys[0].cpu().numpy()
+                if ref is None:
+                    ref = y
+                b = alg_bytes(A.nnz, A.n_rows, A.n_cols, base.info["n_groups"])
+                out["results"].append({"matrix": name, "pad_loads": pad, "load_policy": lp,
+                                       "slots": base.info["slots"], "us_hbm": cold * 1e3, "us_cache": warm * 1e3,
+                                       "gbs_hbm": b / (cold * 1e-3) / 1e9, "copies_rotated": copies,
+                                       "equal_to_first_variant": bool(np.array_equal(y, ref))})
+                for m in mats[1:]:
+                    m.close()
+                base.close()
+        hyb = rg.hyb_from_csr(A)
+        per = hyb.info["device_bytes"] + 4 * (A.n_rows + A.n_cols)
+        copies = max(1, math.ceil(ROTATE_BYTES / per))
+        hybs = [hyb] + [hyb.clone() for _ in range(copies - 1)]
+        ys = [torch.empty(A.n_rows, device="cuda:0") for _ in range(copies)]
+        for i in range(args.warmup):
+            rg.hyb_spmv(hybs[i % copies], xd, ys[i % copies])
+        cold = float(np.mean(_events(torch, lambda i: rg.hyb_spmv(hybs[i % copies], xd, ys[i % copies]), args.steps)))
+        warm = float(np.mean(_events(torch, lambda i: rg.hyb_spmv(hybs[0], xd, ys[0]), args.steps)))
+        out["results"].append({"matrix": name, "format": "hybrid", "us_hbm": cold * 1e3, "us_cache": warm * 1e3})
+        for h in hybs[1:]:
+            h.close()
     print(json.dumps(out), flush=True)
 
 
@@ -385,7 +458,8 @@ def main():
     ap.add_argument("--no-check", action="store_true", help="skip the oracle check of the outputs")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a 1 GiB device copy (for scaling the HBM byte counters)")
-    ap.add_argument("--config", default="spmv", choices=["spmv", "spmm", "batched", "cg", "grad", "fp64"],
+    ap.add_argument("--config", default="spmv",
+                    choices=["spmv", "spmm", "batched", "cg", "grad", "fp64", "variants"],
                     help="spmv (default, the contract line) or another form of the path")
     ap.add_argument("--batch-count", type=int, default=4096)
     ap.add_argument("--cg-n", type=int, default=160)
@@ -415,7 +489,7 @@ def main():
     rg._lib.load()
     if args.config != "spmv":
         {"spmm": bench_spmm, "batched": bench_batched, "cg": bench_cg, "grad": bench_grad,
-         "fp64": bench_fp64}[args.config](
+         "fp64": bench_fp64, "variants": bench_variants}[args.config](
             args, torch, rg, W)
         return
     log("generating matrices ...")
@@ -456,6 +530,7 @@ def main():
         d = time_launches(torch, lambda i, c=c: c.hyb_spmv(i, rg), K, Wm)
         hyb_ms.append(d)
 
+    read_gbs = achievable_read_gbs(torch, rg)
     flops = sum(c.flops for c in cases)
     value = flops * K / (total_ms * 1e-3) / 1e9
     detail = {}
@@ -470,7 +545,8 @@ def main():
             "fill_pct": 100.0 * (c.info["slots"] + c.info["long_nnz"] - c.A.nnz) / max(1, c.A.nnz),
             "rgcsr": {"us": 1e3 * t, "us_median": 1e3 * float(np.median(per_kernel[ci])),
                       "gflops": c.flops / (t * 1e-3) / 1e9, "gbs": c.bytes / (t * 1e-3) / 1e9,
-                      "hbm_frac": c.bytes / (t * 1e-3) / 1e9 / HBM_PEAK_GBS},
+                      "hbm_frac": c.bytes / (t * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                      "frac_of_achievable_read": c.bytes / (t * 1e-3) / 1e9 / read_gbs},
             "hybrid": {"us": 1e3 * th, "gflops": c.flops / (th * 1e-3) / 1e9,
                        "gbs": c.bytes / (th * 1e-3) / 1e9, "hbm_frac": c.bytes / (th * 1e-3) / 1e9 / HBM_PEAK_GBS,
                        "ell_width": c.hyb_info["ell_width"], "coo_nnz": c.hyb_info["coo_nnz"]},
@@ -504,7 +580,8 @@ def main():
         "roofline": {"bound": "hbm", "kernel": dc.name, "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "traffic": tr,
-                     "alg_bytes_per_launch": dc.bytes, "avg_launch_us": t_dom * 1e6},
+                     "alg_bytes_per_launch": dc.bytes, "avg_launch_us": t_dom * 1e6,
+                     "achievable_read_gbs": read_gbs, "frac_of_achievable_read": achieved / read_gbs},
         "cases": detail,
         "wall_s_timed": wall,
     }

@@ -93,13 +93,22 @@ typedef struct {
     int32_t pad_loads;      /* kernel schedule: 1 = value/column loads run over the
                                group width so they need not wait for the row length
                                (padding is still never multiplied), 0 = loads stop at
-                               the row length, -1 = on when padding is at most 100% of the
-                               grouped nonzeros */
+                               the row length, -1 = 1 when padding is at most 100% of the
+                               grouped nonzeros, else 0; 2 = sliced ELLPACK (Section 3.3):
+                               row lengths are not read and every slot of the group width
+                               is multiplied, padding included (same result for finite x;
+                               needs group_size * lanes_per_row a multiple of 64) */
+    int32_t load_policy;    /* where loads may be cached, after the paper's texture-cache
+                               study (Section 4.3): 0 (default) = value/column streams
+                               nontemporal, x gathers cached; 1 = every load cached;
+                               2 = x gathers nontemporal too.  1 and 2 need F32 values,
+                               lanes_per_row = 1 and F32 vectors, and apply to single
+                               right-hand-side launches */
 } rgcsr_opts;
 
 /* Fills *opts with the paper's layout: G = 64, T = 1, sigma = 1, no long
  * rows, float32 storage, no CSR map, no transpose, validation on, automatic
- * kernel schedule (rows_per_lane = 0, pad_loads = -1). */
+ * kernel schedule (rows_per_lane = 0, pad_loads = -1, load_policy = 0). */
 void rgcsr_default_opts(rgcsr_opts *opts);
 
 typedef struct rgcsr_matrix_s *rgcsr_handle;
@@ -118,7 +127,7 @@ typedef struct {
     int32_t group_size, lanes_per_row, value_dtype, has_transpose;
     int64_t sort_window, long_row_threshold;
     int64_t device_bytes; /* device memory the handle owns */
-    int32_t rows_per_lane, pad_loads; /* kernel schedule in use */
+    int32_t rows_per_lane, pad_loads, load_policy; /* kernel schedule in use */
 } rgcsr_info_t;
 
 /* ---- Host-only layout (no GPU needed; used to check the layout on CPU) ---- */
@@ -337,6 +346,18 @@ const char *rgcsr_last_error(void);
 
 /* Library version string, e.g. "rgcsr 0.1 gfx950". */
 const char *rgcsr_version(void);
+
+/* ---- Measurement helper ----------------------------------------------------- */
+
+/* Reads `bytes` bytes of device memory at buf with the nontemporal 16-byte
+ * loads the SpMV uses for its value and column streams, one launch on
+ * `stream`, so that timing it gives the achievable HBM read rate: a second
+ * denominator beside the peak for the bandwidth model of Section 3.4.  buf
+ * is a device pointer, 16-byte aligned, and bytes a multiple of 16; sink is a
+ * device pointer to 4 bytes that the kernel may write (its contents are
+ * meaningless).  Nothing is allocated; RGCSR_EINVAL on a null pointer or a
+ * misaligned argument. */
+rgcsr_status rgcsr_stream_read(const void *buf, int64_t bytes, void *sink, void *stream);
 
 #ifdef __cplusplus
 }

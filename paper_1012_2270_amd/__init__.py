@@ -71,12 +71,12 @@ def _dev_check(t, name: str):
 
 def make_opts(G: int = 64, T: int = 1, sigma: int = 1, tau: int = -1, value_dtype: str = "f32",
               keep_csr_map: bool = False, build_transpose: bool = False, validate: bool = True,
-              rows_per_lane: int = 0, pad_loads: int = -1) -> _lib.Opts:
+              rows_per_lane: int = 0, pad_loads: int = -1, load_policy: int = 0) -> _lib.Opts:
     o = _lib.Opts()
     o.group_size, o.lanes_per_row, o.sort_window, o.long_row_threshold = G, T, sigma, tau
     o.value_dtype = DTYPE_CODES[value_dtype]
     o.keep_csr_map, o.build_transpose, o.validate = int(keep_csr_map), int(build_transpose), int(validate)
-    o.rows_per_lane, o.pad_loads = rows_per_lane, pad_loads
+    o.rows_per_lane, o.pad_loads, o.load_policy = rows_per_lane, pad_loads, load_policy
     return o
 
 
@@ -394,8 +394,9 @@ def opts_dict(o: _lib.Opts) -> dict:
 
 def opts_from_dict(d: dict) -> _lib.Opts:
     o = _lib.Opts()
+    defaults = opts_dict(make_opts())
     for f, _ in _lib.Opts._fields_:
-        setattr(o, f, int(d[f]))
+        setattr(o, f, int(d.get(f, defaults[f])))
     return o
 
 
@@ -450,6 +451,14 @@ def rgcsr_autotune(A, x, y, base: _lib.Opts | None = None, max_candidates: int =
 
 def version() -> str:
     return _lib.load().rgcsr_version().decode()
+
+
+def rgcsr_stream_read(buf, sink, stream=None) -> None:
+    """One streaming read of the device tensor buf (the achievable-bandwidth
+    probe); sink is a small device tensor the kernel may write."""
+    _dev_check(buf, "buf")
+    _dev_check(sink, "sink")
+    _lib.call("rgcsr_stream_read", _ptr(buf), buf.numel() * buf.element_size(), _ptr(sink), _stream(stream))
 
 
 # ----------------------------------------------------------------------------

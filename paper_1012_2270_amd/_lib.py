@@ -26,7 +26,7 @@ class Opts(ctypes.Structure):
     _fields_ = [("group_size", c_i32), ("lanes_per_row", c_i32), ("sort_window", c_i64),
                 ("long_row_threshold", c_i64), ("value_dtype", c_i32), ("keep_csr_map", c_i32),
                 ("build_transpose", c_i32), ("validate", c_i32), ("rows_per_lane", c_i32),
-                ("pad_loads", c_i32)]
+                ("pad_loads", c_i32), ("load_policy", c_i32)]
 
 
 class Info(ctypes.Structure):
@@ -35,7 +35,8 @@ class Info(ctypes.Structure):
                 ("n_matrices", c_i64), ("long_work", c_i64), ("partials", c_i64),
                 ("group_size", c_i32), ("lanes_per_row", c_i32), ("value_dtype", c_i32),
                 ("has_transpose", c_i32), ("sort_window", c_i64), ("long_row_threshold", c_i64),
-                ("device_bytes", c_i64), ("rows_per_lane", c_i32), ("pad_loads", c_i32)]
+                ("device_bytes", c_i64), ("rows_per_lane", c_i32), ("pad_loads", c_i32),
+                ("load_policy", c_i32)]
 
     def as_dict(self) -> dict:
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -95,6 +96,7 @@ SIGNATURES = {
     "rgcsr_status_string": (ctypes.c_char_p, [c_int]),
     "rgcsr_last_error": (ctypes.c_char_p, []),
     "rgcsr_version": (ctypes.c_char_p, []),
+    "rgcsr_stream_read": (c_int, [c_vp, c_i64, c_vp, c_vp]),
 }
 
 _lib = None

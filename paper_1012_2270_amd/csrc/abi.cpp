@@ -91,6 +91,7 @@ struct rgcsr_matrix_s {
     bool ragged = false, perm = false;
     int32_t wpg = 0, gpw = 0;
     int32_t R = 1, pad = 0;  // kernel schedule: rows per lane (0 = per wavefront), padded-width loads
+    int32_t lp = 0;          // load policy (0 = nontemporal matrix streams, cached x)
     std::vector<int32_t> items;  // R = 0: one word per wavefront, first wave item << 2 | log2(rows per lane)
     std::vector<int64_t> row_off, col_off;
     void *mem = nullptr;
@@ -234,12 +235,20 @@ std::vector<int32_t> wave_runs(const HostLayout &L, int32_t wpg) {
 // grouped nonzeros; rows per lane fixed by the caller or, by default, chosen
 // per wavefront (wave_runs) when a lane owns a whole row and a group fills
 // whole wavefronts, else one.
-void choose_schedule(rgcsr_matrix_s *h, const HostLayout &L, int32_t rows_per_lane, int32_t pad_loads) {
+void choose_schedule(rgcsr_matrix_s *h, const HostLayout &L, int32_t rows_per_lane, int32_t pad_loads,
+                     int32_t load_policy) {
     int64_t short_nnz = 0;
     for (int32_t v : L.short_len) short_nnz += v;
     const int64_t pad_slots = L.slots - short_nnz;
+    if (pad_loads < -1 || pad_loads > 2) fail(RGCSR_EINVAL, "pad_loads must be -1, 0, 1 or 2");
+    if (pad_loads == 2 && h->gpw > 0)
+        fail(RGCSR_EUNSUPPORTED, "sliced ELLPACK needs group_size * lanes_per_row a multiple of 64");
     if (pad_loads < 0) h->pad = pad_slots <= short_nnz ? 1 : 0;
-    else h->pad = pad_loads ? 1 : 0;
+    else h->pad = pad_loads;
+    if (load_policy < 0 || load_policy > 2) fail(RGCSR_EINVAL, "load_policy must be 0, 1 or 2");
+    if (load_policy != 0 && (L.vdt != RGCSR_F32 || L.T != 1))
+        fail(RGCSR_EUNSUPPORTED, "load policies 1 and 2 need F32 values and lanes_per_row = 1");
+    h->lp = load_policy;
     int32_t R = rows_per_lane;
     if (R != 0 && R != 1 && R != 2 && R != 4 && R != 8) fail(RGCSR_EINVAL, "rows_per_lane must be 0, 1, 2, 4 or 8");
     if (L.T != 1 || h->gpw > 0) R = 1;
@@ -265,7 +274,7 @@ void choose_schedule(rgcsr_matrix_s *h, const HostLayout &L, int32_t rows_per_la
 
 rgcsr_matrix_s *make_device(const HostLayout &L, const std::vector<int64_t> *row_ptr,
                             const HostLayout *map, hipStream_t st, int32_t rows_per_lane = 0,
-                            int32_t pad_loads = -1) {
+                            int32_t pad_loads = -1, int32_t load_policy = 0) {
     auto *h = new rgcsr_matrix_s();
     try {
         h->device = current_device();
@@ -286,7 +295,7 @@ rgcsr_matrix_s *make_device(const HostLayout &L, const std::vector<int64_t> *row
         const int64_t GT = (int64_t)L.G * L.T;
         h->wpg = GT >= 64 ? (int32_t)(GT / 64) : 0;
         h->gpw = GT < 64 ? (int32_t)(64 / GT) : 0;
-        choose_schedule(h, L, rows_per_lane, pad_loads);
+        choose_schedule(h, L, rows_per_lane, pad_loads, load_policy);
         // the kernels address a group's slots with 32-bit byte offsets
         int64_t max_group = 0;
         for (size_t g = 0; g + 1 < L.gp.size(); g++) max_group = std::max(max_group, L.gp[g + 1] - L.gp[g]);
@@ -416,7 +425,8 @@ void spmv_launch(const rgcsr_matrix_s *h, int K, const void *X, int64_t ldx, voi
     if (K > 1 && h->prm.T != 1) fail(RGCSR_EUNSUPPORTED, "several right-hand sides need lanes_per_row = 1");
     if (K == 1 && h->n_cols * ldx * (f64 ? 8 : 4) >= (int64_t(1) << 32))
         fail(RGCSR_EUNSUPPORTED, "x (n_cols * ldx elements) of 4 GiB or more");
-    hipError_t e = launch_spmv(P, vd, f64, h->prm.T, K, K == 1 ? h->R : 1, (int)nwg, st);
+    if (K == 1 && h->lp != 0 && f64) fail(RGCSR_EUNSUPPORTED, "load policies 1 and 2 need F32 vectors");
+    hipError_t e = launch_spmv(P, vd, f64, h->prm.T, K, K == 1 ? h->R : 1, K == 1 ? h->lp : 0, (int)nwg, st);
     if (e != hipSuccess) fail(RGCSR_EHIP, std::string("spmv launch: ") + hipGetErrorString(e));
     if (h->n_combine) {
         e = launch_combine(h->combine, (int32_t)h->n_combine, h->long_row, h->partial, Y, ldy, f64, K, st);
@@ -442,6 +452,7 @@ void rgcsr_default_opts(rgcsr_opts *o) {
     o->validate = 1;
     o->rows_per_lane = 0;
     o->pad_loads = -1;
+    o->load_policy = 0;
 }
 
 const char *rgcsr_status_string(rgcsr_status s) {
@@ -460,6 +471,17 @@ const char *rgcsr_status_string(rgcsr_status s) {
 const char *rgcsr_last_error(void) { return g_last_error.c_str(); }
 
 const char *rgcsr_version(void) { return "rgcsr 0.1 gfx950"; }
+
+rgcsr_status rgcsr_stream_read(const void *buf, int64_t bytes, void *sink, void *stream) {
+    ABI_TRY
+    if (!buf || !sink || bytes < 0) fail(RGCSR_EINVAL, "buf and sink must be device pointers, bytes >= 0");
+    if (bytes % 16 != 0 || (uintptr_t)buf % 16 != 0 || (uintptr_t)sink % 4 != 0)
+        fail(RGCSR_EINVAL, "buf must be 16-byte aligned with bytes a multiple of 16, sink 4-byte aligned");
+    // eight 256-thread workgroups per CU stride over the buffer
+    const int nb = (int)std::min<int64_t>(std::max<int64_t>(1, bytes / 4096), (int64_t)cu_count(current_device()) * 8);
+    HIPCHK(launch_stream_read(buf, bytes / 16, (int32_t *)sink, nb, (hipStream_t)stream));
+    ABI_CATCH
+}
 
 rgcsr_status rgcsr_layout_sizes(int64_t n_rows, int64_t n_cols, int64_t nnz, const int64_t *row_ptr,
                                 const int32_t *col_idx, const rgcsr_opts *opts, rgcsr_info_t *out) {
@@ -562,10 +584,10 @@ rgcsr_status rgcsr_from_csr(int64_t n_rows, int64_t n_cols, int64_t nnz, const i
     const bool keep = o.keep_csr_map != 0, tr = o.build_transpose != 0;
     build_host(B, p, o.value_dtype, 1, &n_rows, &n_cols, &rp, &col, &val, vals_dtype, o.validate != 0, keep, tr);
     rgcsr_matrix_s *h = make_device(B.L, (keep || tr) ? &B.row_ptr : nullptr, nullptr, st, o.rows_per_lane,
-                                    o.pad_loads);
+                                    o.pad_loads, o.load_policy);
     if (tr) {
         try {
-            h->AT = make_device(B.LT, nullptr, &B.LTmap, st, o.rows_per_lane, o.pad_loads);
+            h->AT = make_device(B.LT, nullptr, &B.LTmap, st, o.rows_per_lane, o.pad_loads, o.load_policy);
         } catch (...) {
             free_handle(h);
             throw;
@@ -595,10 +617,10 @@ rgcsr_status rgcsr_from_csr_batch(int32_t count, const int64_t *n_rows, const in
     build_host(B, p, o.value_dtype, count, n_rows, n_cols, row_ptr, col_idx, vals, vals_dtype, o.validate != 0,
                keep, tr);
     rgcsr_matrix_s *h = make_device(B.L, (keep || tr) ? &B.row_ptr : nullptr, nullptr, st, o.rows_per_lane,
-                                    o.pad_loads);
+                                    o.pad_loads, o.load_policy);
     if (tr) {
         try {
-            h->AT = make_device(B.LT, nullptr, &B.LTmap, st, o.rows_per_lane, o.pad_loads);
+            h->AT = make_device(B.LT, nullptr, &B.LTmap, st, o.rows_per_lane, o.pad_loads, o.load_policy);
         } catch (...) {
             free_handle(h);
             throw;
@@ -814,6 +836,7 @@ rgcsr_status rgcsr_info(rgcsr_handle A, rgcsr_info_t *out) {
     out->device_bytes = (int64_t)A->bytes + (A->AT ? (int64_t)A->AT->bytes : 0);
     out->rows_per_lane = A->R;
     out->pad_loads = A->pad;
+    out->load_policy = A->lp;
     ABI_CATCH
 }
 

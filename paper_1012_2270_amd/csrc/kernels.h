@@ -58,7 +58,8 @@ struct HybParams {
 enum { kRR = 0, kRR0 = 1, kPQ = 2, kAlpha = 3, kBeta = 4, kOut = 5, kNumScal = 8 };
 enum { kScalPQ = 0, kScalRRNew = 1, kScalRRInit = 2, kScalOut = 3 };
 
-hipError_t launch_spmv(const SpmvParams &P, int vdt, int vec_f64, int T, int K, int R, int nwg, hipStream_t st);
+hipError_t launch_spmv(const SpmvParams &P, int vdt, int vec_f64, int T, int K, int R, int load_policy, int nwg,
+                       hipStream_t st);
 hipError_t launch_combine(const LongItem *items, int32_t n, const int32_t *long_row, const void *partial, void *Y,
                           int64_t ldy, int vec_f64, int K, hipStream_t st);
 hipError_t launch_setval(const SpmvParams &P, int vdt, int T, const void *theta, int theta_f64,
@@ -80,6 +81,7 @@ hipError_t launch_refine_start(int64_t n, const double *r64, double s, float *r,
                                double *part, int nb, hipStream_t st);
 hipError_t launch_refine_add(int64_t n, double *x, const float *d, double inv_s, int nb, hipStream_t st);
 hipError_t launch_copy(int64_t n, const void *a, void *b, int f64, int nb, hipStream_t st);
+hipError_t launch_stream_read(const void *a, int64_t n16, int32_t *sink, int nb, hipStream_t st);
 hipError_t launch_zero(int64_t n, void *a, int esz, int nb, hipStream_t st);
 
 }  // namespace rg

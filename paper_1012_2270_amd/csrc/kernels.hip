@@ -66,6 +66,19 @@ template <> struct Val<RGCSR_BF16> {
 
 template <class T> __device__ __forceinline__ T ldnt(const T *p) { return __builtin_nontemporal_load(p); }
 
+// Load policy of the SpMV, an ablation of where x and the matrix streams live
+// (after the paper's texture-cache study): 0 = value/column streams
+// nontemporal, x gathers cached (the default); 1 = every load cached;
+// 2 = x gathers nontemporal as well.
+template <int LP, class T> __device__ __forceinline__ T ld_stream(const T *p) {
+    if constexpr (LP == 1) return *p;
+    else return __builtin_nontemporal_load(p);
+}
+template <int LP, class T> __device__ __forceinline__ T ld_x(const T *p) {
+    if constexpr (LP == 2) return __builtin_nontemporal_load(p);
+    else return *p;
+}
+
 // Read-only metadata through the constant address space: with a uniform index
 // the compiler issues scalar loads, which need no vector registers and do not
 // wait on outstanding vector loads.
@@ -220,14 +233,18 @@ template <int K> constexpr int unroll_for() { return K == 1 ? 8 : (K <= 4 ? 4 : 
 // X[c * ldx] for one right-hand side with a 32-bit byte offset from the
 // uniform base (scalar base + vector offset addressing; the host checks
 // n_cols * ldx * size < 4 GiB for single right-hand-side launches).
-template <class A> __device__ __forceinline__ A ldx32(const A *X, int32_t c, uint32_t row_bytes) {
-    return *(const A *)((const char *)X + (uint32_t)c * row_bytes);
+template <int LP, class A> __device__ __forceinline__ A ldx32(const A *X, int32_t c, uint32_t row_bytes) {
+    return ld_x<LP>((const A *)((const char *)X + (uint32_t)c * row_bytes));
 }
 
 // Row groups when every lane of a wavefront belongs to the same group
 // (G*T a multiple of 64): the group pointers are scalar, value/column loads
-// use 32-bit offsets from the group's first slot.
-template <int VD, class A, int K, int T, int R, bool PAD>
+// use 32-bit offsets from the group's first slot.  PAD: 0 = loads and
+// multiplies stop at the row length (the RgCSR kernel of Section 3.4); 1 =
+// loads run over the group width, multiplies stop at the row length; 2 =
+// sliced ELLPACK (Section 3.3): no row lengths, every slot of the group width
+// is multiplied, padding included.
+template <int VD, class A, int K, int T, int R, int PAD, int LP>
 __device__ __forceinline__ void spmv_groups_uniform(const SpmvParams &P, int32_t first, int lane) {
     using V = Val<VD>;
     using S = typename V::S;
@@ -251,8 +268,10 @@ __device__ __forceinline__ void spmv_groups_uniform(const SpmvParams &P, int32_t
         ok[r] = t < m.sg;
         rowi[r] = (int32_t)m.row0 + t;
         // unconditional loads at a clamped index (no branch around them);
-        // the output row is fetched now so the final store does not wait
-        len[r] = P.short_len[ok[r] ? rowi[r] : 0];
+        // the output row is fetched now so the final store does not wait.
+        // PAD == 2 (sliced ELLPACK) reads no row lengths.
+        if constexpr (PAD != 2) len[r] = P.short_len[ok[r] ? rowi[r] : 0];
+        else len[r] = 0;
         orow[r] = P.perm ? P.short_row[ok[r] ? rowi[r] : 0] : rowi[r];
         stride[r] = m.sg * T;
         const bool has = m.g1 > m.g0;
@@ -296,18 +315,20 @@ __device__ __forceinline__ void spmv_groups_uniform(const SpmvParams &P, int32_t
 #pragma unroll
             for (int u = 0; u < U; u++) {
                 const uint32_t o = c0 + u < nl[r] ? (uint32_t)(off0[r] + (c0 + u) * stride[r]) : 0u;
-                v[r][u] = ldnt((const S *)((const char *)vb[r] + o * (uint32_t)sizeof(S)));
-                ci[r][u] = ldnt((const int32_t *)((const char *)cb[r] + o * 4u));
+                v[r][u] = ld_stream<LP>((const S *)((const char *)vb[r] + o * (uint32_t)sizeof(S)));
+                ci[r][u] = ld_stream<LP>((const int32_t *)((const char *)cb[r] + o * 4u));
             }
+        // steps multiplied: up to the row length, or (PAD == 2) every slot of
+        // the group width, padding included
         int n[R];
 #pragma unroll
-        for (int r = 0; r < R; r++) n[r] = len[r] > q ? (len[r] - q + T - 1) / T : 0;
+        for (int r = 0; r < R; r++) n[r] = PAD == 2 ? nl[r] : (len[r] > q ? (len[r] - q + T - 1) / T : 0);
 #pragma unroll
         for (int r = 0; r < R; r++)
 #pragma unroll
             for (int u = 0; u < U; u++) {
                 const int32_t c = c0 + u < n[r] ? ci[r][u] : 0;
-                if constexpr (K == 1) xv[r][u][0] = ldx32(X, c, xrow);
+                if constexpr (K == 1) xv[r][u][0] = ldx32<LP>(X, c, xrow);
                 else load_row<A, K>(X + (int64_t)c * P.ldx, xv[r][u]);
             }
 #pragma unroll
@@ -337,7 +358,7 @@ __device__ __forceinline__ void spmv_groups_uniform(const SpmvParams &P, int32_t
 
 // Row groups of fewer than 64 lanes (several groups per wavefront): one row
 // per lane, per-lane group metadata.
-template <int VD, class A, int K, int T>
+template <int VD, class A, int K, int T, int LP>
 __device__ __forceinline__ void spmv_groups_lane(const SpmvParams &P, int32_t w, int lane) {
     using V = Val<VD>;
     using S = typename V::S;
@@ -357,8 +378,8 @@ __device__ __forceinline__ void spmv_groups_lane(const SpmvParams &P, int32_t w,
 #pragma unroll
         for (int u = 0; u < U; u++) {
             const int64_t s = c0 + u < n ? L.base + (int64_t)(c0 + u) * L.stride : L.base;
-            v[u] = ldnt(vals + s);
-            ci[u] = ldnt(P.slot_col + s);
+            v[u] = ld_stream<LP>(vals + s);
+            ci[u] = ld_stream<LP>(P.slot_col + s);
         }
 #pragma unroll
         for (int u = 0; u < U; u++) load_row<A, K>(X + (int64_t)ci[u] * P.ldx, xv[u]);
@@ -385,31 +406,32 @@ __device__ __forceinline__ void spmv_groups_lane(const SpmvParams &P, int32_t w,
     }
 }
 
-template <int VD, class A, int K, int T, int R>
+template <int VD, class A, int K, int T, int R, int LP>
 __device__ __forceinline__ void spmv_groups_fixed(const SpmvParams &P, int32_t first, int lane) {
-    if (P.pad) spmv_groups_uniform<VD, A, K, T, R, true>(P, first, lane);
-    else spmv_groups_uniform<VD, A, K, T, R, false>(P, first, lane);
+    if (P.pad == 2) spmv_groups_uniform<VD, A, K, T, R, 2, LP>(P, first, lane);
+    else if (P.pad) spmv_groups_uniform<VD, A, K, T, R, 1, LP>(P, first, lane);
+    else spmv_groups_uniform<VD, A, K, T, R, 0, LP>(P, first, lane);
 }
 
 // R > 0: every wavefront takes R consecutive wave items.  R = 0: wavefront w
 // takes the run of wave items that item word w names (first item << 2 |
 // log2 of the run length), so narrow groups are packed several to a
 // wavefront and wide ones run alone.
-template <int VD, class A, int K, int T, int R>
+template <int VD, class A, int K, int T, int R, int LP>
 __device__ __forceinline__ void spmv_short(const SpmvParams &P, int32_t w, int lane) {
     if constexpr (R == 0) {
         const int32_t it = ldc(P.short_items, w);
         const int32_t first = it >> 2;
         switch (it & 3) {
-            case 0: spmv_groups_fixed<VD, A, K, T, 1>(P, first, lane); break;
-            case 1: spmv_groups_fixed<VD, A, K, T, 2>(P, first, lane); break;
-            case 2: spmv_groups_fixed<VD, A, K, T, 4>(P, first, lane); break;
-            default: spmv_groups_fixed<VD, A, K, T, 8>(P, first, lane); break;
+            case 0: spmv_groups_fixed<VD, A, K, T, 1, LP>(P, first, lane); break;
+            case 1: spmv_groups_fixed<VD, A, K, T, 2, LP>(P, first, lane); break;
+            case 2: spmv_groups_fixed<VD, A, K, T, 4, LP>(P, first, lane); break;
+            default: spmv_groups_fixed<VD, A, K, T, 8, LP>(P, first, lane); break;
         }
     } else if (P.wpg > 0) {
-        spmv_groups_fixed<VD, A, K, T, R>(P, w * R, lane);
+        spmv_groups_fixed<VD, A, K, T, R, LP>(P, w * R, lane);
     } else if constexpr (R == 1) {
-        spmv_groups_lane<VD, A, K, T>(P, w, lane);
+        spmv_groups_lane<VD, A, K, T, LP>(P, w, lane);
     }
 }
 
@@ -417,7 +439,7 @@ __device__ __forceinline__ void spmv_short(const SpmvParams &P, int32_t w, int l
 // relative to uniform bases vb/cb (scalar base + vector offset addressing).
 // Branch-free unrolled body as in the row groups: out-of-range steps re-read
 // the lane's first element (valid whenever the loop runs) and are masked.
-template <int VD, class A, int K, int U>
+template <int VD, class A, int K, int U, int LP>
 __device__ __forceinline__ void strided_dot32(const typename Val<VD>::S *vb, const int32_t *cb, const A *X,
                                               int64_t ldx, uint32_t xrow, int32_t o, int32_t e, int32_t stride,
                                               A (&acc)[K]) {
@@ -430,12 +452,12 @@ __device__ __forceinline__ void strided_dot32(const typename Val<VD>::S *vb, con
 #pragma unroll
         for (int u = 0; u < U; u++) {
             const uint32_t oo = (uint32_t)(o0 + u * stride < e ? o0 + u * stride : o);
-            v[u] = ldnt((const S *)((const char *)vb + oo * (uint32_t)sizeof(S)));
-            ci[u] = ldnt((const int32_t *)((const char *)cb + oo * 4u));
+            v[u] = ld_stream<LP>((const S *)((const char *)vb + oo * (uint32_t)sizeof(S)));
+            ci[u] = ld_stream<LP>((const int32_t *)((const char *)cb + oo * 4u));
         }
 #pragma unroll
         for (int u = 0; u < U; u++) {
-            if constexpr (K == 1) xv[u][0] = ldx32(X, ci[u], xrow);
+            if constexpr (K == 1) xv[u][0] = ldx32<LP>(X, ci[u], xrow);
             else load_row<A, K>(X + (int64_t)ci[u] * ldx, xv[u]);
         }
 #pragma unroll
@@ -454,7 +476,7 @@ __device__ __forceinline__ void strided_dot32(const typename Val<VD>::S *vb, con
 // Long rows of at most kWaveRowMax nonzeros: it.b consecutive rows of the
 // long list with it.c lanes each.  Their nonzeros are contiguous, so offsets
 // are taken from the item's first nonzero (a scalar load).
-template <int VD, class A, int K>
+template <int VD, class A, int K, int LP>
 __device__ __forceinline__ void spmv_wave_long(const SpmvParams &P, int32_t w, int lane) {
     using S = typename Val<VD>::S;
     A *Y = (A *)P.y;
@@ -474,7 +496,7 @@ __device__ __forceinline__ void spmv_wave_long(const SpmvParams &P, int32_t w, i
 #pragma unroll
     for (int k = 0; k < K; k++) acc[k] = A(0);
     constexpr int U = K == 1 ? kWaveUnroll : unroll_for<K>();
-    strided_dot32<VD, A, K, U>(vb, cb, X, P.ldx, (uint32_t)(P.ldx * (int64_t)sizeof(A)), b + q, e, TL, acc);
+    strided_dot32<VD, A, K, U, LP>(vb, cb, X, P.ldx, (uint32_t)(P.ldx * (int64_t)sizeof(A)), b + q, e, TL, acc);
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1)
         if (off < TL)
@@ -489,7 +511,7 @@ __device__ __forceinline__ void spmv_wave_long(const SpmvParams &P, int32_t w, i
 // bounds and every lane is busy; the products go to this wavefront's LDS
 // slice and the item's lane-per-row mapping then sums them in the same
 // strided order as spmv_wave_long.
-template <int VD>
+template <int VD, int LP>
 __device__ __forceinline__ void spmv_wave_long_lds(const SpmvParams &P, int32_t w, int lane, float *buf) {
     using V = Val<VD>;
     using S = typename V::S;
@@ -508,8 +530,8 @@ __device__ __forceinline__ void spmv_wave_long_lds(const SpmvParams &P, int32_t 
 #pragma unroll
     for (int u = 0; u < U; u++) {
         const uint32_t o = lane + 64 * u < n ? (uint32_t)(lane + 64 * u) : 0u;
-        v[u] = ldnt((const S *)((const char *)vb + o * (uint32_t)sizeof(S)));
-        ci[u] = ldnt((const int32_t *)((const char *)cb + o * 4u));
+        v[u] = ld_stream<LP>((const S *)((const char *)vb + o * (uint32_t)sizeof(S)));
+        ci[u] = ld_stream<LP>((const int32_t *)((const char *)cb + o * 4u));
     }
     // row bounds and output row of this lane, needed only after the gathers
     const int TL = it.c;
@@ -520,7 +542,7 @@ __device__ __forceinline__ void spmv_wave_long_lds(const SpmvParams &P, int32_t 
     const int32_t b = (int32_t)(P.long_ptr[li] - item0), e = (int32_t)(P.long_ptr[li + 1] - item0);
     const int32_t orow = P.long_row[li];
 #pragma unroll
-    for (int u = 0; u < U; u++) xv[u] = ldx32(X, ci[u], xrow);
+    for (int u = 0; u < U; u++) xv[u] = ldx32<LP>(X, ci[u], xrow);
 #pragma unroll
     for (int u = 0; u < U; u++) buf[lane + 64 * u] = V::template cvt<float>(v[u]) * xv[u];
     if (lane == 0) buf[kWaveRowMax] = 0.f;  // terms past a row read this slot
@@ -543,7 +565,7 @@ __device__ __forceinline__ void spmv_wave_long_lds(const SpmvParams &P, int32_t 
 
 // One chunk (at most kBlockChunk nonzeros) of a very long row, reduced by the
 // whole workgroup in LDS.
-template <int VD, class A, int K>
+template <int VD, class A, int K, int LP>
 __device__ __forceinline__ void spmv_block_item(const SpmvParams &P, int32_t u, A (*red)[K]) {
     using S = typename Val<VD>::S;
     A *Y = (A *)P.y;
@@ -556,7 +578,7 @@ __device__ __forceinline__ void spmv_block_item(const SpmvParams &P, int32_t u, 
 #pragma unroll
     for (int k = 0; k < K; k++) acc[k] = A(0);
     constexpr int U = K == 1 ? 16 : unroll_for<K>();
-    strided_dot32<VD, A, K, U>((const S *)P.long_val + beg, P.long_col + beg, X, P.ldx,
+    strided_dot32<VD, A, K, U, LP>((const S *)P.long_val + beg, P.long_col + beg, X, P.ldx,
                                (uint32_t)(P.ldx * (int64_t)sizeof(A)), (int32_t)threadIdx.x, n, kBlockThreads, acc);
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1)
@@ -579,27 +601,27 @@ __device__ __forceinline__ void spmv_block_item(const SpmvParams &P, int32_t u, 
     __syncthreads();
 }
 
-template <int VD, class A, int K, int T, int R, bool LONG>
+template <int VD, class A, int K, int T, int R, bool LONG, int LP>
 __device__ __forceinline__ void spmv_unit(const SpmvParams &P, int32_t u, int lane, int wv, A (*red)[K], float *lbuf) {
     constexpr bool kLdsLong = LONG && K == 1 && sizeof(A) == 4;
     if (LONG && u < P.n_block_items) {
-        spmv_block_item<VD, A, K>(P, u, red);
+        spmv_block_item<VD, A, K, LP>(P, u, red);
         return;
     }
     const int32_t w = __builtin_amdgcn_readfirstlane((u - (LONG ? P.n_block_items : 0)) * kBlockWaves + wv);
     if (w >= P.n_wave_items) return;
     if (LONG && w < P.n_wave_long) {
-        if constexpr (kLdsLong) spmv_wave_long_lds<VD>(P, w, lane, lbuf);
-        else spmv_wave_long<VD, A, K>(P, w, lane);
+        if constexpr (kLdsLong) spmv_wave_long_lds<VD, LP>(P, w, lane, lbuf);
+        else spmv_wave_long<VD, A, K, LP>(P, w, lane);
     } else {
-        spmv_short<VD, A, K, T, R>(P, w - (LONG ? P.n_wave_long : 0), lane);
+        spmv_short<VD, A, K, T, R, LP>(P, w - (LONG ? P.n_wave_long : 0), lane);
     }
 }
 
 // A single right-hand side runs one unit per workgroup (the grid covers every
 // unit, so nothing stays live across units); several right-hand sides may run
 // a persistent grid that strides over the units.
-template <int VD, class A, int K, int T, int R, bool LONG>
+template <int VD, class A, int K, int T, int R, bool LONG, int LP>
 __global__ __launch_bounds__(kBlockThreads) void rgcsr_spmv_k(SpmvParams P) {
     constexpr bool kLdsLong = LONG && K == 1 && sizeof(A) == 4;
     __shared__ A red[kBlockWaves][K];
@@ -609,10 +631,10 @@ __global__ __launch_bounds__(kBlockThreads) void rgcsr_spmv_k(SpmvParams P) {
     const int nwg = gridDim.x;
     if constexpr (K == 1) {
         const int32_t u = first_unit(blockIdx.x, nwg, P.n_long_units);
-        if (u < P.total_units) spmv_unit<VD, A, K, T, R, LONG>(P, u, lane, wv, red, lbuf[kLdsLong ? wv : 0]);
+        if (u < P.total_units) spmv_unit<VD, A, K, T, R, LONG, LP>(P, u, lane, wv, red, lbuf[kLdsLong ? wv : 0]);
     } else {
         for (int32_t u = first_unit(blockIdx.x, nwg, P.n_long_units); u < P.total_units; u += nwg)
-            spmv_unit<VD, A, K, T, R, LONG>(P, u, lane, wv, red, lbuf[0]);
+            spmv_unit<VD, A, K, T, R, LONG, LP>(P, u, lane, wv, red, lbuf[0]);
     }
 }
 
@@ -941,13 +963,27 @@ __global__ __launch_bounds__(256) void fill_k(int64_t n, VT *a, VT v) {
 // ---------------------------------------------------------------------------
 static hipError_t check_launch() { return hipGetLastError(); }
 
-template <int VD, class A, int K, int T, int R>
+template <int VD, class A, int K, int T, int R, int LP = 0>
 static hipError_t launch_spmv_t(const SpmvParams &P, int nwg, hipStream_t st) {
     if (P.n_block_items + P.n_wave_long > 0)
-        hipLaunchKernelGGL((rgcsr_spmv_k<VD, A, K, T, R, true>), dim3(nwg), dim3(kBlockThreads), 0, st, P);
+        hipLaunchKernelGGL((rgcsr_spmv_k<VD, A, K, T, R, true, LP>), dim3(nwg), dim3(kBlockThreads), 0, st, P);
     else
-        hipLaunchKernelGGL((rgcsr_spmv_k<VD, A, K, T, R, false>), dim3(nwg), dim3(kBlockThreads), 0, st, P);
+        hipLaunchKernelGGL((rgcsr_spmv_k<VD, A, K, T, R, false, LP>), dim3(nwg), dim3(kBlockThreads), 0, st, P);
     return check_launch();
+}
+
+// Load policies other than the default: FP32 values and vectors, one
+// right-hand side, one lane per row.
+template <int LP>
+static hipError_t launch_spmv_lp(const SpmvParams &P, int R, int nwg, hipStream_t st) {
+    switch (R) {
+    case 0: return launch_spmv_t<RGCSR_F32, float, 1, 1, 0, LP>(P, nwg, st);
+    case 1: return launch_spmv_t<RGCSR_F32, float, 1, 1, 1, LP>(P, nwg, st);
+    case 2: return launch_spmv_t<RGCSR_F32, float, 1, 1, 2, LP>(P, nwg, st);
+    case 4: return launch_spmv_t<RGCSR_F32, float, 1, 1, 4, LP>(P, nwg, st);
+    case 8: return launch_spmv_t<RGCSR_F32, float, 1, 1, 8, LP>(P, nwg, st);
+    }
+    return hipErrorInvalidValue;
 }
 
 // One lane per row (T = 1) takes R in {1, 2, 4, 8} rows per lane, or R = 0
@@ -1014,7 +1050,14 @@ hipError_t launch_combine(const LongItem *items, int32_t n, const int32_t *long_
     return launch_combine_a<float>(items, n, long_row, partial, Y, ldy, K, st);
 }
 
-hipError_t launch_spmv(const SpmvParams &P, int vdt, int vec_f64, int T, int K, int R, int nwg, hipStream_t st) {
+hipError_t launch_spmv(const SpmvParams &P, int vdt, int vec_f64, int T, int K, int R, int load_policy, int nwg,
+                       hipStream_t st) {
+    if (load_policy != 0) {
+        if (vec_f64 || vdt != RGCSR_F32 || K != 1 || T != 1) return hipErrorNotSupported;
+        if (load_policy == 1) return launch_spmv_lp<1>(P, R, nwg, st);
+        if (load_policy == 2) return launch_spmv_lp<2>(P, R, nwg, st);
+        return hipErrorInvalidValue;
+    }
     if (vec_f64) {
         if (vdt == RGCSR_F64) return launch_spmv_vk<RGCSR_F64, double>(P, T, K, R, nwg, st);
         if (vdt == RGCSR_F32) return launch_spmv_vk<RGCSR_F32, double>(P, T, K, R, nwg, st);
@@ -1217,6 +1260,23 @@ hipError_t launch_copy(int64_t n, const void *a, void *b, int f64, int nb, hipSt
         hipLaunchKernelGGL((copy_k<double>), dim3(nb), dim3(256), 0, st, n, (const double *)a, (double *)b);
     else
         hipLaunchKernelGGL((copy_k<float>), dim3(nb), dim3(256), 0, st, n, (const float *)a, (float *)b);
+    return check_launch();
+}
+
+// Streaming read of n 16-byte words with the matrix streams' nontemporal
+// loads; the sum is stored only in a case no data reaches in practice, which
+// keeps every load live.
+__global__ __launch_bounds__(256) void stream_read_k(const i32x4 *a, int64_t n, int32_t *sink) {
+    i32x4 acc = {0, 0, 0, 0};
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
+        acc ^= __builtin_nontemporal_load(a + i);
+    const int32_t v = acc.x ^ acc.y ^ acc.z ^ acc.w;
+    if (v == 0x5bd1e995) sink[0] = v;
+}
+
+hipError_t launch_stream_read(const void *a, int64_t n16, int32_t *sink, int nb, hipStream_t st) {
+    if (n16 == 0) return hipSuccess;
+    hipLaunchKernelGGL(stream_read_k, dim3(nb), dim3(256), 0, st, (const i32x4 *)a, n16, sink);
     return check_launch();
 }
 

@@ -123,14 +123,15 @@ def test_zipf_sorted_with_long_rows(torch_cuda, oracle):
 @pytest.mark.parametrize("sigma,tau", [(4096, 32), (512, 16), (1, -1), (1 << 40, 24)])
 def test_rows_per_lane_schedules_agree(torch_cuda, oracle, sigma, tau):
     """Every kernel schedule (rows per lane fixed at 1, 2, 4, 8 or chosen per
-    wavefront; loads over the group width or the row length) multiplies each
-    row in the same serial order, so all give the same bits, within tolerance
-    of the oracle."""
+    wavefront; loads over the group width or the row length; sliced ELLPACK,
+    which multiplies the padding) multiplies each row in the same serial
+    order, so all give the same values (padding adds only zeros for finite x),
+    within tolerance of the oracle."""
     A = W.zipf_matrix(150_001, seed=9)
     x = W.uniform_vector(A.n_cols, 16, np.float32)
     ref = None
     for R in (0, 1, 2, 4, 8):
-        for pad in (0, 1):
+        for pad in (0, 1, 2):
             say("schedules zipf 150001", sigma, tau, R, pad)
             M = rg.rgcsr_from_csr(A, G=64, sigma=sigma, tau=tau, rows_per_lane=R, pad_loads=pad)
             assert (M.info["rows_per_lane"] == R or R == 0) and M.info["pad_loads"] == pad
@@ -140,7 +141,54 @@ def test_rows_per_lane_schedules_agree(torch_cuda, oracle, sigma, tau):
                 check_spmv(oracle, A, x, y)
                 ref = y
             else:
+                np.testing.assert_array_equal(y, ref)
+
+
+@pytest.mark.parametrize("G,T,sigma,tau", [(64, 1, 1, -1), (128, 1, 1 << 40, 32), (64, 2, 1, -1), (32, 2, 4096, 8)])
+def test_sliced_ellpack_mode(torch_cuda, oracle, G, T, sigma, tau):
+    """Sliced ELLPACK over the same layout (no row lengths, padding
+    multiplied) equals RgCSR for finite x, including lanes_per_row > 1."""
+    A = W.random_csr(3001, 2500, seed=21, max_len=70, empty_frac=0.2, long_rows=5, long_len=2300,
+                     dtype=np.float32)
+    x = W.uniform_vector(A.n_cols, 17, np.float32)
+    say("sliced ELLPACK", G, T, sigma, tau)
+    M = rg.rgcsr_from_csr(A, G=G, T=T, sigma=sigma, tau=tau, pad_loads=1)
+    E = rg.rgcsr_from_csr(A, G=G, T=T, sigma=sigma, tau=tau, pad_loads=2)
+    assert E.info["pad_loads"] == 2
+    y, ye = host(M.spmv(dev(x))), host(E.spmv(dev(x)))
+    check_spmv(oracle, A, x, ye)
+    np.testing.assert_array_equal(ye, y)
+    with pytest.raises(rg.RgcsrError) as e:   # groups narrower than a wavefront
+        rg.rgcsr_from_csr(A, G=16, T=1, pad_loads=2)
+    assert e.value.status == 6
+
+
+def test_load_policies_same_result(torch_cuda, oracle):
+    """Cached streams (1) and nontemporal x (2) change only cache hints: the
+    bits equal the default policy's; unsupported combinations are errors."""
+    torch = torch_cuda
+    A = W.zipf_matrix(120_000, seed=10)
+    x = W.uniform_vector(A.n_cols, 18, np.float32)
+    ref = None
+    for lay in (dict(sigma=1, tau=-1), dict(sigma=512, tau=16)):
+        for lp in (0, 1, 2):
+            say("load policy", lay, lp)
+            M = rg.rgcsr_from_csr(A, G=64, load_policy=lp, **lay)
+            assert M.info["load_policy"] == lp
+            y = host(M.spmv(dev(x)))
+            M.close()
+            if lp == 0:
+                check_spmv(oracle, A, x, y)
+                ref = y
+            else:
                 np.testing.assert_array_equal(y.view(np.uint32), ref.view(np.uint32))
+    with pytest.raises(rg.RgcsrError) as e:
+        rg.rgcsr_from_csr(A, G=64, load_policy=1, value_dtype="f64")
+    assert e.value.status == 6
+    M = rg.rgcsr_from_csr(A, G=64, load_policy=2)
+    with pytest.raises(rg.RgcsrError) as e:
+        M.spmv(torch.zeros(A.n_cols, dtype=torch.float64, device="cuda:0"))
+    assert e.value.status == 6
 
 
 def test_deterministic_repeat(torch_cuda, oracle):
@@ -230,6 +278,23 @@ def test_errors_surface_as_status(torch_cuda):
     Md = rg.rgcsr_from_csr(A, value_dtype="f64")
     with pytest.raises(rg.RgcsrError):
         Md.spmv(torch.zeros(100, device="cuda:0"))
+
+
+def test_stream_read_helper(torch_cuda):
+    """The bandwidth probe reads any 16-byte multiple and rejects bad sizes."""
+    torch = torch_cuda
+    buf = torch.zeros(1 << 22, dtype=torch.uint8, device="cuda:0")
+    sink = torch.zeros(1, dtype=torch.int32, device="cuda:0")
+    rg.rgcsr_stream_read(buf, sink)
+    rg.rgcsr_stream_read(buf[:16], sink)
+    torch.cuda.synchronize()
+    assert int(sink.item()) == 0  # all-zero data never reaches the store
+    with pytest.raises(rg.RgcsrError) as e:
+        rg._lib.call("rgcsr_stream_read", buf.data_ptr(), 17, sink.data_ptr(), 0)
+    assert e.value.status == 1
+    with pytest.raises(rg.RgcsrError) as e:
+        rg._lib.call("rgcsr_stream_read", buf.data_ptr() + 4, 16, sink.data_ptr(), 0)
+    assert e.value.status == 1
 
 
 @pytest.mark.slow
