@@ -449,6 +449,65 @@ def bench_variants(args, torch, rg, W):
     print(json.dumps(out), flush=True)
 
 
+def bench_ordering(args, torch, rg, W):
+    """Row-ordering study (x locality): the 7-point stencil as generated, under
+    a random symmetric permutation, that permutation followed by a global
+    descending sort, and followed by Reverse Cuthill-McKee; the Zipf matrix as
+    generated and under RCM.  RgCSR and Hybrid, FP32, from HBM."""
+    import oracle
+
+    def stats(A):
+        rows = np.repeat(np.arange(A.n_rows, dtype=np.int64), np.diff(A.row_ptr))
+        d = np.abs(rows - A.col)
+        return {"bandwidth": int(d.max()), "mean_abs_offset": float(d.mean())}
+
+    def timed(A, x, lay):
+        base = rg.rgcsr_from_csr(A, **lay)
+        hyb = rg.hyb_from_csr(A)
+        res = {"slots": base.info["slots"], "long_nnz": base.info["long_nnz"]}
+        for name, H, fn in (("rgcsr", base, rg.rgcsr_spmv), ("hybrid", hyb, rg.hyb_spmv)):
+            per = H.info["device_bytes"] + 4 * (A.n_rows + A.n_cols)
+            copies = max(1, math.ceil(ROTATE_BYTES / per))
+            hs = [H] + [H.clone() for _ in range(copies - 1)]
+            xs = [torch.from_numpy(x).to("cuda:0") for _ in range(copies)]
+            ys = [torch.empty(A.n_rows, device="cuda:0") for _ in range(copies)]
+            for i in range(args.warmup):
+                fn(hs[i % copies], xs[i % copies], ys[i % copies])
+            t = float(np.mean(_events(torch, lambda i: fn(hs[i % copies], xs[i % copies], ys[i % copies]),
+                                      args.steps)))
+            fn(hs[0], xs[0], ys[0])
+            err = oracle.scaled_error(ys[0].cpu().numpy(), oracle.csr_spmv(A, x), oracle.csr_absmv(A, x))
+            b = alg_bytes(A.nnz, A.n_rows, A.n_cols, base.info["n_groups"])
+            res[name] = {"us": t * 1e3, "gbs": b / (t * 1e-3) / 1e9, "max_scaled_error": err}
+            for h in hs[1:]:
+                h.close()
+        return res
+
+    out = {"metric": "SpMV time under row orderings (x locality), FP32", "results": []}
+    S, xs = W.workload_laplace3d(128)
+    t0 = time.time()
+    Ss, _ = W.scrambled(S, 9)
+    ps = time.time() - t0
+    t0 = time.time()
+    prcm = rg.rgcsr_rcm_order(Ss)
+    rcm_s = time.time() - t0
+    Srcm = W.permute_symmetric(Ss, prcm)
+    paper = dict(G=64, T=1, sigma=1, tau=-1)
+    for name, A, lay in (("natural", S, paper), ("scrambled", Ss, paper),
+                         ("scrambled+descending", Ss, dict(G=64, T=1, sigma=1 << 40, tau=-1)),
+                         ("scrambled+rcm", Srcm, paper)):
+        out["results"].append({"matrix": "laplace3d_7pt_128", "ordering": name, **stats(A), **timed(A, xs, lay)})
+    Z, xz = W.workload_zipf(1_000_000)
+    t0 = time.time()
+    pz = rg.rgcsr_rcm_order(Z)
+    rcm_z = time.time() - t0
+    Zr = W.permute_symmetric(Z, pz)
+    for name, A, lay in (("natural", Z, LAYOUT_ZIPF), ("rcm", Zr, LAYOUT_ZIPF)):
+        out["results"].append({"matrix": "zipf2_1e6", "ordering": name, **stats(A), **timed(A, xz, lay)})
+    out["rcm_seconds"] = {"laplace3d_7pt_128_scrambled": rcm_s, "zipf2_1e6": rcm_z, "scramble_s": ps}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -459,7 +518,7 @@ def main():
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a 1 GiB device copy (for scaling the HBM byte counters)")
     ap.add_argument("--config", default="spmv",
-                    choices=["spmv", "spmm", "batched", "cg", "grad", "fp64", "variants"],
+                    choices=["spmv", "spmm", "batched", "cg", "grad", "fp64", "variants", "ordering"],
                     help="spmv (default, the contract line) or another form of the path")
     ap.add_argument("--batch-count", type=int, default=4096)
     ap.add_argument("--cg-n", type=int, default=160)
@@ -489,7 +548,7 @@ def main():
     rg._lib.load()
     if args.config != "spmv":
         {"spmm": bench_spmm, "batched": bench_batched, "cg": bench_cg, "grad": bench_grad,
-         "fp64": bench_fp64, "variants": bench_variants}[args.config](
+         "fp64": bench_fp64, "variants": bench_variants, "ordering": bench_ordering}[args.config](
             args, torch, rg, W)
         return
     log("generating matrices ...")

@@ -347,6 +347,23 @@ const char *rgcsr_last_error(void);
 /* Library version string, e.g. "rgcsr 0.1 gfx950". */
 const char *rgcsr_version(void);
 
+/* ---- Row ordering (host only) ------------------------------------------------ */
+
+/* Reverse Cuthill-McKee ordering of the symmetrised sparsity pattern of a
+ * square host CSR matrix (row_ptr[n+1], col_idx[nnz]; validated like
+ * rgcsr_from_csr).  The paper studies row orderings for padding and x cache
+ * use (Section 4.4.2, Table 7: descending length and AMD) and leaves orderings
+ * that improve x locality to future work (Section 5); this bandwidth-reducing
+ * ordering stands in for AMD.  Rule: i ~ j when i != j and a_ij or a_ji is
+ * stored; components are started from the unnumbered vertex of smallest
+ * (degree, index); the unnumbered neighbours of each numbered vertex are
+ * numbered in (degree, index) order (Cuthill and McKee, 1969); the sequence
+ * is reversed (George, 1971).  Writes perm[new] = old (n int32, caller-owned
+ * host memory); apply it to rows and columns alike (A' = P A P^T, x' = P x,
+ * y = P^T y').  RGCSR_ECSR on malformed input, RGCSR_EOVERFLOW for n >= 2^31. */
+rgcsr_status rgcsr_rcm_order(int64_t n, int64_t nnz, const int64_t *row_ptr, const int32_t *col_idx,
+                             int32_t *perm);
+
 /* ---- Measurement helper ----------------------------------------------------- */
 
 /* Reads `bytes` bytes of device memory at buf with the nontemporal 16-byte

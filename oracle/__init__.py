@@ -331,6 +331,43 @@ def hyb_spmv(H: dict, x, bf16_bits: bool = False) -> np.ndarray:
 # ----------------------------------------------------------------------------
 # Judging a floating-point result
 # ----------------------------------------------------------------------------
+def rcm_order(A) -> np.ndarray:
+    """Reverse Cuthill-McKee order of a square CSR matrix, perm[new] = old, in
+    plain Python from the published definition (Cuthill and McKee, 1969;
+    reversed by George, 1971); the row-ordering study the paper leaves to
+    future work (Section 4.4.2, Table 7, Section 5).  Graph: i ~ j for i != j
+    when a_ij or a_ji is stored.  Each component starts at the unnumbered
+    vertex of smallest (degree, index); a numbered vertex numbers its
+    unnumbered neighbours in (degree, index) order; the sequence is reversed.
+    For small matrices (a Python loop per edge)."""
+    n = A.n_rows
+    assert A.n_cols == n
+    nbrs = [set() for _ in range(n)]
+    for i in range(n):
+        for k in range(int(A.row_ptr[i]), int(A.row_ptr[i + 1])):
+            j = int(A.col[k])
+            if j != i:
+                nbrs[i].add(j)
+                nbrs[j].add(i)
+    deg = [len(s) for s in nbrs]
+    key = lambda v: (deg[v], v)
+    numbered = [False] * n
+    order = []
+    for s in sorted(range(n), key=key):
+        if numbered[s]:
+            continue
+        numbered[s] = True
+        order.append(s)
+        head = len(order) - 1
+        while head < len(order):
+            v = order[head]
+            head += 1
+            for u in sorted((u for u in nbrs[v] if not numbered[u]), key=key):
+                numbered[u] = True
+                order.append(u)
+    return np.array(order[::-1], dtype=np.int32)
+
+
 def scaled_error(y, y_ref, s) -> float:
     """max_i |y_i - y_ref_i| / max_i s_i; when max s = 0 the result must be
     exactly zero and the error is 0 or inf."""

@@ -453,6 +453,16 @@ def version() -> str:
     return _lib.load().rgcsr_version().decode()
 
 
+def rgcsr_rcm_order(A) -> np.ndarray:
+    """Reverse Cuthill-McKee order of a square host CSR matrix: perm[new] = old."""
+    if A.n_rows != A.n_cols:
+        raise ValueError("ordering needs a square matrix")
+    rp, col, _ = _csr_arrays(A)
+    perm = np.empty(A.n_rows, dtype=np.int32)
+    _lib.call("rgcsr_rcm_order", A.n_rows, int(rp[-1]), _ptr(rp), _ptr(col), _ptr(perm))
+    return perm
+
+
 def rgcsr_stream_read(buf, sink, stream=None) -> None:
     """One streaming read of the device tensor buf (the achievable-bandwidth
     probe); sink is a small device tensor the kernel may write."""

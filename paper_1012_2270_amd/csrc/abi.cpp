@@ -472,6 +472,15 @@ const char *rgcsr_last_error(void) { return g_last_error.c_str(); }
 
 const char *rgcsr_version(void) { return "rgcsr 0.1 gfx950"; }
 
+rgcsr_status rgcsr_rcm_order(int64_t n, int64_t nnz, const int64_t *row_ptr, const int32_t *col_idx,
+                             int32_t *perm) {
+    ABI_TRY
+    if (n < 0 || (n > 0 && (!row_ptr || !perm)) || (nnz > 0 && !col_idx)) fail(RGCSR_EINVAL, "bad argument");
+    validate_csr(n, n, nnz, row_ptr, col_idx);
+    rcm_order(n, row_ptr, col_idx, perm);
+    ABI_CATCH
+}
+
 rgcsr_status rgcsr_stream_read(const void *buf, int64_t bytes, void *sink, void *stream) {
     ABI_TRY
     if (!buf || !sink || bytes < 0) fail(RGCSR_EINVAL, "buf and sink must be device pointers, bytes >= 0");

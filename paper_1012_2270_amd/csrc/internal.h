@@ -154,6 +154,10 @@ LayoutParams resolve_opts(const rgcsr_opts *opts);
 void validate_csr(int64_t n_rows, int64_t n_cols, int64_t nnz, const int64_t *rp,
                   const int32_t *col);
 
+// Reverse Cuthill-McKee order of the symmetrised pattern of a square CSR
+// matrix, perm[new] = old (ordering.cpp).
+void rcm_order(int64_t n, const int64_t *rp, const int32_t *col, int32_t *perm);
+
 // Appends the layout of one CSR matrix (values already in the storage dtype,
 // esz bytes each; pad_bytes fills artificial zeros) to L, offsetting rows by
 // L.n_rows and columns by L.n_cols.  When vals is null only sizes and index

@@ -178,6 +178,31 @@ def batched_set(count: int = 4096, n_lo: int = 100, n_hi: int = 20_000,
     return out
 
 
+def permute_symmetric(A: CSR, perm: np.ndarray) -> CSR:
+    """Rows and columns renumbered by perm (perm[new] = old): A'[i, j] =
+    A[perm[i], perm[j]], columns ascending within each row."""
+    n = A.n_rows
+    assert A.n_cols == n and len(perm) == n
+    perm = np.asarray(perm, dtype=np.int64)
+    inv = np.empty(n, dtype=np.int64)
+    inv[perm] = np.arange(n, dtype=np.int64)
+    lens = np.diff(A.row_ptr)[perm]
+    row_ptr = np.zeros(n + 1, dtype=np.int64)
+    np.cumsum(lens, out=row_ptr[1:])
+    src = np.arange(A.nnz, dtype=np.int64) + np.repeat(A.row_ptr[perm] - row_ptr[:-1], lens)
+    new_col = inv[A.col[src]]
+    rows = np.repeat(np.arange(n, dtype=np.int64), lens)
+    order = np.lexsort((new_col, rows))
+    return CSR(n, n, row_ptr, new_col[order].astype(np.int32), A.val[src][order])
+
+
+def scrambled(A: CSR, seed: int) -> tuple[CSR, np.ndarray]:
+    """A under a seeded random symmetric permutation (a matrix with the same
+    structure and no index locality), with that permutation."""
+    perm = np.random.default_rng(seed).permutation(A.n_rows).astype(np.int32)
+    return permute_symmetric(A, perm), perm
+
+
 def random_csr(n_rows: int, n_cols: int, seed: int, max_len: int | None = None,
                empty_frac: float = 0.1, long_rows: int = 0, long_len: int | None = None,
                dtype=np.float64, values: str = "normal") -> CSR:

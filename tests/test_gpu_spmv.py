@@ -191,6 +191,23 @@ def test_load_policies_same_result(torch_cuda, oracle):
     assert e.value.status == 6
 
 
+def test_rcm_reordered_spmv(torch_cuda, oracle):
+    """SpMV of P A P^T on P x is P (A x): the ordering only renumbers."""
+    A = W.zipf_matrix(40_000, seed=5, max_len=500)
+    S, _ = W.scrambled(W.laplacian_3d_7pt(24, dtype=np.float32), 3)
+    for M0 in (A, S):
+        x = W.uniform_vector(M0.n_cols, 19, np.float32)
+        perm = rg.rgcsr_rcm_order(M0)
+        B = W.permute_symmetric(M0, perm)
+        say("rcm reordered", M0.n_rows)
+        M = rg.rgcsr_from_csr(B, G=64, sigma=512, tau=16)
+        y = host(M.spmv(dev(np.ascontiguousarray(x[perm]))))
+        check_spmv(oracle, B, x[perm], y)
+        yo = oracle.csr_spmv(M0, x)[perm]
+        assert np.max(np.abs(y - yo)) <= 1e-5 * max(1.0, float(np.max(oracle.csr_absmv(M0, x))))
+        M.close()
+
+
 def test_deterministic_repeat(torch_cuda, oracle):
     """No atomics in RgCSR SpMV: repeated launches give identical bits, also
     for rows split over several wavefronts."""
