@@ -396,10 +396,11 @@ def bench_fp64(args, torch, rg, W):
 
 def bench_variants(args, torch, rg, W):
     """Kernel-variant study on the benchmark matrices (FP32): loads bounded by
-    the row length, loads over the group width, and sliced ELLPACK (no row
+    the row length, loads over the group width, sliced ELLPACK (no row
     lengths, padding multiplied), each under three load policies (nontemporal
-    matrix streams with cached x, everything cached, x nontemporal too), from
-    HBM (rotating copies) and from the 256 MB cache (one copy)."""
+    matrix streams with cached x, everything cached, x nontemporal too), and
+    row lengths read off the columns (default policy), from HBM (rotating
+    copies) and from the 256 MB cache (one copy)."""
     A1, x1 = W.workload_laplace3d(128)
     A2, x2 = W.workload_zipf(1_000_000)
     A3 = W.stencil_3d_27pt(160, dtype=np.float32)
@@ -409,8 +410,8 @@ def bench_variants(args, torch, rg, W):
                             ("stencil27_160", A3, x3, LAYOUT_STENCIL)):
         xd = torch.from_numpy(x).to("cuda:0")
         ref = None
-        for pad in (0, 1, 2):
-            for lp in (0, 1, 2):
+        for pad in (0, 1, 2, 3):
+            for lp in ((0, 1, 2) if pad != 3 else (0,)):
                 base = rg.rgcsr_from_csr(A, pad_loads=pad, load_policy=lp, **lay)
                 per = base.info["device_bytes"] + 4 * (A.n_rows + A.n_cols)
                 copies = max(1, math.ceil(ROTATE_BYTES / per))

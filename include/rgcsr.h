@@ -90,14 +90,21 @@ typedef struct {
                                largest count whose widest group times the count is at
                                most 16 (several narrow groups share a wavefront, wide
                                ones run alone); only with lanes_per_row = 1, otherwise 1 */
-    int32_t pad_loads;      /* kernel schedule: 1 = value/column loads run over the
-                               group width so they need not wait for the row length
-                               (padding is still never multiplied), 0 = loads stop at
-                               the row length, -1 = 1 when padding is at most 100% of the
-                               grouped nonzeros, else 0; 2 = sliced ELLPACK (Section 3.3):
-                               row lengths are not read and every slot of the group width
-                               is multiplied, padding included (same result for finite x;
-                               needs group_size * lanes_per_row a multiple of 64) */
+    int32_t pad_loads;      /* kernel schedule: 0 = loads stop at the row length;
+                               1 = value/column loads run over the group width so they
+                               need not wait for the row length (padding is still never
+                               multiplied); 3 = as 1, but the row lengths are not read:
+                               columns ascend strictly within a row and padding repeats
+                               the row's last column, so a step is multiplied exactly
+                               when its column exceeds the previous one (needs
+                               lanes_per_row = 1, group_size a multiple of 64 and no
+                               empty grouped row; same bits as 0 and 1); 2 = sliced
+                               ELLPACK (Section 3.3): row lengths are not read and every
+                               slot of the group width is multiplied, padding included
+                               (same values for finite x; needs group_size *
+                               lanes_per_row a multiple of 64); -1 = when padding is at
+                               most 100% of the grouped nonzeros 3 if allowed, else 1,
+                               otherwise 0 */
     int32_t load_policy;    /* where loads may be cached, after the paper's texture-cache
                                study (Section 4.3): 0 (default) = value/column streams
                                nontemporal, x gathers cached; 1 = every load cached;

@@ -240,10 +240,17 @@ void choose_schedule(rgcsr_matrix_s *h, const HostLayout &L, int32_t rows_per_la
     int64_t short_nnz = 0;
     for (int32_t v : L.short_len) short_nnz += v;
     const int64_t pad_slots = L.slots - short_nnz;
-    if (pad_loads < -1 || pad_loads > 2) fail(RGCSR_EINVAL, "pad_loads must be -1, 0, 1 or 2");
-    if (pad_loads == 2 && h->gpw > 0)
-        fail(RGCSR_EUNSUPPORTED, "sliced ELLPACK needs group_size * lanes_per_row a multiple of 64");
-    if (pad_loads < 0) h->pad = pad_slots <= short_nnz ? 1 : 0;
+    if (pad_loads < -1 || pad_loads > 3) fail(RGCSR_EINVAL, "pad_loads must be -1, 0, 1, 2 or 3");
+    if (pad_loads >= 2 && h->gpw > 0)
+        fail(RGCSR_EUNSUPPORTED, "pad_loads 2 and 3 need group_size * lanes_per_row a multiple of 64");
+    // row lengths can be read off the columns when a lane owns a whole row
+    // and no grouped row is empty
+    bool no_empty = true;
+    for (int32_t v : L.short_len) no_empty = no_empty && v > 0;
+    const bool cols_give_len = L.T == 1 && h->gpw == 0 && no_empty;
+    if (pad_loads == 3 && !cols_give_len)
+        fail(RGCSR_EUNSUPPORTED, "pad_loads 3 needs lanes_per_row = 1 and no empty rows among the grouped rows");
+    if (pad_loads < 0) h->pad = pad_slots <= short_nnz ? (cols_give_len ? 3 : 1) : 0;
     else h->pad = pad_loads;
     if (load_policy < 0 || load_policy > 2) fail(RGCSR_EINVAL, "load_policy must be 0, 1 or 2");
     if (load_policy != 0 && (L.vdt != RGCSR_F32 || L.T != 1))

@@ -243,7 +243,11 @@ template <int LP, class A> __device__ __forceinline__ A ldx32(const A *X, int32_
 // multiplies stop at the row length (the RgCSR kernel of Section 3.4); 1 =
 // loads run over the group width, multiplies stop at the row length; 2 =
 // sliced ELLPACK (Section 3.3): no row lengths, every slot of the group width
-// is multiplied, padding included.
+// is multiplied, padding included; 3 = loads over the group width and the row
+// length read off the columns: they ascend strictly within a row and padding
+// repeats the row's last column, so a step is multiplied exactly when its
+// column exceeds the previous step's (one lane per row, no empty rows; the
+// host checks both).
 template <int VD, class A, int K, int T, int R, int PAD, int LP>
 __device__ __forceinline__ void spmv_groups_uniform(const SpmvParams &P, int32_t first, int lane) {
     using V = Val<VD>;
@@ -269,8 +273,8 @@ __device__ __forceinline__ void spmv_groups_uniform(const SpmvParams &P, int32_t
         rowi[r] = (int32_t)m.row0 + t;
         // unconditional loads at a clamped index (no branch around them);
         // the output row is fetched now so the final store does not wait.
-        // PAD == 2 (sliced ELLPACK) reads no row lengths.
-        if constexpr (PAD != 2) len[r] = P.short_len[ok[r] ? rowi[r] : 0];
+        // PAD 2 and 3 read no row lengths.
+        if constexpr (PAD < 2) len[r] = P.short_len[ok[r] ? rowi[r] : 0];
         else len[r] = 0;
         orow[r] = P.perm ? P.short_row[ok[r] ? rowi[r] : 0] : rowi[r];
         stride[r] = m.sg * T;
@@ -306,6 +310,9 @@ __device__ __forceinline__ void spmv_groups_uniform(const SpmvParams &P, int32_t
     // the bound read the group's first slot and x[0], in bounds whenever the
     // loop runs) and results are masked with selects, so the loads of a phase
     // are not split by branches and are in flight together.
+    int32_t prevc[R];  // PAD == 3: column of the previous step
+#pragma unroll
+    for (int r = 0; r < R; r++) prevc[r] = -1;
     for (int c0 = 0; c0 < cmax; c0 += U) {
         S v[R][U];
         int32_t ci[R][U];
@@ -322,12 +329,17 @@ __device__ __forceinline__ void spmv_groups_uniform(const SpmvParams &P, int32_t
         // the group width, padding included
         int n[R];
 #pragma unroll
-        for (int r = 0; r < R; r++) n[r] = PAD == 2 ? nl[r] : (len[r] > q ? (len[r] - q + T - 1) / T : 0);
+        for (int r = 0; r < R; r++) n[r] = PAD >= 2 ? nl[r] : (len[r] > q ? (len[r] - q + T - 1) / T : 0);
 #pragma unroll
         for (int r = 0; r < R; r++)
 #pragma unroll
             for (int u = 0; u < U; u++) {
-                const int32_t c = c0 + u < n[r] ? ci[r][u] : 0;
+                // PAD == 3: a padding step (column not above the previous one)
+                // gathers x[0] like a step past the row length, not x at the
+                // row's last column
+                bool g = c0 + u < n[r];
+                if constexpr (PAD == 3) g = g && ci[r][u] > (u == 0 ? prevc[r] : ci[r][u - 1]);
+                const int32_t c = g ? ci[r][u] : 0;
                 if constexpr (K == 1) xv[r][u][0] = ldx32<LP>(X, c, xrow);
                 else load_row<A, K>(X + (int64_t)c * P.ldx, xv[r][u]);
             }
@@ -335,7 +347,11 @@ __device__ __forceinline__ void spmv_groups_uniform(const SpmvParams &P, int32_t
         for (int r = 0; r < R; r++)
 #pragma unroll
             for (int u = 0; u < U; u++) {
-                const bool on = c0 + u < n[r];
+                bool on = c0 + u < n[r];
+                if constexpr (PAD == 3) {
+                    on = on && ci[r][u] > prevc[r];
+                    prevc[r] = ci[r][u];
+                }
                 const A a = V::template cvt<A>(v[r][u]);
 #pragma unroll
                 for (int k = 0; k < K; k++) {
@@ -408,7 +424,9 @@ __device__ __forceinline__ void spmv_groups_lane(const SpmvParams &P, int32_t w,
 
 template <int VD, class A, int K, int T, int R, int LP>
 __device__ __forceinline__ void spmv_groups_fixed(const SpmvParams &P, int32_t first, int lane) {
-    if (P.pad == 2) spmv_groups_uniform<VD, A, K, T, R, 2, LP>(P, first, lane);
+    if (P.pad == 3) {
+        if constexpr (T == 1) spmv_groups_uniform<VD, A, K, T, R, 3, LP>(P, first, lane);
+    } else if (P.pad == 2) spmv_groups_uniform<VD, A, K, T, R, 2, LP>(P, first, lane);
     else if (P.pad) spmv_groups_uniform<VD, A, K, T, R, 1, LP>(P, first, lane);
     else spmv_groups_uniform<VD, A, K, T, R, 0, LP>(P, first, lane);
 }

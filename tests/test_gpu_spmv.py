@@ -131,7 +131,7 @@ def test_rows_per_lane_schedules_agree(torch_cuda, oracle, sigma, tau):
     x = W.uniform_vector(A.n_cols, 16, np.float32)
     ref = None
     for R in (0, 1, 2, 4, 8):
-        for pad in (0, 1, 2):
+        for pad in (0, 1, 2, 3):
             say("schedules zipf 150001", sigma, tau, R, pad)
             M = rg.rgcsr_from_csr(A, G=64, sigma=sigma, tau=tau, rows_per_lane=R, pad_loads=pad)
             assert (M.info["rows_per_lane"] == R or R == 0) and M.info["pad_loads"] == pad
@@ -140,8 +140,29 @@ def test_rows_per_lane_schedules_agree(torch_cuda, oracle, sigma, tau):
             if ref is None:
                 check_spmv(oracle, A, x, y)
                 ref = y
-            else:
+            elif pad == 2:   # padding multiplied: same values, zeros may differ in sign
                 np.testing.assert_array_equal(y, ref)
+            else:
+                np.testing.assert_array_equal(y.view(np.uint32), ref.view(np.uint32))
+
+
+def test_row_lengths_from_columns_mode(torch_cuda, oracle):
+    """pad_loads = 3 reads no row lengths; it is chosen by default when a lane
+    owns a whole row and no grouped row is empty, and refused otherwise."""
+    S = W.laplacian_3d_7pt(20, dtype=np.float32)
+    x = W.uniform_vector(S.n_cols, 20, np.float32)
+    M = rg.rgcsr_from_csr(S, G=64)
+    assert M.info["pad_loads"] == 3
+    y = host(M.spmv(dev(x)))
+    check_spmv(oracle, S, x, y)
+    M0 = rg.rgcsr_from_csr(S, G=64, pad_loads=0)
+    np.testing.assert_array_equal(y.view(np.uint32), host(M0.spmv(dev(x))).view(np.uint32))
+    A = W.random_csr(2000, 2000, seed=3, max_len=20, empty_frac=0.1, dtype=np.float32)
+    assert rg.rgcsr_from_csr(A, G=64).info["pad_loads"] in (0, 1)
+    for kw in (dict(G=64), dict(G=32, T=2)):
+        with pytest.raises(rg.RgcsrError) as e:
+            rg.rgcsr_from_csr(A if kw["G"] == 64 else S, pad_loads=3, **kw)
+        assert e.value.status == 6
 
 
 @pytest.mark.parametrize("G,T,sigma,tau", [(64, 1, 1, -1), (128, 1, 1 << 40, 32), (64, 2, 1, -1), (32, 2, 4096, 8)])
