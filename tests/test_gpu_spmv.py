@@ -229,6 +229,39 @@ def test_rcm_reordered_spmv(torch_cuda, oracle):
         M.close()
 
 
+def test_hip_graph_capture_and_replay(torch_cuda, oracle):
+    """The SpMV (including the chunk-combine launch of a row over 16,384
+    nonzeros) can be captured in a HIP graph: every replay, with eager work
+    and host syncs between replays, equals an eager launch on the same x."""
+    torch = torch_cuda
+    A = W.random_csr(5000, 30000, seed=12, max_len=40, long_rows=3, long_len=20000, dtype=np.float32)
+    M = rg.rgcsr_from_csr(A, G=64, sigma=512, tau=16)
+    assert M.info["partials"] > 0
+    x = torch.from_numpy(W.uniform_vector(A.n_cols, 22, np.float32)).cuda()
+    y = torch.empty(A.n_rows, device="cuda:0")
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        for _ in range(2):
+            rg.rgcsr_spmv(M, x, y)
+    torch.cuda.current_stream().wait_stream(side)
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        rg.rgcsr_spmv(M, x, y)
+    ref = torch.empty_like(y)
+    for rep in range(4):
+        say("graph replay", rep)
+        x.mul_(-1.5).add_(0.25)          # eager work between replays
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        got = y.clone()
+        rg.rgcsr_spmv(M, x, ref)
+        torch.cuda.synchronize()
+        np.testing.assert_array_equal(host(got).view(np.uint32), host(ref).view(np.uint32))
+        check_spmv(oracle, A, host(x), host(got))
+
+
 def test_deterministic_repeat(torch_cuda, oracle):
     """No atomics in RgCSR SpMV: repeated launches give identical bits, also
     for rows split over several wavefronts."""
