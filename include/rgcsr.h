@@ -257,23 +257,43 @@ rgcsr_status rgcsr_clone(rgcsr_handle A, void *stream, rgcsr_handle *out);
  * NULL is accepted. */
 rgcsr_status rgcsr_destroy(rgcsr_handle A);
 
-/* rgcsr_autotune: choose layout and kernel schedule for one host CSR matrix
- * by timing candidates on the current device (the paper sweeps the group
- * size by hand, Table 4).  Candidates: the paper layout with automatic and
- * explicit rows-per-lane schedules, and long-row thresholds in {16, 32, 64,
- * 256} (below the longest row) combined with sort windows {1, 512, 4096, n},
- * skipping windows that do not cut padding; at most max_candidates are built
- * and each timed over `reps` launches of y = A x (x: device, n_cols entries
- * of vec_dtype; y: device scratch of n_rows).  Other fields of *base (value
- * dtype, CSR map, transpose, validation) are kept.  Writes the fastest
- * options to *best; when cands/times_us are not NULL they receive every
- * candidate timed (max_candidates entries of room) and its mean launch time
- * in microseconds, *n_tried their count.  Synchronises the stream. */
+/* rgcsr_autotune: choose the layout for one host CSR matrix by a cost-model
+ * prefilter and device timing (the paper sweeps the group size by hand,
+ * Table 4).  For every sort window sigma in {1, 256, 512, 4096, 65536, n} and
+ * long-row threshold tau in {none, 16, 32, 64, 256, 1024} (below the longest
+ * row), the (G, T) in {64, 128, 256, 512} x {1, 2, 4, 8} with the fewest
+ * modelled bytes is kept: value and column loads (over the group width when
+ * the default schedule loads padding), long rows, row lengths, output
+ * indices and group pointers.  In the order paper layout (64, 1, 1, none),
+ * cheapest layout of each sort window, remaining layouts by modelled bytes,
+ * each layout is built with the automatic kernel schedule and, when that
+ * schedule would load padding, also with loads that stop at the row length,
+ * until max_candidates are taken; each is timed over `reps` launches of
+ * y = A x (x: device,
+ * n_cols entries of vec_dtype; y: device scratch of n_rows).  Other fields
+ * of *base (value dtype, CSR map, transpose, validation, load policy) are
+ * kept.  Writes the fastest options to *best; when cands/times_us are not
+ * NULL they receive every candidate timed (max_candidates entries of room)
+ * and its mean launch time in microseconds, *n_tried their count.
+ * Synchronises the stream. */
 rgcsr_status rgcsr_autotune(int64_t n_rows, int64_t n_cols, int64_t nnz, const int64_t *row_ptr,
                             const int32_t *col_idx, const void *vals, rgcsr_dtype vals_dtype,
                             const rgcsr_opts *base, const void *x, void *y, rgcsr_dtype vec_dtype,
                             int32_t max_candidates, int32_t reps, rgcsr_opts *cands, double *times_us,
                             int32_t *n_tried, rgcsr_opts *best, void *stream);
+
+/* rgcsr_autotune_batch: the same search for a batch (the inputs of
+ * rgcsr_from_csr_batch): sort windows {1, 256, 1024, whole matrix},
+ * thresholds {none, 64, 256}, the cost model summed over the matrices; each
+ * candidate is built
+ * as one batch handle and timed on launches over all matrices (x, y: the
+ * concatenated per-matrix vectors, device). */
+rgcsr_status rgcsr_autotune_batch(int32_t count, const int64_t *n_rows, const int64_t *n_cols,
+                                  const int64_t *const *row_ptr, const int32_t *const *col_idx,
+                                  const void *const *vals, rgcsr_dtype vals_dtype, const rgcsr_opts *base,
+                                  const void *x, void *y, rgcsr_dtype vec_dtype, int32_t max_candidates,
+                                  int32_t reps, rgcsr_opts *cands, double *times_us, int32_t *n_tried,
+                                  rgcsr_opts *best, void *stream);
 
 /* ---- Hybrid ELL + COO (Section 3.3) --------------------------------------- */
 

@@ -412,34 +412,19 @@ def matrix_fingerprint(A) -> str:
     return h.hexdigest()[:24]
 
 
-def rgcsr_autotune(A, x, y, base: _lib.Opts | None = None, max_candidates: int = 16, reps: int = 20,
-                   cache_path: str | None = None, stream=None) -> tuple[_lib.Opts, list]:
-    """Pick layout and schedule for A by timing candidates on the device
-    (native search in librgcsr).  Results are cached in a JSON file keyed by
-    the matrix fingerprint and the value dtype (cache_path, default
+def _cached_tune(key: str, cache_path, run):
+    """JSON cache of autotuner results (cache_path, default
     $RGCSR_AUTOTUNE_CACHE if set, else no cache)."""
     import json
     import os
-    base = base if base is not None else make_opts()
     path = cache_path or os.environ.get("RGCSR_AUTOTUNE_CACHE")
-    key = f"{matrix_fingerprint(A)}:{base.value_dtype}:{_code_of_tensor(x)}"
     cache = {}
     if path and os.path.exists(path):
         with open(path) as f:
             cache = json.load(f)
         if key in cache:
             return opts_from_dict(cache[key]["best"]), cache[key]["tried"]
-    _dev_check(x, "x")
-    _dev_check(y, "y")
-    rp, col, val = _csr_arrays(A)
-    cands = (_lib.Opts * max_candidates)()
-    times = np.zeros(max_candidates, np.float64)
-    n = ctypes.c_int32(0)
-    best = _lib.Opts()
-    _lib.call("rgcsr_autotune", A.n_rows, A.n_cols, int(rp[-1]), _ptr(rp), _ptr(col), _ptr(val),
-              _code_of_numpy(val), ctypes.byref(base), _ptr(x), _ptr(y), _code_of_tensor(x), max_candidates,
-              reps, ctypes.addressof(cands), _ptr(times), ctypes.byref(n), ctypes.byref(best), _stream(stream))
-    tried = [{"opts": opts_dict(cands[i]), "us": float(times[i])} for i in range(n.value)]
+    best, tried = run()
     if path:
         cache[key] = {"best": opts_dict(best), "tried": tried}
         tmp = path + ".tmp"
@@ -447,6 +432,64 @@ def rgcsr_autotune(A, x, y, base: _lib.Opts | None = None, max_candidates: int =
             json.dump(cache, f, indent=1)
         os.replace(tmp, path)
     return best, tried
+
+
+def rgcsr_autotune(A, x, y, base: _lib.Opts | None = None, max_candidates: int = 16, reps: int = 20,
+                   cache_path: str | None = None, stream=None) -> tuple[_lib.Opts, list]:
+    """Pick layout and schedule for A by a cost-model prefilter and timing
+    the best candidates on the device (native search in librgcsr).  Results
+    are cached in a JSON file keyed by the matrix fingerprint, the value dtype
+    and the vector dtype."""
+    base = base if base is not None else make_opts()
+    key = f"{matrix_fingerprint(A)}:{base.value_dtype}:{_code_of_tensor(x)}"
+
+    def run():
+        _dev_check(x, "x")
+        _dev_check(y, "y")
+        rp, col, val = _csr_arrays(A)
+        cands = (_lib.Opts * max_candidates)()
+        times = np.zeros(max_candidates, np.float64)
+        n = ctypes.c_int32(0)
+        best = _lib.Opts()
+        _lib.call("rgcsr_autotune", A.n_rows, A.n_cols, int(rp[-1]), _ptr(rp), _ptr(col), _ptr(val),
+                  _code_of_numpy(val), ctypes.byref(base), _ptr(x), _ptr(y), _code_of_tensor(x), max_candidates,
+                  reps, ctypes.addressof(cands), _ptr(times), ctypes.byref(n), ctypes.byref(best), _stream(stream))
+        return best, [{"opts": opts_dict(cands[i]), "us": float(times[i])} for i in range(n.value)]
+    return _cached_tune(key, cache_path, run)
+
+
+def rgcsr_autotune_batch(mats, x, y, base: _lib.Opts | None = None, max_candidates: int = 12, reps: int = 10,
+                         cache_path: str | None = None, stream=None) -> tuple[_lib.Opts, list]:
+    """Same for a batch of matrices (rgcsr_from_csr_batch): every candidate
+    is built as a batch handle and timed on one launch over all matrices.  x
+    and y hold the concatenated per-matrix vectors."""
+    import hashlib
+    base = base if base is not None else make_opts()
+    h = hashlib.sha256()
+    for M in mats:
+        h.update(matrix_fingerprint(M).encode())
+    key = f"batch{len(mats)}:{h.hexdigest()[:24]}:{base.value_dtype}:{_code_of_tensor(x)}"
+
+    def run():
+        _dev_check(x, "x")
+        _dev_check(y, "y")
+        arrs = [_csr_arrays(M) for M in mats]
+        count = len(mats)
+        nr = np.array([M.n_rows for M in mats], np.int64)
+        nc = np.array([M.n_cols for M in mats], np.int64)
+        rps = (ctypes.c_void_p * count)(*[_ptr(a[0]) for a in arrs])
+        cols = (ctypes.c_void_p * count)(*[_ptr(a[1]) for a in arrs])
+        vals = (ctypes.c_void_p * count)(*[_ptr(a[2]) for a in arrs])
+        cands = (_lib.Opts * max_candidates)()
+        times = np.zeros(max_candidates, np.float64)
+        n = ctypes.c_int32(0)
+        best = _lib.Opts()
+        _lib.call("rgcsr_autotune_batch", count, _ptr(nr), _ptr(nc), ctypes.addressof(rps), ctypes.addressof(cols),
+                  ctypes.addressof(vals), _code_of_numpy(arrs[0][2]),
+                  ctypes.byref(base), _ptr(x), _ptr(y), _code_of_tensor(x), max_candidates, reps,
+                  ctypes.addressof(cands), _ptr(times), ctypes.byref(n), ctypes.byref(best), _stream(stream))
+        return best, [{"opts": opts_dict(cands[i]), "us": float(times[i])} for i in range(n.value)]
+    return _cached_tune(key, cache_path, run)
 
 
 def version() -> str:

@@ -93,6 +93,9 @@ SIGNATURES = {
     "rgcsr_autotune": (c_int, [c_i64, c_i64, c_i64, c_vp, c_vp, c_vp, c_int, ctypes.POINTER(Opts), c_vp, c_vp,
                                c_int, c_i32, c_i32, c_vp, c_vp, ctypes.POINTER(c_i32), ctypes.POINTER(Opts),
                                c_vp]),
+    "rgcsr_autotune_batch": (c_int, [c_i32, c_vp, c_vp, c_vp, c_vp, c_vp, c_int, ctypes.POINTER(Opts), c_vp, c_vp,
+                                     c_int, c_i32, c_i32, c_vp, c_vp, ctypes.POINTER(c_i32), ctypes.POINTER(Opts),
+                                     c_vp]),
     "rgcsr_status_string": (ctypes.c_char_p, [c_int]),
     "rgcsr_last_error": (ctypes.c_char_p, []),
     "rgcsr_version": (ctypes.c_char_p, []),

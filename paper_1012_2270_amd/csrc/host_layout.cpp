@@ -90,6 +90,30 @@ static void order_and_split(const LayoutParams &p, int64_t n_rows, const int64_t
 
 static inline int64_t round_up(int64_t v, int64_t m) { return (v + m - 1) / m * m; }
 
+void short_lengths(const LayoutParams &p, int64_t n_rows, const int64_t *rp, std::vector<int32_t> &lens,
+                   int64_t *n_long, int64_t *long_nnz) {
+    std::vector<int32_t> sv, lv;
+    order_and_split(p, n_rows, rp, sv, lv);
+    lens.resize(sv.size());
+    for (size_t i = 0; i < sv.size(); i++) lens[i] = (int32_t)(rp[sv[i] + 1] - rp[sv[i]]);
+    int64_t lz = 0;
+    for (int32_t r : lv) lz += rp[r + 1] - rp[r];
+    *n_long = (int64_t)lv.size();
+    *long_nnz = lz;
+}
+
+int64_t group_slots(const std::vector<int32_t> &lens, int32_t G, int32_t T) {
+    int64_t s = 0;
+    const int64_t n = (int64_t)lens.size();
+    for (int64_t g0 = 0; g0 < n; g0 += G) {
+        const int64_t g1 = std::min<int64_t>(n, g0 + G);
+        int64_t w = 0;
+        for (int64_t i = g0; i < g1; i++) w = std::max<int64_t>(w, lens[i]);
+        s += (g1 - g0) * round_up(w, T);
+    }
+    return s;
+}
+
 void layout_sizes(const LayoutParams &p, int64_t n_rows, const int64_t *rp, int64_t *ng,
                   int64_t *ns, int64_t *nl, int64_t *slots, int64_t *long_nnz,
                   std::vector<int64_t> *long_lens_sorted) {

@@ -166,6 +166,13 @@ void append_layout(HostLayout &L, const LayoutParams &p, int64_t n_rows, int64_t
                    const int64_t *rp, const int32_t *col, const uint8_t *vals, int esz,
                    uint8_t pad_byte);
 
+// Lengths of the grouped rows in layout order under (sigma, tau) of p, and
+// the count and nonzeros of the long rows; slots of those rows in groups of
+// G rows with widths rounded up to T.  Cost model of the autotuner.
+void short_lengths(const LayoutParams &p, int64_t n_rows, const int64_t *rp, std::vector<int32_t> &lens,
+                   int64_t *n_long, int64_t *long_nnz);
+int64_t group_slots(const std::vector<int32_t> &lens, int32_t G, int32_t T);
+
 // Sizes only (no arrays), for rgcsr_layout_sizes.
 void layout_sizes(const LayoutParams &p, int64_t n_rows, const int64_t *rp, int64_t *ng,
                   int64_t *ns, int64_t *nl, int64_t *slots, int64_t *long_nnz,

@@ -398,3 +398,43 @@ def test_autotune_picks_a_timed_candidate_and_caches(torch_cuda, oracle, tmp_pat
     check_spmv(oracle, A, host(x), host(M.spmv(x)))
     best2, tried2 = rg.rgcsr_autotune(A, x, y, cache_path=cache)   # served from the cache
     assert rg.opts_dict(best2) == rg.opts_dict(best) and tried2 == tried
+
+
+def test_autotune_covers_group_size_and_lanes(torch_cuda, oracle):
+    """The cost model proposes group sizes and lanes per row beyond (64, 1)
+    where they move fewer bytes (long uniform rows), always keeps the paper
+    layout, and every timed candidate is correct."""
+    torch = torch_cuda
+    A = W.banded_poisson_matrix(30_000, 120.0, 400, np.random.default_rng(31), np.float32)
+    x = dev(W.uniform_vector(A.n_cols, 23, np.float32))
+    y = torch.empty(A.n_rows, device="cuda:0")
+    say("autotune G and T")
+    best, tried = rg.rgcsr_autotune(A, x, y, max_candidates=6, reps=2)
+    pairs = {(t["opts"]["group_size"], t["opts"]["lanes_per_row"]) for t in tried}
+    assert (64, 1) in pairs
+    for t in tried:
+        M = rg.rgcsr_from_csr(A, opts=rg.opts_from_dict(t["opts"]))
+        check_spmv(oracle, A, host(x), host(M.spmv(x)))
+        M.close()
+
+
+def test_autotune_batch(torch_cuda, oracle, tmp_path):
+    torch = torch_cuda
+    mats = W.batched_set(count=48, n_lo=50, n_hi=3000, seed=32)
+    ncols = sum(M.n_cols for M in mats)
+    nrows = sum(M.n_rows for M in mats)
+    xh = W.uniform_vector(ncols, 24, np.float32)
+    x, y = dev(xh), torch.empty(nrows, device="cuda:0")
+    cache = str(tmp_path / "tune_batch.json")
+    say("autotune batch")
+    best, tried = rg.rgcsr_autotune_batch(mats, x, y, max_candidates=5, reps=2, cache_path=cache)
+    assert 1 <= len(tried) <= 5
+    assert rg.opts_dict(best) in [t["opts"] for t in tried]
+    B = rg.rgcsr_from_csr_batch(mats, opts=best)
+    yh = host(B.spmv(x))
+    ro, co = B.batch_offsets()
+    for i in range(0, len(mats), 7):
+        M = mats[i]
+        check_spmv(oracle, M, xh[co[i]:co[i + 1]], yh[ro[i]:ro[i + 1]])
+    best2, tried2 = rg.rgcsr_autotune_batch(mats, x, y, cache_path=cache)
+    assert rg.opts_dict(best2) == rg.opts_dict(best) and tried2 == tried
