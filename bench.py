@@ -148,15 +148,17 @@ def check_outputs(cases, torch):
 # ----------------------------------------------------------------------------
 # Other forms of the hot path (one JSON line each; not the contract line)
 # ----------------------------------------------------------------------------
-def _events(torch, fn, reps):
+def _mean_launch_ms(torch, fn, reps):
+    """Mean duration (ms) of fn(i) over reps back-to-back calls on the
+    current stream, HIP events only at the two ends."""
     torch.cuda.synchronize()
-    ev = [torch.cuda.Event(enable_timing=True) for _ in range(reps + 1)]
-    ev[0].record()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
     for i in range(reps):
         fn(i)
-        ev[i + 1].record()
+    b.record()
     torch.cuda.synchronize()
-    return [ev[i].elapsed_time(ev[i + 1]) for i in range(reps)]
+    return a.elapsed_time(b) / reps
 
 
 def achievable_read_gbs(torch, rg, nbytes=2 << 30, reps=10):
@@ -166,7 +168,7 @@ def achievable_read_gbs(torch, rg, nbytes=2 << 30, reps=10):
     sink = torch.zeros(1, dtype=torch.int32, device="cuda:0")
     for _ in range(2):
         rg.rgcsr_stream_read(buf, sink)
-    t = _events(torch, lambda i: rg.rgcsr_stream_read(buf, sink), reps)
+    t = _mean_launch_ms(torch, lambda i: rg.rgcsr_stream_read(buf, sink), reps)
     del buf
     return nbytes / (float(np.mean(t)) * 1e-3) / 1e9
 
@@ -187,12 +189,12 @@ def bench_spmm(args, torch, rg, W):
         Ys = [torch.empty((A.n_rows, k), device="cuda:0") for _ in range(copies)]
         for i in range(args.warmup):
             rg.rgcsr_spmv_batched(mats[i % copies], Xs[i % copies], Ys[i % copies])
-        t = _events(torch, lambda i: rg.rgcsr_spmv_batched(mats[i % copies], Xs[i % copies], Ys[i % copies]),
+        t = _mean_launch_ms(torch, lambda i: rg.rgcsr_spmv_batched(mats[i % copies], Xs[i % copies], Ys[i % copies]),
                     args.steps)
         ms = float(np.mean(t))
         xcols = [X0[:, c].contiguous() for c in range(k)]
         ycol = torch.empty(A.n_rows, device="cuda:0")
-        t1 = _events(torch, lambda i: [rg.rgcsr_spmv(mats[i % copies], xcols[c], ycol) for c in range(k)],
+        t1 = _mean_launch_ms(torch, lambda i: [rg.rgcsr_spmv(mats[i % copies], xcols[c], ycol) for c in range(k)],
                      max(10, args.steps // 4))
         Y = Ys[0]
         rg.rgcsr_spmv_batched(mats[0], Xs[0], Y)
@@ -243,7 +245,7 @@ def bench_batched(args, torch, rg, W):
         X, Y = x.view(-1, 1), y.view(-1, 1)
         for _ in range(args.warmup):
             rg.rgcsr_spmv_batched(B, X, Y, persistent)
-        t = _events(torch, lambda i: rg.rgcsr_spmv_batched(B, X, Y, persistent), args.steps)
+        t = _mean_launch_ms(torch, lambda i: rg.rgcsr_spmv_batched(B, X, Y, persistent), args.steps)
         ms = float(np.mean(t))
         res["persistent" if persistent else "per_item"] = {"us": ms * 1e3, "gbs": b / (ms * 1e-3) / 1e9,
                                                           "gflops": 2 * nnz / (ms * 1e-3) / 1e9}
@@ -252,7 +254,7 @@ def bench_batched(args, torch, rg, W):
     X, Y = x.view(-1, 1), torch.empty_like(y).view(-1, 1)
     for _ in range(args.warmup):
         rg.rgcsr_spmv_batched(B64, X, Y, False)
-    t64 = float(np.mean(_events(torch, lambda i: rg.rgcsr_spmv_batched(B64, X, Y, False), args.steps)))
+    t64 = float(np.mean(_mean_launch_ms(torch, lambda i: rg.rgcsr_spmv_batched(B64, X, Y, False), args.steps)))
     res["paper_layout_per_item"] = {"us": t64 * 1e3, "gbs": b / (t64 * 1e-3) / 1e9}
     B64.close()
     yh = y.cpu().numpy()
@@ -297,7 +299,7 @@ def bench_cg(args, torch, rg, W):
         yv = torch.empty(A.n_rows, dtype=vec, device="cuda:0")
         for _ in range(3):
             rg.rgcsr_spmv(Alo, xv, yv)
-        t = _events(torch, lambda i: rg.rgcsr_spmv(Alo, xv, yv), 20)
+        t = _mean_launch_ms(torch, lambda i: rg.rgcsr_spmv(Alo, xv, yv), 20)
         s_v = {"f32": 4, "bf16": 2, "f16": 2, "fp64-cg": 8}[dt]
         s_x = 8 if dt == "fp64-cg" else 4
         bb = alg_bytes(A.nnz, A.n_rows, A.n_cols, Alo.info["n_groups"], s_v=s_v, s_x=s_x, s_y=s_x)
@@ -333,8 +335,8 @@ def bench_grad(args, torch, rg, W):
             rg.rgcsr_spmv_transpose_grad(M, xd, y, dx, dv)
         for i in range(args.warmup):
             step(i)
-        t = _events(torch, step, args.steps)
-        fw = _events(torch, lambda i: rg.rgcsr_spmv(M, xd, y), args.steps)
+        t = _mean_launch_ms(torch, step, args.steps)
+        fw = _mean_launch_ms(torch, lambda i: rg.rgcsr_spmv(M, xd, y), args.steps)
         s = oracle.csr_absmv(A, x)
         st = float(np.max(s + np.abs(bvec))) * float(np.max(np.abs(x)))
         out["results"].append({"dx": "transposed" if transpose else "atomic",
@@ -382,9 +384,9 @@ def bench_fp64(args, torch, rg, W):
         ys = [torch.empty(A.n_rows, dtype=torch.float64, device="cuda:0") for _ in range(copies)]
         for i in range(args.warmup):
             rg.rgcsr_spmv(mats[i % copies], xs[i % copies], ys[i % copies])
-        t = float(np.mean(_events(torch, lambda i: rg.rgcsr_spmv(mats[i % copies], xs[i % copies], ys[i % copies]),
+        t = float(np.mean(_mean_launch_ms(torch, lambda i: rg.rgcsr_spmv(mats[i % copies], xs[i % copies], ys[i % copies]),
                                   args.steps)))
-        th = float(np.mean(_events(torch, lambda i: rg.hyb_spmv(hybs[i % copies], xs[i % copies], ys[i % copies]),
+        th = float(np.mean(_mean_launch_ms(torch, lambda i: rg.hyb_spmv(hybs[i % copies], xs[i % copies], ys[i % copies]),
                                    args.steps)))
         rg.rgcsr_spmv(mats[0], xs[0], ys[0])
         err = oracle.scaled_error(ys[0].cpu().numpy(), oracle.csr_spmv(A64, x), oracle.csr_absmv(A64, x))
@@ -426,9 +428,9 @@ def bench_variants(args, torch, rg, W):
                 ys = [torch.empty(A.n_rows, device="cuda:0") for _ in range(copies)]
                 for i in range(args.warmup):
                     rg.rgcsr_spmv(mats[i % copies], xs[i % copies], ys[i % copies])
-                cold = float(np.mean(_events(torch, lambda i: rg.rgcsr_spmv(mats[i % copies], xs[i % copies],
+                cold = float(np.mean(_mean_launch_ms(torch, lambda i: rg.rgcsr_spmv(mats[i % copies], xs[i % copies],
                                                                              ys[i % copies]), args.steps)))
-                warm = float(np.mean(_events(torch, lambda i: rg.rgcsr_spmv(mats[0], xs[0], ys[0]), args.steps)))
+                warm = float(np.mean(_mean_launch_ms(torch, lambda i: rg.rgcsr_spmv(mats[0], xs[0], ys[0]), args.steps)))
                 rg.rgcsr_spmv(mats[0], xs[0], ys[0])
                 y = ys[0].cpu().numpy()
                 if ref is None:
@@ -448,8 +450,8 @@ def bench_variants(args, torch, rg, W):
         ys = [torch.empty(A.n_rows, device="cuda:0") for _ in range(copies)]
         for i in range(args.warmup):
             rg.hyb_spmv(hybs[i % copies], xd, ys[i % copies])
-        cold = float(np.mean(_events(torch, lambda i: rg.hyb_spmv(hybs[i % copies], xd, ys[i % copies]), args.steps)))
-        warm = float(np.mean(_events(torch, lambda i: rg.hyb_spmv(hybs[0], xd, ys[0]), args.steps)))
+        cold = float(np.mean(_mean_launch_ms(torch, lambda i: rg.hyb_spmv(hybs[i % copies], xd, ys[i % copies]), args.steps)))
+        warm = float(np.mean(_mean_launch_ms(torch, lambda i: rg.hyb_spmv(hybs[0], xd, ys[0]), args.steps)))
         out["results"].append({"matrix": name, "format": "hybrid", "us_hbm": cold * 1e3, "us_cache": warm * 1e3})
         for h in hybs[1:]:
             h.close()
@@ -480,7 +482,7 @@ def bench_ordering(args, torch, rg, W):
             ys = [torch.empty(A.n_rows, device="cuda:0") for _ in range(copies)]
             for i in range(args.warmup):
                 fn(hs[i % copies], xs[i % copies], ys[i % copies])
-            t = float(np.mean(_events(torch, lambda i: fn(hs[i % copies], xs[i % copies], ys[i % copies]),
+            t = float(np.mean(_mean_launch_ms(torch, lambda i: fn(hs[i % copies], xs[i % copies], ys[i % copies]),
                                       args.steps)))
             fn(hs[0], xs[0], ys[0])
             err = oracle.scaled_error(ys[0].cpu().numpy(), oracle.csr_spmv(A, x), oracle.csr_absmv(A, x))
