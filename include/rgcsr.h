@@ -167,10 +167,16 @@ rgcsr_status rgcsr_layout_host(int64_t n_rows, int64_t n_cols, int64_t nnz,
 
 /* rgcsr_from_csr: convert a CSR matrix (Section 3.1) to RgCSR on the current
  * device.  inputs_on_device = 0: row_ptr/col_idx/vals are host pointers,
- * borrowed for the duration of the call.  inputs_on_device = 1: they are
- * device pointers; the call copies them to the host first (synchronising the
- * stream).  The handle owns the device arrays it allocates (hipMalloc); the
- * call synchronises the stream before returning, so the handle is ready. */
+ * borrowed for the duration of the call, converted by the host library.
+ * inputs_on_device = 1: they are device pointers, borrowed until the call
+ * returns, and the conversion runs on the device (validation, window sort,
+ * long-row split, group widths and offsets, scatter and value conversion),
+ * giving the same arrays bit for bit; device inputs are always validated
+ * (opts->validate is ignored), and with build_transpose they are copied to the
+ * host and converted there.  The device path allocates temporary device
+ * memory (freed before return).  The handle owns the device arrays it
+ * allocates (hipMalloc); the call synchronises the stream before returning,
+ * so the handle is ready. */
 rgcsr_status rgcsr_from_csr(int64_t n_rows, int64_t n_cols, int64_t nnz,
                             const int64_t *row_ptr, const int32_t *col_idx,
                             const void *vals, rgcsr_dtype vals_dtype,

@@ -11,6 +11,7 @@
 #include <type_traits>
 #include <vector>
 
+#include "convert.h"
 #include "internal.h"
 #include "kernels.h"
 
@@ -235,18 +236,14 @@ std::vector<int32_t> wave_runs(const HostLayout &L, int32_t wpg) {
 // grouped nonzeros; rows per lane fixed by the caller or, by default, chosen
 // per wavefront (wave_runs) when a lane owns a whole row and a group fills
 // whole wavefronts, else one.
-void choose_schedule(rgcsr_matrix_s *h, const HostLayout &L, int32_t rows_per_lane, int32_t pad_loads,
-                     int32_t load_policy) {
-    int64_t short_nnz = 0;
-    for (int32_t v : L.short_len) short_nnz += v;
+void choose_schedule(rgcsr_matrix_s *h, const HostLayout &L, int64_t short_nnz, bool no_empty,
+                     int32_t rows_per_lane, int32_t pad_loads, int32_t load_policy) {
     const int64_t pad_slots = L.slots - short_nnz;
     if (pad_loads < -1 || pad_loads > 3) fail(RGCSR_EINVAL, "pad_loads must be -1, 0, 1, 2 or 3");
     if (pad_loads >= 2 && h->gpw > 0)
         fail(RGCSR_EUNSUPPORTED, "pad_loads 2 and 3 need group_size * lanes_per_row a multiple of 64");
     // row lengths can be read off the columns when a lane owns a whole row
     // and no grouped row is empty
-    bool no_empty = true;
-    for (int32_t v : L.short_len) no_empty = no_empty && v > 0;
     const bool cols_give_len = L.T == 1 && h->gpw == 0 && no_empty;
     if (pad_loads == 3 && !cols_give_len)
         fail(RGCSR_EUNSUPPORTED, "pad_loads 3 needs lanes_per_row = 1 and no empty rows among the grouped rows");
@@ -302,7 +299,13 @@ rgcsr_matrix_s *make_device(const HostLayout &L, const std::vector<int64_t> *row
         const int64_t GT = (int64_t)L.G * L.T;
         h->wpg = GT >= 64 ? (int32_t)(GT / 64) : 0;
         h->gpw = GT < 64 ? (int32_t)(64 / GT) : 0;
-        choose_schedule(h, L, rows_per_lane, pad_loads, load_policy);
+        int64_t short_nnz = 0;
+        bool no_empty = true;
+        for (int32_t v : L.short_len) {
+            short_nnz += v;
+            no_empty = no_empty && v > 0;
+        }
+        choose_schedule(h, L, short_nnz, no_empty, rows_per_lane, pad_loads, load_policy);
         // the kernels address a group's slots with 32-bit byte offsets
         int64_t max_group = 0;
         for (size_t g = 0; g + 1 < L.gp.size(); g++) max_group = std::max(max_group, L.gp[g + 1] - L.gp[g]);
@@ -353,6 +356,84 @@ rgcsr_matrix_s *make_device(const HostLayout &L, const std::vector<int64_t> *row
         }
         HIPCHK(hipStreamSynchronize(st));
     } catch (...) {
+        if (h->mem) (void)hipFree(h->mem);
+        delete h;
+        throw;
+    }
+    return h;
+}
+
+// Handle built from device CSR arrays: the plan (order, widths, offsets) and
+// the scatter run on the device (convert.hip); only sizes, the group and
+// long-row offsets and the small work lists go through the host.
+rgcsr_matrix_s *make_device_on_device(DevPlan &P, const LayoutParams &p, int vdt, const int64_t *rp,
+                                      const int32_t *col, const void *vals, int vals_dt, bool keep_map,
+                                      hipStream_t st, int32_t rows_per_lane, int32_t pad_loads,
+                                      int32_t load_policy) {
+    HostLayout L;  // sizes and host-side offsets only
+    L.G = p.G; L.T = p.T; L.sigma = p.sigma; L.tau = p.tau; L.vdt = vdt; L.esz = dtype_size(vdt);
+    L.n_rows = P.n_rows; L.n_cols = P.n_cols; L.nnz = P.nnz;
+    L.ng = P.ng; L.ns = P.ns; L.nl = P.nl; L.slots = P.slots; L.long_nnz = P.long_nnz;
+    L.n_matrices = 1;
+    L.gp = P.gp_host;
+    L.ragged = false;
+    L.row_off = {0, P.n_rows};
+    L.col_off = {0, P.n_cols};
+    build_long_work(P.long_ptr_host, L.work);
+    auto *h = new rgcsr_matrix_s();
+    try {
+        h->device = current_device();
+        h->prm = p;
+        h->vdt = vdt;
+        h->esz = L.esz;
+        h->n_rows = L.n_rows; h->n_cols = L.n_cols; h->nnz = L.nnz;
+        h->ng = L.ng; h->ns = L.ns; h->nl = L.nl; h->slots = L.slots; h->long_nnz = L.long_nnz;
+        h->n_matrices = 1;
+        h->n_wave_long = (int64_t)L.work.wave.size();
+        h->n_block = (int64_t)L.work.block.size();
+        h->n_combine = (int64_t)L.work.combine.size();
+        h->n_partials = L.work.n_partials;
+        h->ragged = false;
+        h->perm = P.perm;
+        h->row_off = L.row_off;
+        h->col_off = L.col_off;
+        const int64_t GT = (int64_t)L.G * L.T;
+        h->wpg = GT >= 64 ? (int32_t)(GT / 64) : 0;
+        h->gpw = GT < 64 ? (int32_t)(64 / GT) : 0;
+        choose_schedule(h, L, P.nnz - P.long_nnz, P.no_empty, rows_per_lane, pad_loads, load_policy);
+        int64_t max_group = 0;
+        for (size_t g = 0; g + 1 < L.gp.size(); g++) max_group = std::max(max_group, L.gp[g + 1] - L.gp[g]);
+        if (max_group * std::max(L.esz, 4) >= (int64_t(1) << 32))
+            fail(RGCSR_EOVERFLOW, "a row group holds 4 GiB or more; use a long-row threshold");
+        Arena a;
+        a.add(&h->gp, (size_t)L.ng + 1);
+        a.add(&h->short_len, (size_t)L.ns);
+        a.add(&h->short_row, h->perm ? (size_t)L.ns : 0);
+        a.add((uint8_t **)&h->slot_val, (size_t)L.slots * L.esz);
+        a.add(&h->slot_col, (size_t)L.slots);
+        a.add(&h->short_items, h->items.size());
+        a.add(&h->wave_work, L.work.wave.size());
+        a.add(&h->block_work, L.work.block.size());
+        a.add(&h->combine, L.work.combine.size());
+        a.add(&h->long_row, (size_t)L.nl);
+        a.add(&h->long_ptr, (size_t)L.nl + 1);
+        a.add((uint8_t **)&h->long_val, (size_t)L.long_nnz * L.esz);
+        a.add(&h->long_col, (size_t)L.long_nnz);
+        a.add((uint8_t **)&h->partial, (size_t)L.work.n_partials * 32 * sizeof(double));
+        if (keep_map) a.add(&h->row_ptr, (size_t)P.n_rows + 1);
+        h->mem = a.commit();
+        h->bytes = a.total;
+        device_fill(P, p, rp, col, vals, vals_dt, vdt, h->gp, h->short_len, h->perm ? h->short_row : nullptr,
+                    h->slot_val, h->slot_col, h->long_row, h->long_ptr, h->long_val, h->long_col, st);
+        upload(h->short_items, h->items, st);
+        upload(h->wave_work, L.work.wave, st);
+        upload(h->block_work, L.work.block, st);
+        upload(h->combine, L.work.combine, st);
+        if (keep_map)
+            HIPCHK(hipMemcpyAsync(h->row_ptr, rp, ((size_t)P.n_rows + 1) * 8, hipMemcpyDeviceToDevice, st));
+        HIPCHK(hipStreamSynchronize(st));
+    } catch (...) {
+        (void)hipStreamSynchronize(st);
         if (h->mem) (void)hipFree(h->mem);
         delete h;
         throw;
@@ -579,6 +660,15 @@ rgcsr_status rgcsr_from_csr(int64_t n_rows, int64_t n_cols, int64_t nnz, const i
     const int64_t *rp = row_ptr;
     const int32_t *col = col_idx;
     const void *val = vals;
+    if (inputs_on_device && !o.build_transpose) {
+        // conversion on the device; device inputs are always validated
+        DevPlan P;
+        P.scratch.st = st;
+        device_plan(P, p, n_rows, n_cols, nnz, row_ptr, col_idx, true, st);
+        *out = make_device_on_device(P, p, o.value_dtype, row_ptr, col_idx, vals, vals_dtype, o.keep_csr_map != 0, st,
+                                     o.rows_per_lane, o.pad_loads, o.load_policy);
+        return RGCSR_OK;
+    }
     if (inputs_on_device) {
         if (!row_ptr) fail(RGCSR_EINVAL, "row_ptr is null");
         h_rp.resize(n_rows + 1);
