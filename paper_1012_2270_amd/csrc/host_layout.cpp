@@ -155,6 +155,7 @@ void append_layout(HostLayout &L, const LayoutParams &p, int64_t n_rows, int64_t
     order_and_split(p, n_rows, rp, sv, lv);
 
     // groups of short rows
+    const int64_t ng_before = L.ng;
     const int64_t n_short = (int64_t)sv.size();
     const int64_t slot0 = L.slots;
     std::vector<int64_t> gstart;  // local group starts in sv
@@ -172,8 +173,8 @@ void append_layout(HostLayout &L, const LayoutParams &p, int64_t n_rows, int64_t
     L.slots = slots;
     L.ng += (int64_t)gstart.size();
 
-    L.short_len.reserve(L.ns + n_short);
-    L.short_row.reserve(L.ns + n_short);
+    // exact reserve() on every append of a batch would copy the arrays each
+    // time; push_back grows them geometrically
     for (int32_t r : sv) {
         L.short_len.push_back((int32_t)(rp[r + 1] - rp[r]));
         L.short_row.push_back((int32_t)(rbase + r));
@@ -230,13 +231,12 @@ void append_layout(HostLayout &L, const LayoutParams &p, int64_t n_rows, int64_t
     L.n_matrices++;
     L.row_off.push_back(L.n_rows);
     L.col_off.push_back(L.n_cols);
-    // groups are ragged when any group before the last has fewer than G rows
-    L.ragged = false;
-    for (int64_t g = 0; g + 1 < L.ng; g++)
-        if (L.grp_row0[g + 1] - L.grp_row0[g] != p.G) {
-            L.ragged = true;
-            break;
-        }
+    // groups are ragged when any group before the last has fewer than G rows;
+    // only the previous matrix's last group and this matrix's groups can make
+    // it so, the earlier ones were checked by earlier appends
+    const int64_t g_check0 = std::max<int64_t>(0, ng_before - 1);
+    for (int64_t g = g_check0; g + 1 < L.ng && !L.ragged; g++)
+        if (L.grp_row0[g + 1] - L.grp_row0[g] != p.G) L.ragged = true;
 }
 
 static int32_t lanes_for(int64_t len) {
