@@ -522,7 +522,10 @@ void spmv_launch(const rgcsr_matrix_s *h, int K, const void *X, int64_t ldx, voi
     }
 }
 
-int64_t nblocks_vec(int64_t n) { return std::max<int64_t>(1, std::min<int64_t>(512, (n + 255) / 256)); }
+// CG vector kernels: up to 2,048 workgroups (eight per CU), each lane taking
+// at least four elements; the partial-sum count is fixed by n, so the
+// reductions are deterministic
+int64_t nblocks_vec(int64_t n) { return std::max<int64_t>(1, std::min<int64_t>(2048, (n + 1023) / 1024)); }
 
 }  // namespace
 

@@ -881,12 +881,26 @@ __device__ __forceinline__ double block_sum(double v, double *sh) {
     return t;
 }
 
+// Grid-stride loop over [0, n) taking four independent elements per pass, so
+// each lane has four loads in flight; f(i) is applied in a fixed order for a
+// fixed grid, which keeps the partial sums deterministic.
+template <class F> __device__ __forceinline__ void grid_loop4(int64_t n, F f) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    for (; i + 3 * stride < n; i += 4 * stride) {
+        f(i);
+        f(i + stride);
+        f(i + 2 * stride);
+        f(i + 3 * stride);
+    }
+    for (; i < n; i += stride) f(i);
+}
+
 template <class TA, class TB>
 __global__ __launch_bounds__(256) void dot_partial_k(int64_t n, const TA *a, const TB *b, double *part) {
     __shared__ double sh[4];
     double acc = 0.0;
-    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
-        acc += (double)a[i] * (double)b[i];
+    grid_loop4(n, [&](int64_t i) { acc += (double)a[i] * (double)b[i]; });
     const double t = block_sum(acc, sh);
     if (threadIdx.x == 0) part[blockIdx.x] = t;
 }
@@ -913,12 +927,12 @@ __global__ __launch_bounds__(256) void cg_xr_k(int64_t n, VT *x, VT *r, const VT
     __shared__ double sh[4];
     const VT alpha = (VT)scal[kAlpha];
     double acc = 0.0;
-    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+    grid_loop4(n, [&](int64_t i) {
         x[i] += alpha * p[i];
         const VT ri = r[i] - alpha * q[i];
         r[i] = ri;
         acc += (double)ri * (double)ri;
-    }
+    });
     const double t = block_sum(acc, sh);
     if (threadIdx.x == 0) part[blockIdx.x] = t;
 }
@@ -927,19 +941,18 @@ __global__ __launch_bounds__(256) void cg_xr_k(int64_t n, VT *x, VT *r, const VT
 template <class VT>
 __global__ __launch_bounds__(256) void cg_p_k(int64_t n, VT *p, const VT *r, const double *scal) {
     const VT beta = (VT)scal[kBeta];
-    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
-        p[i] = r[i] + beta * p[i];
+    grid_loop4(n, [&](int64_t i) { p[i] = r[i] + beta * p[i]; });
 }
 
 // r64 = b - q64 ; partial sums of r64.r64
 __global__ __launch_bounds__(256) void resid_k(int64_t n, const double *b, const double *q, double *r, double *part) {
     __shared__ double sh[4];
     double acc = 0.0;
-    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+    grid_loop4(n, [&](int64_t i) {
         const double ri = b[i] - q[i];
         r[i] = ri;
         acc += ri * ri;
-    }
+    });
     const double t = block_sum(acc, sh);
     if (threadIdx.x == 0) part[blockIdx.x] = t;
 }
@@ -949,31 +962,30 @@ __global__ __launch_bounds__(256) void refine_start_k(int64_t n, const double *r
                                                       float *p, double *part) {
     __shared__ double sh[4];
     double acc = 0.0;
-    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+    grid_loop4(n, [&](int64_t i) {
         const float ri = (float)(r64[i] * s);
         r[i] = ri;
         p[i] = ri;
         d[i] = 0.0f;
         acc += (double)ri * (double)ri;
-    }
+    });
     const double t = block_sum(acc, sh);
     if (threadIdx.x == 0) part[blockIdx.x] = t;
 }
 
 // x64 += d32 * inv_s
 __global__ __launch_bounds__(256) void refine_add_k(int64_t n, double *x, const float *d, double inv_s) {
-    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
-        x[i] += (double)d[i] * inv_s;
+    grid_loop4(n, [&](int64_t i) { x[i] += (double)d[i] * inv_s; });
 }
 
 template <class VT>
 __global__ __launch_bounds__(256) void copy_k(int64_t n, const VT *a, VT *b) {
-    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) b[i] = a[i];
+    grid_loop4(n, [&](int64_t i) { b[i] = a[i]; });
 }
 
 template <class VT>
 __global__ __launch_bounds__(256) void fill_k(int64_t n, VT *a, VT v) {
-    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) a[i] = v;
+    grid_loop4(n, [&](int64_t i) { a[i] = v; });
 }
 
 // ---------------------------------------------------------------------------
