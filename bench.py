@@ -173,6 +173,22 @@ def achievable_read_gbs(torch, rg, nbytes=2 << 30, reps=10):
     return nbytes / (float(np.mean(t)) * 1e-3) / 1e9
 
 
+def gather_floor_us(torch, rg, c, reps):
+    """Time of the gather-floor probe over the matrix's own CSR (column,
+    value) arrays: stream them once and gather x per entry, nothing else;
+    rotating copies like the SpMV."""
+    copies = max(1, min(c.copies, 8))
+    cols = [torch.from_numpy(np.ascontiguousarray(c.A.col, np.int32)).to("cuda:0") for _ in range(copies)]
+    vals = [torch.from_numpy(np.ascontiguousarray(c.A.val, np.float32)).to("cuda:0") for _ in range(copies)]
+    out = torch.empty((c.A.nnz + 7) // 8, device="cuda:0")
+    for i in range(3):
+        rg.rgcsr_gather_floor(cols[i % copies], vals[i % copies], c.xs[i % c.copies], out)
+    ms = _mean_launch_ms(torch, lambda i: rg.rgcsr_gather_floor(cols[i % copies], vals[i % copies],
+                                                                 c.xs[i % c.copies], out), reps)
+    del cols, vals, out
+    return ms * 1e3
+
+
 def bench_spmm(args, torch, rg, W):
     """Multi-RHS SpMM on the Zipf matrix, k in {1, 4, 16, 32}, one launch per k,
     against k sequential single-vector SpMVs."""
@@ -635,6 +651,7 @@ def main():
         hyb_ms.append(timed_steps(lambda i, c=c: c.hyb_spmv(i, rg))[0] / K)
 
     read_gbs = achievable_read_gbs(torch, rg)
+    floors = {c.name: gather_floor_us(torch, rg, c, K) for c in cases}
     flops = sum(c.flops for c in cases)
     value = flops * K / (total_ms * 1e-3) / 1e9
     value_graph = flops * K / (graph_ms * 1e-3) / 1e9
@@ -652,7 +669,8 @@ def main():
                       "us_median_events_around_each": 1e3 * float(np.median(per_kernel[ci])),
                       "gflops": c.flops / (t * 1e-3) / 1e9, "gbs": c.bytes / (t * 1e-3) / 1e9,
                       "hbm_frac": c.bytes / (t * 1e-3) / 1e9 / HBM_PEAK_GBS,
-                      "frac_of_achievable_read": c.bytes / (t * 1e-3) / 1e9 / read_gbs},
+                      "frac_of_achievable_read": c.bytes / (t * 1e-3) / 1e9 / read_gbs,
+                      "gather_floor_us": floors[c.name], "gather_floor_over_time": floors[c.name] / (1e3 * t)},
             "hybrid": {"us": 1e3 * th, "gflops": c.flops / (th * 1e-3) / 1e9,
                        "gbs": c.bytes / (th * 1e-3) / 1e9, "hbm_frac": c.bytes / (th * 1e-3) / 1e9 / HBM_PEAK_GBS,
                        "ell_width": c.hyb_info["ell_width"], "coo_nnz": c.hyb_info["coo_nnz"]},
@@ -687,7 +705,8 @@ def main():
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "traffic": tr,
                      "alg_bytes_per_launch": dc.bytes, "avg_launch_us": t_dom * 1e6,
-                     "achievable_read_gbs": read_gbs, "frac_of_achievable_read": achieved / read_gbs},
+                     "achievable_read_gbs": read_gbs, "frac_of_achievable_read": achieved / read_gbs,
+                     "gather_floor_us": floors[dc.name], "gather_floor_over_time": floors[dc.name] / (t_dom * 1e6)},
         "launch": "eager launches; replaying each step from a HIP graph gives value_graph",
         "value_graph": value_graph,
         "ms_per_step_graph": graph_ms / K,

@@ -409,6 +409,17 @@ rgcsr_status rgcsr_rcm_order(int64_t n, int64_t nnz, const int64_t *row_ptr, con
  * misaligned argument. */
 rgcsr_status rgcsr_stream_read(const void *buf, int64_t bytes, void *sink, void *stream);
 
+/* Gather floor of a matrix: reads n (column, value) pairs (col[n] int32,
+ * val[n] float32, the matrix's CSR arrays) and gathers x[col[k]] for each,
+ * with nothing else of an SpMV (no rows, no cross-lane sums): each of the
+ * ceil(n / 8) lanes writes one partial sum to out (device, ceil(n / 8)
+ * floats, meaningless as results).  Timing it bounds what any SpMV over the
+ * same entries can reach when the x gathers dominate (Section 3.4 models the
+ * bytes; random gathers are limited by the request rate instead).  Every
+ * col[k] must lie in [0, n_cols) of x (not checked on the device). */
+rgcsr_status rgcsr_gather_floor(const int32_t *col, const float *val, int64_t n, const float *x, int64_t n_cols,
+                                float *out, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -506,6 +506,17 @@ def rgcsr_rcm_order(A) -> np.ndarray:
     return perm
 
 
+def rgcsr_gather_floor(col, val, x, out, stream=None) -> None:
+    """The gather-floor probe over device arrays col (int32), val (float32)
+    and x (float32); out holds ceil(len(col) / 8) floats."""
+    for t, nm in ((col, "col"), (val, "val"), (x, "x"), (out, "out")):
+        _dev_check(t, nm)
+    n = col.numel()
+    if val.numel() != n or out.numel() < (n + 7) // 8:
+        raise ValueError("sizes do not match")
+    _lib.call("rgcsr_gather_floor", _ptr(col), _ptr(val), n, _ptr(x), x.numel(), _ptr(out), _stream(stream))
+
+
 def rgcsr_stream_read(buf, sink, stream=None) -> None:
     """One streaming read of the device tensor buf (the achievable-bandwidth
     probe); sink is a small device tensor the kernel may write."""

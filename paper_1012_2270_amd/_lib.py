@@ -100,6 +100,7 @@ SIGNATURES = {
     "rgcsr_last_error": (ctypes.c_char_p, []),
     "rgcsr_version": (ctypes.c_char_p, []),
     "rgcsr_stream_read": (c_int, [c_vp, c_i64, c_vp, c_vp]),
+    "rgcsr_gather_floor": (c_int, [c_vp, c_vp, c_i64, c_vp, c_i64, c_vp, c_vp]),
     "rgcsr_rcm_order": (c_int, [c_i64, c_i64, c_vp, c_vp, c_vp]),
 }
 

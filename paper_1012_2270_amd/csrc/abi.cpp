@@ -572,6 +572,16 @@ rgcsr_status rgcsr_rcm_order(int64_t n, int64_t nnz, const int64_t *row_ptr, con
     ABI_CATCH
 }
 
+rgcsr_status rgcsr_gather_floor(const int32_t *col, const float *val, int64_t n, const float *x, int64_t n_cols,
+                                float *out, void *stream) {
+    ABI_TRY
+    if (n < 0 || (n > 0 && (!col || !val || !x || !out))) fail(RGCSR_EINVAL, "bad argument");
+    if ((n + 7) / 8 / 256 >= INT32_MAX) fail(RGCSR_EOVERFLOW, "too many entries");
+    (void)n_cols;
+    HIPCHK(launch_gather_floor(col, val, n, x, out, (hipStream_t)stream));
+    ABI_CATCH
+}
+
 rgcsr_status rgcsr_stream_read(const void *buf, int64_t bytes, void *sink, void *stream) {
     ABI_TRY
     if (!buf || !sink || bytes < 0) fail(RGCSR_EINVAL, "buf and sink must be device pointers, bytes >= 0");

@@ -82,6 +82,8 @@ hipError_t launch_refine_start(int64_t n, const double *r64, double s, float *r,
 hipError_t launch_refine_add(int64_t n, double *x, const float *d, double inv_s, int nb, hipStream_t st);
 hipError_t launch_copy(int64_t n, const void *a, void *b, int f64, int nb, hipStream_t st);
 hipError_t launch_stream_read(const void *a, int64_t n16, int32_t *sink, int nb, hipStream_t st);
+hipError_t launch_gather_floor(const int32_t *col, const float *val, int64_t n, const float *x, float *out,
+                               hipStream_t st);
 hipError_t launch_zero(int64_t n, void *a, int esz, int nb, hipStream_t st);
 
 }  // namespace rg

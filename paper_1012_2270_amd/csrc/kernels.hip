@@ -1304,6 +1304,41 @@ __global__ __launch_bounds__(256) void stream_read_k(const i32x4 *a, int64_t n, 
     if (v == 0x5bd1e995) sink[0] = v;
 }
 
+// Gather floor: the (column, value) stream of a matrix in CSR order with one
+// x gather per entry and nothing else (no rows, no reduction across lanes):
+// lane l of the grid takes entries l, l + S, ..., l + 7S (S = grid size) and
+// writes one partial sum.  Its time bounds what any SpMV over the same entries
+// can reach when x gathers dominate.
+__global__ __launch_bounds__(256) void gather_floor_k(const int32_t *col, const float *val, int64_t n,
+                                                      const float *x, float *out) {
+    const int64_t S = (int64_t)gridDim.x * 256;
+    const int64_t l = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    int32_t c[8];
+    float v[8];
+#pragma unroll
+    for (int u = 0; u < 8; u++) {
+        const int64_t e = l + u * S < n ? l + u * S : 0;
+        c[u] = __builtin_nontemporal_load(col + e);
+        v[u] = __builtin_nontemporal_load(val + e);
+    }
+    float acc = 0.f;
+#pragma unroll
+    for (int u = 0; u < 8; u++) {
+        const float xv = x[c[u]];
+        acc = l + u * S < n ? __builtin_fmaf(v[u], xv, acc) : acc;
+    }
+    if (l < (n + 7) / 8) out[l] = acc;
+}
+
+hipError_t launch_gather_floor(const int32_t *col, const float *val, int64_t n, const float *x, float *out,
+                               hipStream_t st) {
+    if (n == 0) return hipSuccess;
+    const int64_t threads = (n + 7) / 8;
+    hipLaunchKernelGGL(gather_floor_k, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, st, col, val, n, x,
+                       out);
+    return check_launch();
+}
+
 hipError_t launch_stream_read(const void *a, int64_t n16, int32_t *sink, int nb, hipStream_t st) {
     if (n16 == 0) return hipSuccess;
     hipLaunchKernelGGL(stream_read_k, dim3(nb), dim3(256), 0, st, (const i32x4 *)a, n16, sink);

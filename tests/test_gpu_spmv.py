@@ -368,6 +368,28 @@ def test_stream_read_helper(torch_cuda):
     assert e.value.status == 1
 
 
+def test_gather_floor_helper(torch_cuda):
+    """The gather-floor probe visits every entry once: lane l sums entries
+    l, l + S, ..., l + 7S (S = lanes rounded up to whole workgroups)."""
+    torch = torch_cuda
+    n, ncols = 100_003, 5000
+    rng = np.random.default_rng(3)
+    col = rng.integers(0, ncols, n).astype(np.int32)
+    val = rng.standard_normal(n).astype(np.float32)
+    x = rng.standard_normal(ncols).astype(np.float32)
+    lanes = (n + 7) // 8
+    S = (lanes + 255) // 256 * 256
+    out = torch.empty(lanes, device="cuda:0")
+    rg.rgcsr_gather_floor(dev(col), dev(val), dev(x), out)
+    got = host(out)
+    prod = np.zeros(S * 8)
+    prod[:n] = val.astype(np.float64) * x[col].astype(np.float64)
+    ref = prod.reshape(8, S).sum(axis=0)[:lanes]
+    assert np.max(np.abs(got - ref)) <= 1e-5 * max(1.0, float(np.max(np.abs(ref))))
+    with pytest.raises(ValueError):
+        rg.rgcsr_gather_floor(dev(col), dev(val[:-1]), dev(x), out)
+
+
 @pytest.mark.slow
 def test_full_size_laplace3d_and_zipf(torch_cuda, oracle):
     """The benchmark matrices at full size, in the benchmark's layouts."""
