@@ -523,20 +523,20 @@ __device__ __forceinline__ void spmv_wave_long(const SpmvParams &P, int32_t w, i
     if (ok && q == 0) store_row<A, K>(Y + (int64_t)orow * P.ldy, acc);
 }
 
-// Same work item, single right-hand side with float accumulation: the item's
-// nonzeros (at most kWaveRowMax, contiguous) are loaded element-parallel, lane
-// l taking elements l, l + 64, ..., so the value/column loads need no row
-// bounds and every lane is busy; the products go to this wavefront's LDS
-// slice and the item's lane-per-row mapping then sums them in the same
+// Same work item, single right-hand side: the item's nonzeros (at most
+// kWaveRowMax, contiguous) are loaded element-parallel, lane l taking elements
+// l, l + 64, ..., so the value/column loads need no row bounds and every lane
+// is busy; the products (in the accumulation type A) go to this wavefront's
+// LDS slice and the item's lane-per-row mapping then sums them in the same
 // strided order as spmv_wave_long.
-template <int VD, int LP>
-__device__ __forceinline__ void spmv_wave_long_lds(const SpmvParams &P, int32_t w, int lane, float *buf) {
+template <int VD, class A, int LP>
+__device__ __forceinline__ void spmv_wave_long_lds(const SpmvParams &P, int32_t w, int lane, A *buf) {
     using V = Val<VD>;
     using S = typename V::S;
     constexpr int U = kWaveRowMax / 64;
-    float *Y = (float *)P.y;
-    const float *X = (const float *)P.x;
-    const uint32_t xrow = (uint32_t)(P.ldx * (int64_t)sizeof(float));
+    A *Y = (A *)P.y;
+    const A *X = (const A *)P.x;
+    const uint32_t xrow = (uint32_t)(P.ldx * (int64_t)sizeof(A));
     const LongItem it = ldc(P.wave_work, w);
     const int64_t item0 = ldc(P.long_ptr, (int64_t)it.a);
     const int32_t n = (int32_t)(ldc(P.long_ptr, (int64_t)it.a + it.b) - item0);
@@ -544,7 +544,7 @@ __device__ __forceinline__ void spmv_wave_long_lds(const SpmvParams &P, int32_t 
     const int32_t *cb = P.long_col + item0;
     S v[U];
     int32_t ci[U];
-    float xv[U];
+    A xv[U];
 #pragma unroll
     for (int u = 0; u < U; u++) {
         const uint32_t o = lane + 64 * u < n ? (uint32_t)(lane + 64 * u) : 0u;
@@ -562,15 +562,15 @@ __device__ __forceinline__ void spmv_wave_long_lds(const SpmvParams &P, int32_t 
 #pragma unroll
     for (int u = 0; u < U; u++) xv[u] = ldx32<LP>(X, ci[u], xrow);
 #pragma unroll
-    for (int u = 0; u < U; u++) buf[lane + 64 * u] = V::template cvt<float>(v[u]) * xv[u];
-    if (lane == 0) buf[kWaveRowMax] = 0.f;  // terms past a row read this slot
+    for (int u = 0; u < U; u++) buf[lane + 64 * u] = V::template cvt<A>(v[u]) * xv[u];
+    if (lane == 0) buf[kWaveRowMax] = A(0);  // terms past a row read this slot
     // the slice is private to this wavefront: LDS accesses of one wavefront
     // complete in order, only the compiler must not move the reads up
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     const int32_t nj = ok && e - b > q ? (e - b - q + TL - 1) >> sh : 0;
-    float acc = 0.f;
+    A acc = A(0);
 #pragma nounroll
     for (int j0 = 0; j0 < U; j0 += 4)
 #pragma unroll
@@ -620,8 +620,8 @@ __device__ __forceinline__ void spmv_block_item(const SpmvParams &P, int32_t u, 
 }
 
 template <int VD, class A, int K, int T, int R, bool LONG, int LP>
-__device__ __forceinline__ void spmv_unit(const SpmvParams &P, int32_t u, int lane, int wv, A (*red)[K], float *lbuf) {
-    constexpr bool kLdsLong = LONG && K == 1 && sizeof(A) == 4;
+__device__ __forceinline__ void spmv_unit(const SpmvParams &P, int32_t u, int lane, int wv, A (*red)[K], A *lbuf) {
+    constexpr bool kLdsLong = LONG && K == 1;
     if (LONG && u < P.n_block_items) {
         spmv_block_item<VD, A, K, LP>(P, u, red);
         return;
@@ -629,7 +629,7 @@ __device__ __forceinline__ void spmv_unit(const SpmvParams &P, int32_t u, int la
     const int32_t w = __builtin_amdgcn_readfirstlane((u - (LONG ? P.n_block_items : 0)) * kBlockWaves + wv);
     if (w >= P.n_wave_items) return;
     if (LONG && w < P.n_wave_long) {
-        if constexpr (kLdsLong) spmv_wave_long_lds<VD, LP>(P, w, lane, lbuf);
+        if constexpr (kLdsLong) spmv_wave_long_lds<VD, A, LP>(P, w, lane, lbuf);
         else spmv_wave_long<VD, A, K, LP>(P, w, lane);
     } else {
         spmv_short<VD, A, K, T, R, LP>(P, w - (LONG ? P.n_wave_long : 0), lane);
@@ -641,9 +641,9 @@ __device__ __forceinline__ void spmv_unit(const SpmvParams &P, int32_t u, int la
 // a persistent grid that strides over the units.
 template <int VD, class A, int K, int T, int R, bool LONG, int LP>
 __global__ __launch_bounds__(kBlockThreads) void rgcsr_spmv_k(SpmvParams P) {
-    constexpr bool kLdsLong = LONG && K == 1 && sizeof(A) == 4;
+    constexpr bool kLdsLong = LONG && K == 1;
     __shared__ A red[kBlockWaves][K];
-    __shared__ float lbuf[kLdsLong ? kBlockWaves : 1][kLdsLong ? kWaveRowMax + 1 : 1];
+    __shared__ A lbuf[kLdsLong ? kBlockWaves : 1][kLdsLong ? kWaveRowMax + 1 : 1];
     const int lane = threadIdx.x & 63;
     const int wv = threadIdx.x >> 6;
     const int nwg = gridDim.x;

@@ -120,6 +120,19 @@ def test_zipf_sorted_with_long_rows(torch_cuda, oracle):
         M.close()
 
 
+def test_zipf_fp64_long_rows(torch_cuda, oracle):
+    """Double values, vectors and accumulation through every long-row path
+    (LDS-staged wavefront items and workgroup items) on a power-law matrix."""
+    A = W.zipf_matrix(200_000, seed=6).astype(np.float64)
+    x = W.uniform_vector(A.n_cols, 16, np.float64)
+    for (G, T, sigma, tau) in [(64, 1, 512, 16), (64, 1, 200_000, 40), (64, 2, 4096, 32)]:
+        say("zipf 200k fp64", G, T, sigma, tau)
+        M = rg.rgcsr_from_csr(A, G=G, T=T, sigma=sigma, tau=tau, value_dtype="f64")
+        assert M.info["long_work"] > 0
+        check_spmv(oracle, A, x, host(M.spmv(dev(x))), tol=TOL_F64)
+        M.close()
+
+
 @pytest.mark.parametrize("sigma,tau", [(4096, 32), (512, 16), (1, -1), (1 << 40, 24)])
 def test_rows_per_lane_schedules_agree(torch_cuda, oracle, sigma, tau):
     """Every kernel schedule (rows per lane fixed at 1, 2, 4, 8 or chosen per
