@@ -183,6 +183,37 @@ rgcsr_status rgcsr_from_csr(int64_t n_rows, int64_t n_cols, int64_t nnz,
                             const rgcsr_opts *opts, int inputs_on_device, void *stream,
                             rgcsr_handle *out);
 
+/* Caller-owned device memory (for callers whose allocator, e.g. PyTorch's,
+ * owns every device buffer), in two steps over host CSR arrays:
+ *
+ * rgcsr_plan_from_csr: validates (per opts->validate) and converts the host
+ * CSR input on the host, exactly as rgcsr_from_csr does, and keeps the
+ * layout in a host-side plan.  Arguments as rgcsr_from_csr with
+ * inputs_on_device = 0; needs no GPU.
+ * rgcsr_plan_device_bytes: bytes of device memory the handle needs (its
+ * arrays and, with build_transpose, those of A^T), one contiguous block.
+ * rgcsr_build: places the handle's arrays in [device_buf, device_buf +
+ * buf_bytes) -- a device pointer, 256-byte aligned, at least the plan's
+ * device bytes, else RGCSR_EINVAL before any device work -- uploads the
+ * layout on `stream` and synchronises it.  The handle borrows the buffer:
+ * it must stay allocated and untouched until rgcsr_destroy, which does not
+ * free it.  device_buf = NULL: the handle allocates and owns the block as
+ * rgcsr_from_csr does.  A plan builds one handle: once a build has passed its
+ * argument checks (whether it then succeeds or not), rgcsr_build and
+ * rgcsr_plan_device_bytes on that plan return RGCSR_EINVAL; argument errors
+ * leave the plan usable.  rgcsr_clone of a borrowing handle returns a handle
+ * that owns its memory.
+ * rgcsr_plan_destroy: frees the plan (host memory only); NULL is allowed. */
+typedef struct rgcsr_plan_s *rgcsr_plan;
+rgcsr_status rgcsr_plan_from_csr(int64_t n_rows, int64_t n_cols, int64_t nnz,
+                                 const int64_t *row_ptr, const int32_t *col_idx,
+                                 const void *vals, rgcsr_dtype vals_dtype,
+                                 const rgcsr_opts *opts, rgcsr_plan *out);
+rgcsr_status rgcsr_plan_device_bytes(rgcsr_plan plan, int64_t *bytes);
+rgcsr_status rgcsr_build(rgcsr_plan plan, void *device_buf, int64_t buf_bytes, void *stream,
+                         rgcsr_handle *out);
+rgcsr_status rgcsr_plan_destroy(rgcsr_plan plan);
+
 /* rgcsr_from_csr_batch: build one handle holding `count` independent host CSR
  * matrices as a block-diagonal matrix: matrix m's rows follow matrix m-1's,
  * and so do its columns, so x and y of the batch are the per-matrix vectors

@@ -128,8 +128,9 @@ def hyb_choose_width(A, value_dtype: str = "f32") -> int:
 class RgCSRMatrix:
     """Owns one librgcsr handle (a matrix or a block-diagonal batch)."""
 
-    def __init__(self, handle: int):
+    def __init__(self, handle: int, memory=None):
         self._h = ctypes.c_void_p(handle)
+        self._memory = memory  # caller-owned device buffer the handle borrows (rgcsr_build)
         info = _lib.Info()
         _lib.call("rgcsr_info", self._h, ctypes.byref(info))
         self.info = info.as_dict()
@@ -144,6 +145,7 @@ class RgCSRMatrix:
         if self._h is not None and self._h.value:
             _lib.call("rgcsr_destroy", self._h)
         self._h = None
+        self._memory = None  # released only after the handle is gone
 
     def __del__(self):
         try:
@@ -188,6 +190,50 @@ def rgcsr_from_csr(A, opts: _lib.Opts | None = None, stream=None, bf16_bits: boo
     _lib.call("rgcsr_from_csr", A.n_rows, A.n_cols, int(rp[-1]), _ptr(rp), _ptr(col), _ptr(val),
               _code_of_numpy(val, bf16_bits), ctypes.byref(opts), 0, _stream(stream), ctypes.byref(h))
     return RgCSRMatrix(h.value)
+
+
+class RgCSRPlan:
+    """Host-side layout of one matrix (rgcsr_plan_from_csr); build() places
+    the device arrays in a torch-allocated buffer the handle borrows."""
+
+    def __init__(self, handle: int):
+        self._p = ctypes.c_void_p(handle)
+        b = ctypes.c_int64()
+        _lib.call("rgcsr_plan_device_bytes", self._p, ctypes.byref(b))
+        self.device_bytes = b.value
+
+    def build(self, buffer=None, stream=None) -> RgCSRMatrix:
+        """buffer: a CUDA uint8 tensor of at least device_bytes (allocated
+        here with torch when None); the returned matrix keeps it alive."""
+        torch = _torch()
+        if buffer is None:
+            buffer = torch.empty(max(1, self.device_bytes), dtype=torch.uint8, device="cuda")
+        _dev_check(buffer, "buffer")
+        h = ctypes.c_void_p()
+        _lib.call("rgcsr_build", self._p, _ptr(buffer), int(buffer.numel() * buffer.element_size()), _stream(stream),
+                  ctypes.byref(h))
+        return RgCSRMatrix(h.value, memory=buffer)
+
+    def close(self):
+        if self._p is not None and self._p.value:
+            _lib.call("rgcsr_plan_destroy", self._p)
+        self._p = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def rgcsr_plan_from_csr(A, opts: _lib.Opts | None = None, bf16_bits: bool = False, **kw) -> RgCSRPlan:
+    """Host conversion of a host CSR matrix, device memory left to the caller."""
+    opts = opts if opts is not None else make_opts(**kw)
+    rp, col, val = _csr_arrays(A)
+    p = ctypes.c_void_p()
+    _lib.call("rgcsr_plan_from_csr", A.n_rows, A.n_cols, int(rp[-1]), _ptr(rp), _ptr(col), _ptr(val),
+              _code_of_numpy(val, bf16_bits), ctypes.byref(opts), ctypes.byref(p))
+    return RgCSRPlan(p.value)
 
 
 def rgcsr_from_csr_device(n_rows: int, n_cols: int, row_ptr, col, vals, opts: _lib.Opts, stream=None) -> RgCSRMatrix:

@@ -4,6 +4,7 @@
 
 #include <algorithm>
 #include <chrono>
+#include <memory>
 #include <cmath>
 #include <mutex>
 #include <new>
@@ -59,10 +60,11 @@ struct Arena {
         req.push_back({(void **)p, count * sizeof(T)});
         total += (count * sizeof(T) + 255) / 256 * 256;
     }
-    void *commit() {
+    // Places the arrays in `base` (caller memory of at least `total` bytes,
+    // 256-byte aligned) or, when null, in one new hipMalloc block.
+    void *commit(void *base = nullptr) {
         if (total == 0) return nullptr;
-        void *base = nullptr;
-        HIPCHK(hipMalloc(&base, total));
+        if (!base) HIPCHK(hipMalloc(&base, total));
         size_t off = 0;
         for (auto &r : req) {
             *r.first = (char *)base + off;
@@ -97,6 +99,7 @@ struct rgcsr_matrix_s {
     std::vector<int64_t> row_off, col_off;
     void *mem = nullptr;
     size_t bytes = 0;
+    bool owns_mem = true;  // false: the arrays live in caller memory (rgcsr_build)
     int64_t *gp = nullptr;
     int32_t *grp_row0 = nullptr, *short_len = nullptr, *short_row = nullptr, *slot_col = nullptr;
     void *slot_val = nullptr;
@@ -158,6 +161,23 @@ struct Built {
     HostLayout LTmap;    // layout of A^T whose "values" are source indices
     std::vector<int64_t> row_ptr;  // global CSR row pointers
 };
+
+}  // namespace
+
+// Host layout of one matrix and its handle(s) with the device arrays listed
+// but not placed; rgcsr_build hands the handles over.
+struct rgcsr_plan_s {
+    Built B;
+    bool with_row_ptr = false;
+    Arena a, aT;
+    rgcsr_matrix_s *h = nullptr, *hT = nullptr;
+    ~rgcsr_plan_s() {
+        delete h;
+        delete hT;
+    }
+};
+
+namespace {
 
 void build_host(Built &B, const LayoutParams &p, int vdt, int32_t count, const int64_t *n_rows,
                 const int64_t *n_cols, const int64_t *const *rp, const int32_t *const *col,
@@ -276,12 +296,13 @@ void choose_schedule(rgcsr_matrix_s *h, const HostLayout &L, int64_t short_nnz, 
     h->R = R;
 }
 
-rgcsr_matrix_s *make_device(const HostLayout &L, const std::vector<int64_t> *row_ptr,
-                            const HostLayout *map, hipStream_t st, int32_t rows_per_lane = 0,
-                            int32_t pad_loads = -1, int32_t load_policy = 0) {
+// A handle whose fields describe the host layout and whose device arrays are
+// listed in `a` but not yet placed (plan step of rgcsr_plan_from_csr and of
+// make_device).  Host work only.
+rgcsr_matrix_s *prepare_handle(const HostLayout &L, bool with_row_ptr, const HostLayout *map, Arena &a,
+                               int32_t rows_per_lane, int32_t pad_loads, int32_t load_policy) {
     auto *h = new rgcsr_matrix_s();
     try {
-        h->device = current_device();
         h->prm = LayoutParams{L.G, L.T, L.sigma, L.tau};
         h->vdt = L.vdt;
         h->esz = L.esz;
@@ -312,7 +333,6 @@ rgcsr_matrix_s *make_device(const HostLayout &L, const std::vector<int64_t> *row
         if (max_group * std::max(L.esz, 4) >= (int64_t(1) << 32))
             fail(RGCSR_EOVERFLOW, "a row group holds 4 GiB or more; use a long-row threshold");
 
-        Arena a;
         a.add(&h->gp, L.gp.size());
         a.add(&h->grp_row0, h->ragged ? L.grp_row0.size() : 0);
         a.add(&h->short_len, L.short_len.size());
@@ -328,35 +348,59 @@ rgcsr_matrix_s *make_device(const HostLayout &L, const std::vector<int64_t> *row
         a.add((uint8_t **)&h->long_val, L.long_val.size());
         a.add(&h->long_col, L.long_col.size());
         a.add((uint8_t **)&h->partial, (size_t)L.work.n_partials * 32 * sizeof(double));
-        if (row_ptr) a.add(&h->row_ptr, row_ptr->size());
+        if (with_row_ptr) a.add(&h->row_ptr, (size_t)L.n_rows + 1);
         if (map) {
             a.add(&h->t_map_slot, (size_t)map->slots);
             a.add(&h->t_map_long, (size_t)map->long_nnz);
         }
-        h->mem = a.commit();
         h->bytes = a.total;
-        upload(h->gp, L.gp, st);
-        if (h->ragged) upload(h->grp_row0, L.grp_row0, st);
-        upload(h->short_len, L.short_len, st);
-        if (h->perm) upload(h->short_row, L.short_row, st);
-        upload_bytes(h->slot_val, L.slot_val, st);
-        upload(h->slot_col, L.slot_col, st);
-        upload(h->short_items, h->items, st);
-        upload(h->wave_work, L.work.wave, st);
-        upload(h->block_work, L.work.block, st);
-        upload(h->combine, L.work.combine, st);
-        upload(h->long_row, L.long_row, st);
-        upload(h->long_ptr, L.long_ptr, st);
-        upload_bytes(h->long_val, L.long_val, st);
-        upload(h->long_col, L.long_col, st);
-        if (row_ptr) upload(h->row_ptr, *row_ptr, st);
-        if (map) {
-            if (map->slots) HIPCHK(hipMemcpyAsync(h->t_map_slot, map->slot_val.data(), (size_t)map->slots * 4, hipMemcpyHostToDevice, st));
-            if (map->long_nnz) HIPCHK(hipMemcpyAsync(h->t_map_long, map->long_val.data(), (size_t)map->long_nnz * 4, hipMemcpyHostToDevice, st));
-        }
-        HIPCHK(hipStreamSynchronize(st));
     } catch (...) {
-        if (h->mem) (void)hipFree(h->mem);
+        delete h;
+        throw;
+    }
+    return h;
+}
+
+// Places a prepared handle's arrays (in `buf` when given: caller memory the
+// handle borrows; else in a block the handle owns) and uploads the layout.
+// On failure the handle is left for the caller to free.
+void place_and_upload(rgcsr_matrix_s *h, Arena &a, const HostLayout &L, const std::vector<int64_t> *row_ptr,
+                      const HostLayout *map, void *buf, hipStream_t st) {
+    h->device = current_device();
+    h->owns_mem = buf == nullptr;
+    h->mem = a.commit(buf);
+    upload(h->gp, L.gp, st);
+    if (h->ragged) upload(h->grp_row0, L.grp_row0, st);
+    upload(h->short_len, L.short_len, st);
+    if (h->perm) upload(h->short_row, L.short_row, st);
+    upload_bytes(h->slot_val, L.slot_val, st);
+    upload(h->slot_col, L.slot_col, st);
+    upload(h->short_items, h->items, st);
+    upload(h->wave_work, L.work.wave, st);
+    upload(h->block_work, L.work.block, st);
+    upload(h->combine, L.work.combine, st);
+    upload(h->long_row, L.long_row, st);
+    upload(h->long_ptr, L.long_ptr, st);
+    upload_bytes(h->long_val, L.long_val, st);
+    upload(h->long_col, L.long_col, st);
+    if (row_ptr && h->row_ptr) upload(h->row_ptr, *row_ptr, st);
+    if (map) {
+        if (map->slots) HIPCHK(hipMemcpyAsync(h->t_map_slot, map->slot_val.data(), (size_t)map->slots * 4, hipMemcpyHostToDevice, st));
+        if (map->long_nnz) HIPCHK(hipMemcpyAsync(h->t_map_long, map->long_val.data(), (size_t)map->long_nnz * 4, hipMemcpyHostToDevice, st));
+    }
+    HIPCHK(hipStreamSynchronize(st));
+}
+
+rgcsr_matrix_s *make_device(const HostLayout &L, const std::vector<int64_t> *row_ptr,
+                            const HostLayout *map, hipStream_t st, int32_t rows_per_lane = 0,
+                            int32_t pad_loads = -1, int32_t load_policy = 0) {
+    Arena a;
+    rgcsr_matrix_s *h = prepare_handle(L, row_ptr != nullptr, map, a, rows_per_lane, pad_loads, load_policy);
+    try {
+        place_and_upload(h, a, L, row_ptr, map, nullptr, st);
+    } catch (...) {
+        (void)hipStreamSynchronize(st);
+        if (h->mem && h->owns_mem) (void)hipFree(h->mem);
         delete h;
         throw;
     }
@@ -444,7 +488,7 @@ rgcsr_matrix_s *make_device_on_device(DevPlan &P, const LayoutParams &p, int vdt
 void free_handle(rgcsr_matrix_s *h) {
     if (!h) return;
     if (h->AT) free_handle(h->AT);
-    if (h->mem) (void)hipFree(h->mem);
+    if (h->mem && h->owns_mem) (void)hipFree(h->mem);
     delete h;
 }
 
@@ -716,6 +760,83 @@ rgcsr_status rgcsr_from_csr(int64_t n_rows, int64_t n_cols, int64_t nnz, const i
     ABI_CATCH
 }
 
+rgcsr_status rgcsr_plan_from_csr(int64_t n_rows, int64_t n_cols, int64_t nnz, const int64_t *row_ptr,
+                                 const int32_t *col_idx, const void *vals, rgcsr_dtype vals_dtype,
+                                 const rgcsr_opts *opts, rgcsr_plan *out) {
+    ABI_TRY
+    if (!out) fail(RGCSR_EINVAL, "out is null");
+    *out = nullptr;
+    rgcsr_opts o;
+    if (opts) o = *opts; else rgcsr_default_opts(&o);
+    const LayoutParams p = resolve_opts(&o);
+    check_device_geometry(p);
+    check_dtype(o.value_dtype, "value_dtype");
+    check_dtype(vals_dtype, "vals");
+    if (n_rows < 0 || n_cols < 0 || nnz < 0) fail(RGCSR_EINVAL, "negative size");
+    if (!row_ptr) fail(RGCSR_EINVAL, "row_ptr is null");
+    if (!o.validate && row_ptr[n_rows] != nnz) fail(RGCSR_ECSR, "row_ptr[n_rows] != nnz");
+    std::unique_ptr<rgcsr_plan_s> P(new rgcsr_plan_s());
+    P->with_row_ptr = o.keep_csr_map != 0 || o.build_transpose != 0;
+    const bool tr = o.build_transpose != 0;
+    build_host(P->B, p, o.value_dtype, 1, &n_rows, &n_cols, &row_ptr, &col_idx, &vals, vals_dtype, o.validate != 0,
+               o.keep_csr_map != 0, tr);
+    P->h = prepare_handle(P->B.L, P->with_row_ptr, nullptr, P->a, o.rows_per_lane, o.pad_loads, o.load_policy);
+    if (tr) P->hT = prepare_handle(P->B.LT, false, &P->B.LTmap, P->aT, o.rows_per_lane, o.pad_loads, o.load_policy);
+    *out = P.release();
+    ABI_CATCH
+}
+
+rgcsr_status rgcsr_plan_device_bytes(rgcsr_plan plan, int64_t *bytes) {
+    ABI_TRY
+    if (!plan || !bytes) fail(RGCSR_EINVAL, "null argument");
+    if (!plan->h) fail(RGCSR_EINVAL, "the plan has been built already");
+    *bytes = (int64_t)(plan->a.total + plan->aT.total);
+    ABI_CATCH
+}
+
+rgcsr_status rgcsr_build(rgcsr_plan plan, void *device_buf, int64_t buf_bytes, void *stream, rgcsr_handle *out) {
+    ABI_TRY
+    if (!plan || !out) fail(RGCSR_EINVAL, "null argument");
+    *out = nullptr;
+    if (!plan->h) fail(RGCSR_EINVAL, "the plan has been built already");
+    const size_t total = plan->a.total + plan->aT.total;
+    if (device_buf) {
+        if (buf_bytes < 0 || (size_t)buf_bytes < total) fail(RGCSR_EINVAL, "device buffer smaller than the plan's device bytes");
+        if ((uintptr_t)device_buf % 256) fail(RGCSR_EINVAL, "device buffer not 256-byte aligned");
+    }
+    hipStream_t st = (hipStream_t)stream;
+    // the plan gives up its prepared handles whether or not the build succeeds
+    rgcsr_matrix_s *h = plan->h, *hT = plan->hT;
+    plan->h = plan->hT = nullptr;
+    auto drop = [&](rgcsr_matrix_s *x) {
+        if (!x) return;
+        if (x->mem && x->owns_mem) (void)hipFree(x->mem);
+        delete x;
+    };
+    try {
+        place_and_upload(h, plan->a, plan->B.L, plan->with_row_ptr ? &plan->B.row_ptr : nullptr, nullptr, device_buf, st);
+        if (hT) {
+            void *bufT = device_buf ? (void *)((char *)device_buf + plan->a.total) : nullptr;
+            place_and_upload(hT, plan->aT, plan->B.LT, nullptr, &plan->B.LTmap, bufT, st);
+        }
+    } catch (...) {
+        (void)hipStreamSynchronize(st);
+        drop(hT);
+        drop(h);
+        throw;
+    }
+    h->AT = hT;
+    plan->B = Built();
+    *out = h;
+    ABI_CATCH
+}
+
+rgcsr_status rgcsr_plan_destroy(rgcsr_plan plan) {
+    ABI_TRY
+    delete plan;
+    ABI_CATCH
+}
+
 rgcsr_status rgcsr_from_csr_batch(int32_t count, const int64_t *n_rows, const int64_t *n_cols,
                                   const int64_t *const *row_ptr, const int32_t *const *col_idx,
                                   const void *const *vals, rgcsr_dtype vals_dtype, const rgcsr_opts *opts,
@@ -975,6 +1096,7 @@ template <class H, class... P> void rebase(H *dst, const H *src, P H::*...member
 rgcsr_matrix_s *clone_handle(const rgcsr_matrix_s *A, hipStream_t st) {
     auto *h = new rgcsr_matrix_s(*A);
     h->mem = nullptr;
+    h->owns_mem = true;
     h->AT = nullptr;
     try {
         if (A->bytes) HIPCHK(hipMalloc(&h->mem, A->bytes));

@@ -279,3 +279,58 @@ def test_cg_f64(torch_cuda, oracle):
     assert st["converged"] and math.sqrt(float(np.dot(r, r))) / math.sqrt(float(np.dot(b, b))) <= 1e-10
     x_orc, it_orc, _ = oracle.cg(A, b, tol=1e-10)
     assert abs(st["inner_iterations"] - it_orc) <= 4   # same method, checked every 4 steps
+
+
+# ----------------------------------------------------------------------------
+# Caller-owned device memory (plan, then build into a torch buffer)
+# ----------------------------------------------------------------------------
+@pytest.mark.parametrize("lay", [dict(), dict(sigma=4000, tau=16, value_dtype="bf16"),
+                                 dict(keep_csr_map=True, build_transpose=True, tau=24)])
+def test_build_into_torch_memory(torch_cuda, oracle, lay):
+    """A handle built into a torch-allocated block holds the same arrays and
+    gives the same bits as one that allocates its own; the block is the
+    plan's size; a plan builds once."""
+    torch = torch_cuda
+    A = W.random_csr(4000, 3000, seed=31, max_len=40, empty_frac=0.1, long_rows=3, long_len=2500,
+                     dtype=np.float32)
+    x = W.uniform_vector(A.n_cols, 32, np.float32)
+    say("build into torch memory", lay)
+    P = rg.rgcsr_plan_from_csr(A, **lay)
+    buf = torch.empty(P.device_bytes + 512, dtype=torch.uint8, device="cuda:0")
+    M = P.build(buf[256:])          # an aligned view inside a larger tensor
+    Mo = rg.rgcsr_from_csr(A, **lay)
+    assert M.info["device_bytes"] == P.device_bytes == Mo.info["device_bytes"]
+    ed, eo = M.export(), Mo.export()
+    for k in ("gp", "short_len", "short_row", "slot_col", "long_row", "long_ptr", "long_col"):
+        np.testing.assert_array_equal(ed[k], eo[k], err_msg=k)
+    for k in ("slot_val", "long_val"):
+        np.testing.assert_array_equal(ed[k].view(np.uint8), eo[k].view(np.uint8), err_msg=k)
+    xd = dev(x)
+    y, yo = host(M.spmv(xd)), host(Mo.spmv(xd))
+    np.testing.assert_array_equal(y.view(np.uint32), yo.view(np.uint32))
+    vals64 = storage_values(oracle, A, lay["value_dtype"]) if "value_dtype" in lay else None
+    check_spmv(oracle, A, x, y, vals64=vals64)
+    if lay.get("build_transpose"):
+        dy = dev(W.normal_vector(A.n_rows, 33, np.float32))
+        dx, dxo = torch.empty(A.n_cols, device="cuda:0"), torch.empty(A.n_cols, device="cuda:0")
+        dv, dvo = torch.empty(A.nnz, device="cuda:0"), torch.empty(A.nnz, device="cuda:0")
+        rg.rgcsr_spmv_transpose_grad(M, xd, dy, dx, dv)
+        rg.rgcsr_spmv_transpose_grad(Mo, xd, dy, dxo, dvo)
+        np.testing.assert_array_equal(host(dx).view(np.uint32), host(dxo).view(np.uint32))
+        np.testing.assert_array_equal(host(dv).view(np.uint32), host(dvo).view(np.uint32))
+    with pytest.raises(rg.RgcsrError) as e:
+        P.build(buf[256:])
+    assert e.value.status == 1
+    # a clone owns its memory and outlives the borrowed block
+    C = M.clone()
+    M.close()
+    del buf
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(host(C.spmv(xd)).view(np.uint32), yo.view(np.uint32))
+    C.close()
+    Mo.close()
+    P.close()
+    # without a buffer the binding allocates one with torch
+    M2 = rg.rgcsr_plan_from_csr(A, **lay).build()
+    np.testing.assert_array_equal(host(M2.spmv(xd)).view(np.uint32), yo.view(np.uint32))
+    M2.close()

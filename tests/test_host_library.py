@@ -185,3 +185,44 @@ def test_empty_matrix_layout(lib, oracle):
     A = W.CSR(5, 3, np.zeros(6, np.int64), np.zeros(0, np.int32), np.zeros(0))
     L = rg.rgcsr_layout_host(A, rg.make_opts(G=4, value_dtype="f64"))
     same_layout(L, oracle.rgcsr_layout(A, 4))
+
+
+def test_plan_needs_no_gpu_and_sizes_the_device_block(lib):
+    """rgcsr_plan_from_csr converts on the host only; the device bytes cover
+    every layout array (each 256-byte aligned inside one block)."""
+    A = W.random_csr(3000, 2500, seed=9, max_len=60, empty_frac=0.1, long_rows=4, long_len=2000)
+    for kw in (dict(G=64), dict(G=64, sigma=512, tau=24), dict(G=128, T=2, value_dtype="bf16")):
+        P = rg.rgcsr_plan_from_csr(A, **kw)
+        s = rg.rgcsr_layout_sizes(A, rg.make_opts(**kw))
+        esz = {"f32": 4, "bf16": 2}[kw.get("value_dtype", "f32")]
+        arrays = (s["slots"] + s["long_nnz"]) * (esz + 4) + (s["n_groups"] + 1) * 8 + s["n_short"] * 4
+        assert arrays <= P.device_bytes <= arrays + 64 * 1024 + 16 * A.n_rows
+        assert P.device_bytes % 256 == 0
+        PT = rg.rgcsr_plan_from_csr(A, build_transpose=True, **kw)
+        assert PT.device_bytes > P.device_bytes + A.nnz * (esz + 4)
+        P.close()
+        PT.close()
+
+
+def test_plan_build_argument_errors(lib):
+    """A buffer below the plan's size or off 256-byte alignment is refused
+    before any device work, and the plan stays buildable; bad CSR is refused
+    by the plan step."""
+    A = W.random_csr(500, 400, seed=2, max_len=20)
+    P = rg.rgcsr_plan_from_csr(A)
+    h = ctypes.c_void_p()
+    with pytest.raises(rg.RgcsrError) as e:
+        _lib.call("rgcsr_build", P._p, 1 << 20, P.device_bytes - 1, None, ctypes.byref(h))
+    assert e.value.status == 1 and "smaller" in str(e.value)
+    with pytest.raises(rg.RgcsrError) as e:
+        _lib.call("rgcsr_build", P._p, (1 << 20) + 64, P.device_bytes, None, ctypes.byref(h))
+    assert e.value.status == 1 and "aligned" in str(e.value)
+    b = ctypes.c_int64()
+    _lib.call("rgcsr_plan_device_bytes", P._p, ctypes.byref(b))
+    assert b.value == P.device_bytes
+    P.close()
+    bad = W.CSR(3, 4, np.array([0, 2, 1, 3], np.int64), np.array([0, 1, 2], np.int32), np.ones(3))
+    with pytest.raises(rg.RgcsrError) as e:
+        rg.rgcsr_plan_from_csr(bad)
+    assert e.value.status == 2
+    assert lib.rgcsr_plan_destroy(None) == 0
