@@ -122,9 +122,42 @@ def cpu_baseline(cases, budget_s=10.0):
         el = time.perf_counter() - t0
         if el >= budget_s:
             break
-    return {"value": flops / el / 1e9, "unit": "GFLOP/s", "cores": 1, "kind": "oracle",
-            "sample": f"{passes} full passes over both matrices (the whole step), float64, "
-                      f"{el:.1f} s on one core"}
+    out = {"value": flops / el / 1e9, "unit": "GFLOP/s", "cores": 1, "kind": "oracle",
+           "sample": f"{passes} full passes over both matrices (the whole step), float64, "
+                     f"{el:.1f} s on one core",
+           "host_cpu": host_cpu()}
+    try:  # a library SpMV on the same host core, for context
+        import scipy.sparse as sp
+        sm = [(sp.csr_matrix((A64.val, A64.col, A64.row_ptr), shape=(A.n_rows, A.n_cols)), x64, A.nnz)
+              for A, A64, x64 in mats]
+        sm[0][0] @ sm[0][1]
+        passes, flops, t0 = 0, 0, time.perf_counter()
+        while True:
+            for S, x64, nnz in sm:
+                S @ x64
+                flops += 2 * nnz
+            passes += 1
+            el = time.perf_counter() - t0
+            if el >= budget_s / 2:
+                break
+        out["library"] = {"value": flops / el / 1e9, "unit": "GFLOP/s", "kind": "scipy.sparse csr_matrix @ x, float64",
+                          "sample": f"{passes} full passes, {el:.1f} s"}
+    except ImportError:
+        pass
+    return out
+
+
+def host_cpu() -> dict:
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"model": model, "cores_available": len(os.sched_getaffinity(0))}
 
 
 def check_outputs(cases, torch):
@@ -326,6 +359,12 @@ def bench_cg(args, torch, rg, W):
         out["results"].append({"storage": dt, **st, "oracle_relres": rel,
                                "max_abs_x_minus_1": float(np.max(np.abs(xh - 1.0))),
                                "spmv_us": us, "spmv_gbs": bb / us / 1e3})
+    if not args.no_cpu:
+        # the oracle's plain FP64 CG (serial CSR SpMV) to the same residual, one host core
+        t0 = time.perf_counter()
+        xc, it, rel = oracle.cg(A, b64, tol=1e-10)
+        out["cpu_baseline"] = {"kind": "oracle", "seconds": time.perf_counter() - t0, "iterations": it,
+                               "relres": rel, "cores": 1, "host_cpu": host_cpu()}
     print(json.dumps(out), flush=True)
 
 
@@ -339,8 +378,12 @@ def bench_grad(args, torch, rg, W):
     bvec = W.normal_vector(A.n_rows, W.SEEDS["grad_b"], np.float32)
     xd, bd = torch.from_numpy(x).to("cuda:0"), torch.from_numpy(bvec).to("cuda:0")
     theta = torch.from_numpy(A.val).to("cuda:0")
+    t0 = time.perf_counter()
     r, dx_ref, dv_ref, L = oracle.adjoint(A, x, bvec)
-    out = {"metric": "SpMV forward + backward, Zipf n=1e6, FP32", "results": []}
+    cpu_s = time.perf_counter() - t0
+    out = {"metric": "SpMV forward + backward, Zipf n=1e6, FP32", "results": [],
+           "cpu_baseline": {"kind": "oracle", "seconds": cpu_s, "cores": 1,
+                            "sample": "one FP64 forward (r = A x - b) and backward (dx = A^T r, dtheta) pass"}}
     for transpose in (True, False):
         M = rg.rgcsr_from_csr(A, keep_csr_map=True, build_transpose=transpose, **LAYOUT_ZIPF)
         y = torch.empty(A.n_rows, device="cuda:0")
@@ -642,6 +685,9 @@ def main():
     # per-kernel launch duration: K back-to-back launches of that kernel alone
     # (rotating copies), events only at the two ends
     per_launch = [timed_steps(lambda i, c=c: c.spmv(i, rg))[0] / K for c in cases]
+    # the same back to back on one copy only: served from the 256 MB MALL when
+    # it fits (labelled, never the reported rate)
+    mall_warm = [timed_steps(lambda i, c=c: c.spmv(0, rg))[0] / K for c in cases]
 
     # Hybrid on the same matrices (comparison, not part of the step)
     hyb_ms = []
@@ -667,6 +713,9 @@ def main():
             "fill_pct": 100.0 * (c.info["slots"] + c.info["long_nnz"] - c.A.nnz) / max(1, c.A.nnz),
             "rgcsr": {"us": 1e3 * t, "us_events_around_each": 1e3 * float(np.mean(per_kernel[ci])),
                       "us_median_events_around_each": 1e3 * float(np.median(per_kernel[ci])),
+                      "us_p10_p90_events_around_each": [1e3 * float(np.percentile(per_kernel[ci], 10)),
+                                                        1e3 * float(np.percentile(per_kernel[ci], 90))],
+                      "us_mall_warm_one_copy": 1e3 * mall_warm[ci],
                       "gflops": c.flops / (t * 1e-3) / 1e9, "gbs": c.bytes / (t * 1e-3) / 1e9,
                       "hbm_frac": c.bytes / (t * 1e-3) / 1e9 / HBM_PEAK_GBS,
                       "frac_of_achievable_read": c.bytes / (t * 1e-3) / 1e9 / read_gbs,
