@@ -718,40 +718,112 @@ __global__ __launch_bounds__(256) void gather_map_k(int64_t n, const int32_t *ma
 
 // ---------------------------------------------------------------------------
 // Backward: dvals[k] = dy[row(k)] * x[col(k)]; optionally dx += v * dy (atomic)
+//
+// The work is split as in the SpMV (workgroup chunks of the longest rows,
+// wavefront items of long rows, then row groups), and every lane issues the
+// column (and value) loads of up to U elements before their x gathers, so a
+// row costs a few dependent memory levels, not one per element.  Each output
+// is a single product, so the order of the work does not change dvals.
 // ---------------------------------------------------------------------------
+template <int VD, class A, bool DVALS, bool ATOMIC_DX, int U>
+__device__ __forceinline__ void grad_elems(const typename Val<VD>::S *vb, const int32_t *cb, const A *X, A d,
+                                           A *dv, A *dx, int32_t o, int32_t e, int32_t stride) {
+    using V = Val<VD>;
+    using S = typename V::S;
+    for (int32_t o0 = o; o0 < e; o0 += stride * U) {
+        int32_t ci[U];
+        S v[U];
+        A xv[U];
+#pragma unroll
+        for (int u = 0; u < U; u++) {
+            const int32_t oo = o0 + u * stride < e ? o0 + u * stride : o;
+            ci[u] = cb[oo];
+            if constexpr (ATOMIC_DX) v[u] = vb[oo];
+        }
+        if constexpr (DVALS) {
+#pragma unroll
+            for (int u = 0; u < U; u++) xv[u] = X[ci[u]];
+        }
+#pragma unroll
+        for (int u = 0; u < U; u++) {
+            if (o0 + u * stride < e) {
+                if constexpr (DVALS) dv[o0 + u * stride] = d * xv[u];
+                if constexpr (ATOMIC_DX) atomicAdd(dx + ci[u], V::template cvt<A>(v[u]) * d);
+            }
+        }
+    }
+}
+
 template <int VD, class A, int T, bool DVALS, bool ATOMIC_DX>
 __global__ __launch_bounds__(256) void grad_k(SpmvParams P, const A *dy, A *dvals, A *dx, const int64_t *row_ptr) {
     using V = Val<VD>;
     using S = typename V::S;
     const int lane = threadIdx.x & 63;
-    const int32_t w = blockIdx.x * 4 + (int)(threadIdx.x >> 6);
-    if (w >= P.total_waves) return;
     const A *X = (const A *)P.x;
-    if (w < P.n_long_waves) {
-        const int64_t li = w;
-        const int64_t row = P.long_row[li];
-        const int64_t beg = P.long_ptr[li], end = P.long_ptr[li + 1];
+    const S *lv = (const S *)P.long_val;
+    const int32_t u = blockIdx.x;
+    if (u < P.n_block_items) {
+        // a chunk of at most kBlockChunk nonzeros of one long row
+        const LongItem it = ldc(P.block_work, u);
+        const int64_t li = it.a;
+        const int64_t lb = ldc(P.long_ptr, li);
+        const int64_t beg = lb + (int64_t)it.b * kBlockChunk;
+        const int32_t n = (int32_t)min(ldc(P.long_ptr, li + 1) - beg, kBlockChunk);
+        const int64_t row = ldc(P.long_row, li);
         const A d = dy[row];
-        const S *lv = (const S *)P.long_val;
-        const int64_t k0 = DVALS ? row_ptr[row] - beg : 0;
-        for (int64_t e = beg + lane; e < end; e += 64) {
-            const int32_t c = P.long_col[e];
-            if constexpr (DVALS) dvals[k0 + e] = d * X[c];
-            if constexpr (ATOMIC_DX) atomicAdd(dx + c, V::template cvt<A>(lv[e]) * d);
-        }
+        A *dv = DVALS ? dvals + (row_ptr[row] + (beg - lb)) : nullptr;
+        grad_elems<VD, A, DVALS, ATOMIC_DX, 16>(lv + beg, P.long_col + beg, X, d, dv, dx, (int32_t)threadIdx.x, n,
+                                                 kBlockThreads);
         return;
     }
-    const LaneRow L = lane_row<T>(P, w - P.n_long_waves, lane);
-    if (!L.ok) return;
+    const int32_t w = __builtin_amdgcn_readfirstlane((u - P.n_block_items) * 4 + (int)(threadIdx.x >> 6));
+    if (w < P.n_wave_long) {
+        // consecutive long rows of at most kWaveRowMax nonzeros, it.c lanes each
+        const LongItem it = ldc(P.wave_work, w);
+        const int TL = it.c;
+        const int sh = 31 - __builtin_clz(TL);
+        const int r = lane >> sh, q = lane & (TL - 1);
+        if (r >= it.b) return;
+        const int64_t li = (int64_t)it.a + r;
+        const int64_t beg = P.long_ptr[li];
+        const int32_t n = (int32_t)(P.long_ptr[li + 1] - beg);
+        const int64_t row = P.long_row[li];
+        const A d = dy[row];
+        A *dv = DVALS ? dvals + row_ptr[row] : nullptr;
+        grad_elems<VD, A, DVALS, ATOMIC_DX, kWaveUnroll>(lv + beg, P.long_col + beg, X, d, dv, dx, q, n, TL);
+        return;
+    }
+    const int32_t ws = w - P.n_wave_long;
+    if (ws >= P.total_waves - P.n_long_waves) return;
+    const LaneRow L = lane_row<T>(P, ws, lane);
+    if (!L.ok || L.len <= L.q) return;
     const S *sv = (const S *)P.slot_val;
     const int64_t row = P.perm ? (int64_t)P.short_row[L.i] : L.i;
     const A d = dy[row];
-    const int64_t k0 = DVALS ? row_ptr[row] : 0;
-    for (int j = L.q, c = 0; j < L.len; j += T, c++) {
-        const int64_t s = L.base + (int64_t)c * L.stride;
-        const int32_t col = P.slot_col[s];
-        if constexpr (DVALS) dvals[k0 + j] = d * X[col];
-        if constexpr (ATOMIC_DX) atomicAdd(dx + col, V::template cvt<A>(sv[s]) * d);
+    const int32_t nl = (L.len - L.q + T - 1) / T;  // this lane's elements
+    constexpr int US = 8;
+    for (int32_t c0 = 0; c0 < nl; c0 += US) {
+        int32_t ci[US];
+        S v[US];
+        A xv[US];
+#pragma unroll
+        for (int u = 0; u < US; u++) {
+            const int64_t s = L.base + (int64_t)(c0 + u < nl ? c0 + u : 0) * L.stride;
+            ci[u] = P.slot_col[s];
+            if constexpr (ATOMIC_DX) v[u] = sv[s];
+        }
+        if constexpr (DVALS) {
+#pragma unroll
+            for (int u = 0; u < US; u++) xv[u] = X[ci[u]];
+        }
+        const int64_t k0 = DVALS ? row_ptr[row] + L.q : 0;
+#pragma unroll
+        for (int u = 0; u < US; u++) {
+            if (c0 + u < nl) {
+                if constexpr (DVALS) dvals[k0 + (int64_t)(c0 + u) * T] = d * xv[u];
+                if constexpr (ATOMIC_DX) atomicAdd(dx + ci[u], V::template cvt<A>(v[u]) * d);
+            }
+        }
     }
 }
 
@@ -1154,7 +1226,10 @@ hipError_t launch_gather_map(int64_t n, int vdt, const int32_t *map, const void 
 template <int VD, class A, int T>
 static hipError_t launch_grad_t(const SpmvParams &P, const A *dy, A *dvals, A *dx, const int64_t *rp, bool want_dvals,
                                 bool atomic_dx, hipStream_t st) {
-    const int nwg = (P.total_waves + 3) / 4;
+    // block items, then wavefront items (long-row items, then the row groups
+    // one row per lane)
+    const int64_t waves = (int64_t)P.n_wave_long + (P.total_waves - P.n_long_waves);
+    const int nwg = (int)(P.n_block_items + (waves + 3) / 4);
     if (nwg == 0) return hipSuccess;
     if (want_dvals && atomic_dx)
         hipLaunchKernelGGL((grad_k<VD, A, T, true, true>), dim3(nwg), dim3(256), 0, st, P, dy, dvals, dx, rp);

@@ -167,6 +167,10 @@ def test_transpose_grad_against_oracle(torch_cuda, oracle, transpose, lay):
     r, dx_ref, dv_ref, _ = oracle.adjoint(A, x, b)
     st, sx = grad_tolerances(oracle, A, x, b)
     assert np.max(np.abs(host(dv) - dv_ref)) <= 1e-5 * st
+    # each dvals entry is one rounded product of the device dy and x
+    rows = np.repeat(np.arange(A.n_rows), np.diff(A.row_ptr))
+    exact = (host(dy)[rows] * x[A.col]).astype(np.float32)
+    np.testing.assert_array_equal(host(dv).view(np.uint32), exact.view(np.uint32))
     assert np.max(np.abs(host(dx) - dx_ref)) <= 1e-5 * sx
     if transpose:   # no atomics: repeatable bits
         dx2 = torch.empty_like(dx)
@@ -334,3 +338,27 @@ def test_build_into_torch_memory(torch_cuda, oracle, lay):
     M2 = rg.rgcsr_plan_from_csr(A, **lay).build()
     np.testing.assert_array_equal(host(M2.spmv(xd)).view(np.uint32), yo.view(np.uint32))
     M2.close()
+
+
+@pytest.mark.parametrize("transpose", [True, False])
+def test_grad_rows_split_into_chunks(torch_cuda, oracle, transpose):
+    """Rows longer than one workgroup chunk (16,384 nonzeros) and rows of
+    wavefront items in the backward pass: dvals bit-exact, dx to tolerance."""
+    torch = torch_cuda
+    A = W.random_csr(300, 60_000, seed=34, max_len=40, long_rows=2, long_len=40_000, dtype=np.float32)
+    x = W.normal_vector(A.n_cols, 35, np.float32)
+    b = W.normal_vector(A.n_rows, 36, np.float32)
+    say("grad chunked long rows", transpose)
+    M = rg.rgcsr_from_csr(A, keep_csr_map=True, build_transpose=transpose, sigma=300, tau=16)
+    assert M.info["long_work"] > 0
+    xd = dev(x)
+    dy = (M.spmv(xd) - dev(b)).contiguous()
+    dx = torch.empty(A.n_cols, device="cuda:0")
+    dv = torch.empty(A.nnz, device="cuda:0")
+    rg.rgcsr_spmv_transpose_grad(M, xd, dy, dx, dv)
+    rows = np.repeat(np.arange(A.n_rows), np.diff(A.row_ptr))
+    exact = (host(dy)[rows] * x[A.col]).astype(np.float32)
+    np.testing.assert_array_equal(host(dv).view(np.uint32), exact.view(np.uint32))
+    _, dx_ref, _, _ = oracle.adjoint(A, x, b)
+    _, sx = grad_tolerances(oracle, A, x, b)
+    assert np.max(np.abs(host(dx) - dx_ref)) <= 1e-5 * sx
