@@ -36,7 +36,8 @@ struct SpmvParams {
     int32_t n_wave_items;        // all wave items (long-row wave items, then row groups)
     int32_t total_units;         // n_block_items + ceil(n_wave_items / kBlockWaves)
     int32_t n_long_units;        // units holding long-row work: n_block_items + ceil(n_wave_long / kBlockWaves)
-    // per-row long handling of setval/grad: one wavefront per long row
+    // setval/grad: their row-group wavefronts (one row per lane) number
+    // total_waves - n_long_waves (n_long_waves = long rows)
     int32_t n_long_waves;
     int32_t total_waves;
     // vectors

@@ -683,28 +683,70 @@ __device__ __forceinline__ typename Val<VD>::S to_store(SRC v) {
     else return f32_to_bf16_rne((float)v);
 }
 
+// Value update over the SpMV work split (workgroup chunks of the longest
+// rows, wavefront items of long rows, then row groups one row per lane); each
+// lane loads up to U source values before it stores them.
+template <int VD, class SRC, int U>
+__device__ __forceinline__ void copy_elems(const SRC *src, typename Val<VD>::S *dst, int32_t o, int32_t e,
+                                           int32_t stride) {
+    for (int32_t o0 = o; o0 < e; o0 += stride * U) {
+        SRC t[U];
+#pragma unroll
+        for (int u = 0; u < U; u++) t[u] = src[o0 + u * stride < e ? o0 + u * stride : o];
+#pragma unroll
+        for (int u = 0; u < U; u++)
+            if (o0 + u * stride < e) dst[o0 + u * stride] = to_store<VD>(t[u]);
+    }
+}
+
 template <int VD, class SRC, int T>
 __global__ __launch_bounds__(256) void setval_k(SpmvParams P, const SRC *theta, const int64_t *row_ptr) {
     using S = typename Val<VD>::S;
     const int lane = threadIdx.x & 63;
-    const int32_t w = blockIdx.x * 4 + (int)(threadIdx.x >> 6);
-    if (w >= P.total_waves) return;
-    if (w < P.n_long_waves) {
-        // long rows: one wavefront per long row, contiguous copy
-        const int64_t li = w;
-        const int64_t row = P.long_row[li];
-        const int64_t beg = P.long_ptr[li], end = P.long_ptr[li + 1];
-        const int64_t k0 = row_ptr[row] - beg;
-        S *lv = (S *)P.long_val;
-        for (int64_t e = beg + lane; e < end; e += 64) lv[e] = to_store<VD>(theta[k0 + e]);
+    S *lv = (S *)P.long_val;
+    const int32_t u = blockIdx.x;
+    if (u < P.n_block_items) {
+        const LongItem it = ldc(P.block_work, u);
+        const int64_t li = it.a;
+        const int64_t lb = ldc(P.long_ptr, li);
+        const int64_t beg = lb + (int64_t)it.b * kBlockChunk;
+        const int32_t n = (int32_t)min(ldc(P.long_ptr, li + 1) - beg, kBlockChunk);
+        const int64_t row = ldc(P.long_row, li);
+        copy_elems<VD, SRC, 16>(theta + (row_ptr[row] + (beg - lb)), lv + beg, (int32_t)threadIdx.x, n,
+                                kBlockThreads);
         return;
     }
-    const LaneRow L = lane_row<T>(P, w - P.n_long_waves, lane);
-    if (!L.ok) return;
+    const int32_t w = __builtin_amdgcn_readfirstlane((u - P.n_block_items) * 4 + (int)(threadIdx.x >> 6));
+    if (w < P.n_wave_long) {
+        const LongItem it = ldc(P.wave_work, w);
+        const int TL = it.c;
+        const int sh = 31 - __builtin_clz(TL);
+        const int r = lane >> sh, q = lane & (TL - 1);
+        if (r >= it.b) return;
+        const int64_t li = (int64_t)it.a + r;
+        const int64_t beg = P.long_ptr[li];
+        const int32_t n = (int32_t)(P.long_ptr[li + 1] - beg);
+        const int64_t row = P.long_row[li];
+        copy_elems<VD, SRC, kWaveUnroll>(theta + row_ptr[row], lv + beg, q, n, TL);
+        return;
+    }
+    const int32_t ws = w - P.n_wave_long;
+    if (ws >= P.total_waves - P.n_long_waves) return;
+    const LaneRow L = lane_row<T>(P, ws, lane);
+    if (!L.ok || L.len <= L.q) return;
     S *sv = (S *)const_cast<void *>(P.slot_val);
     const int64_t row = P.perm ? (int64_t)P.short_row[L.i] : L.i;
-    const int64_t k0 = row_ptr[row];
-    for (int j = L.q, c = 0; j < L.len; j += T, c++) sv[L.base + (int64_t)c * L.stride] = to_store<VD>(theta[k0 + j]);
+    const SRC *src = theta + row_ptr[row] + L.q;
+    const int32_t nl = (L.len - L.q + T - 1) / T;
+    constexpr int US = 8;
+    for (int32_t c0 = 0; c0 < nl; c0 += US) {
+        SRC t[US];
+#pragma unroll
+        for (int u = 0; u < US; u++) t[u] = src[(int64_t)(c0 + u < nl ? c0 + u : 0) * T];
+#pragma unroll
+        for (int u = 0; u < US; u++)
+            if (c0 + u < nl) sv[L.base + (int64_t)(c0 + u) * L.stride] = to_store<VD>(t[u]);
+    }
 }
 
 template <int VD, class SRC>
@@ -1173,7 +1215,8 @@ hipError_t launch_spmv(const SpmvParams &P, int vdt, int vec_f64, int T, int K, 
 
 template <int VD, class SRC>
 static hipError_t launch_setval_s(const SpmvParams &P, int T, const SRC *theta, const int64_t *rp, hipStream_t st) {
-    const int nwg = (P.total_waves + 3) / 4;
+    const int64_t waves = (int64_t)P.n_wave_long + (P.total_waves - P.n_long_waves);
+    const int nwg = (int)(P.n_block_items + (waves + 3) / 4);
     if (nwg == 0) return hipSuccess;
     switch (T) {
     case 1: hipLaunchKernelGGL((setval_k<VD, SRC, 1>), dim3(nwg), dim3(256), 0, st, P, theta, rp); break;

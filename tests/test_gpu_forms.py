@@ -362,3 +362,10 @@ def test_grad_rows_split_into_chunks(torch_cuda, oracle, transpose):
     _, dx_ref, _, _ = oracle.adjoint(A, x, b)
     _, sx = grad_tolerances(oracle, A, x, b)
     assert np.max(np.abs(host(dx) - dx_ref)) <= 1e-5 * sx
+    # value update over the same split: the layout equals a fresh conversion
+    theta = W.normal_vector(A.nnz, 37, np.float32)
+    rg.rgcsr_set_values(M, dev(theta))
+    exp = oracle.rgcsr_layout(W.CSR(A.n_rows, A.n_cols, A.row_ptr, A.col, theta), 64, 1, 300, 16)
+    got = M.export()
+    np.testing.assert_array_equal(got["slot_val"].view(np.uint32), exp["slot_val"].view(np.uint32))
+    np.testing.assert_array_equal(got["long_val"].view(np.uint32), exp["long_val"].view(np.uint32))
