@@ -45,8 +45,8 @@ void orc_csr_spmv(int64_t n_rows, const int64_t *rp, const int32_t *col,
     }
 }
 
-/* s_i = sum_j |a_ij| * |x_j|, the scale against which floating-point SpMV
- * results are judged. */
+/* s_i = sum_j |a_ij| * |x_j|, the scale of the tolerance on floating-point
+ * SpMV results. */
 void orc_csr_absmv(int64_t n_rows, const int64_t *rp, const int32_t *col,
                    const double *val, const double *x, double *s)
 {
