@@ -523,3 +523,39 @@ def test_autotune_batch(torch_cuda, oracle, tmp_path):
         check_spmv(oracle, M, xh[co[i]:co[i + 1]], yh[ro[i]:ro[i + 1]])
     best2, tried2 = rg.rgcsr_autotune_batch(mats, x, y, cache_path=cache)
     assert rg.opts_dict(best2) == rg.opts_dict(best) and tried2 == tried
+
+
+@pytest.mark.parametrize("empty,lay", [(0.1, dict(G=64)), (0.1, dict(G=64, sigma=1 << 40, tau=16)),
+                                       (0.1, dict(G=64, pad_loads=0)), (0.1, dict(G=64, pad_loads=1)),
+                                       (0.1, dict(G=32, T=2, tau=24)), (0.0, dict(G=64, pad_loads=3)),
+                                       (0.0, dict(G=64, sigma=512, tau=8, pad_loads=3))])
+def test_non_finite_x_reaches_only_rows_that_use_it(torch_cuda, oracle, empty, lay):
+    """y_i sums the stored nonzeros of row i only (§3.4): a NaN or infinity in
+    x reaches exactly the rows with a nonzero in that column, also x[0], which
+    padding and out-of-range steps gather but never multiply."""
+    if empty:
+        A = W.random_csr(3000, 2500, seed=41, max_len=40, empty_frac=empty, long_rows=4, long_len=2200,
+                         dtype=np.float32)
+    else:  # no empty row: every Zipf row has at least one nonzero
+        A = W.zipf_matrix(20_000, seed=41, max_len=3000)
+    x = W.uniform_vector(A.n_cols, 42, np.float32)
+    bad = {0: np.nan, 5: np.inf, 17: -np.inf, 1234: np.nan}
+    for c, v in bad.items():
+        x[c] = v
+    say("non-finite x", lay)
+    ref = oracle.csr_spmv(A, x)
+    xf = x.copy()
+    xf[list(bad)] = 0.0
+    s = oracle.csr_absmv(A, xf)
+    M = rg.rgcsr_from_csr(A, **lay)
+    assert M.info["pad_loads"] == lay.get("pad_loads", M.info["pad_loads"])
+    ys = {"rgcsr": host(M.spmv(dev(x)))}
+    if "tau" not in lay and "T" not in lay and "pad_loads" not in lay:
+        ys["hybrid"] = host(rg.hyb_from_csr(A).spmv(dev(x)))
+    for name, y in ys.items():
+        np.testing.assert_array_equal(np.isnan(y), np.isnan(ref), err_msg=name)
+        np.testing.assert_array_equal(np.isposinf(y), np.isposinf(ref), err_msg=name)
+        np.testing.assert_array_equal(np.isneginf(y), np.isneginf(ref), err_msg=name)
+        fin = np.isfinite(ref)
+        assert np.any(~fin) and np.any(fin)
+        assert oracle.scaled_error(y[fin], ref[fin], s[fin]) <= TOL_F32, name
