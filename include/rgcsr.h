@@ -243,8 +243,10 @@ rgcsr_status rgcsr_spmv(rgcsr_handle A, const void *x, void *y, rgcsr_dtype vec_
  * launch when X and Y are 16-byte aligned with ldx, ldy multiples of 4 (F32)
  * or 2 (F64); other k, or unaligned blocks, run as several launches over
  * column blocks (narrower blocks read X and Y rows with scalar accesses).
- * persistent = 1 launches a fixed grid of wavefronts that loop over the
- * work items (one resident launch); 0 launches one wavefront per item. */
+ * Handles with lanes_per_row > 1 or F16/BF16 stored values run one
+ * single-column launch per column.  persistent = 1 launches a fixed grid of
+ * wavefronts that loop over the work items (one resident launch); 0 launches
+ * one wavefront per item. */
 rgcsr_status rgcsr_spmv_batched(rgcsr_handle A, int32_t k, const void *X, int64_t ldx,
                                 void *Y, int64_t ldy, rgcsr_dtype vec_dtype,
                                 int32_t persistent, void *stream);

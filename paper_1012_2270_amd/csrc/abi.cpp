@@ -901,10 +901,14 @@ rgcsr_status rgcsr_spmv_batched(rgcsr_handle A, int32_t k, const void *X, int64_
     // needs 16-byte aligned rows; otherwise narrower blocks (scalar accesses)
     // are used.
     const bool aligned = ((uintptr_t)X % 16 == 0) && ((uintptr_t)Y % 16 == 0) && (ldx % vw == 0) && (ldy % vw == 0);
+    // the multi-column kernels take one lane per row and F32/F64 values;
+    // other handles run one single-column launch per column (strided x, y)
+    const bool blocks = A->prm.T == 1 && (A->vdt == RGCSR_F32 || A->vdt == RGCSR_F64);
     int32_t done = 0;
     while (done < k) {
         int32_t kb = 1;
         for (int32_t c : {32, 16, 8, 4, 2, 1}) {
+            if (!blocks) break;
             if (c > k - done) continue;
             if (c % vw == 0 && (!aligned || ((size_t)done * esz) % 16 != 0)) continue;
             kb = c;

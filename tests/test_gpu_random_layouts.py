@@ -1,0 +1,87 @@
+"""Seeded random draws over the layout and schedule options: every accepted
+combination of group size, lanes per row, sort window, long-row threshold,
+storage and vector dtype, rows per lane, load mode, load policy and
+right-hand-side count gives the oracle's layout arrays bit for bit and an SpMV
+(or SpMM) within tolerance of the FP64 oracle; combinations the library does
+not run are refused with RGCSR_EUNSUPPORTED."""
+import numpy as np
+import pytest
+
+from gpu_util import TOL_F32, TOL_F64, dev, host, say, storage_values
+
+import paper_1012_2270_amd as rg
+from paper_1012_2270_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+INDEX_ARRAYS = ("gp", "short_len", "short_row", "slot_col", "long_row", "long_ptr", "long_col")
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    rg._lib.load()
+    return torch
+
+
+def draw(rng):
+    T = int(rng.choice([1, 1, 2, 4, 8]))
+    G = int(rng.choice([g for g in (1, 2, 4, 8, 16, 32, 64, 128, 256, 512)
+                        if (g * T) % 64 == 0 or 64 % (g * T) == 0]))
+    vd = str(rng.choice(["f32", "f32", "f64", "bf16", "f16"]))
+    vec = "f64" if vd == "f64" else ("f64" if vd == "f32" and rng.random() < 0.3 else "f32")
+    return dict(G=G, T=T, sigma=int(rng.choice([1, 7, 64, 1000, 1 << 40])), tau=int(rng.choice([-1, 0, 3, 16, 100])),
+                value_dtype=vd, rows_per_lane=int(rng.choice([0, 1, 2, 4, 8])),
+                pad_loads=int(rng.choice([-1, 0, 1, 2, 3])), load_policy=int(rng.choice([0, 0, 0, 0, 1, 2]))), vec
+
+
+@pytest.mark.parametrize("seed", range(40))
+def test_random_layout_and_schedule(torch_cuda, oracle, seed):
+    torch = torch_cuda
+    rng = np.random.default_rng(5000 + seed)
+    n_rows, n_cols = int(rng.integers(1, 4000)), int(rng.integers(1, 4000))
+    A = W.random_csr(n_rows, n_cols, seed=seed, max_len=int(rng.integers(1, min(n_cols, 80) + 1)),
+                     empty_frac=float(rng.choice([0.0, 0.05, 0.3])), long_rows=int(rng.integers(0, 4)),
+                     long_len=int(rng.integers(1, n_cols + 1)), dtype=np.float32)
+    kw, vec = draw(rng)
+    say("random layout", seed, n_rows, n_cols, A.nnz, kw, vec)
+    try:
+        M = rg.rgcsr_from_csr(A, **kw)
+    except rg.RgcsrError as e:
+        # refused only where documented: sliced ELLPACK / column-derived
+        # lengths outside their geometry, or a load policy outside F32 / T = 1
+        assert e.status == 6, str(e)
+        assert kw["pad_loads"] in (2, 3) or kw["load_policy"] != 0, str(e)
+        return
+    G, T, sigma, tau = kw["G"], kw["T"], kw["sigma"], kw["tau"]
+    exp = oracle.rgcsr_layout(A, G, T, sigma, tau)
+    got = M.export()
+    for k in INDEX_ARRAYS:
+        np.testing.assert_array_equal(got[k], exp[k], err_msg=k)
+    vd = kw["value_dtype"]
+    if vd == "f32":
+        for k in ("slot_val", "long_val"):
+            np.testing.assert_array_equal(got[k].view(np.uint8), exp[k].view(np.uint8), err_msg=k)
+    vals64 = storage_values(oracle, A, vd) if vd in ("bf16", "f16") else None
+    B = A if vals64 is None else W.CSR(A.n_rows, A.n_cols, A.row_ptr, A.col, vals64)
+    tol = TOL_F64 if vec == "f64" else TOL_F32
+    npdt = np.float64 if vec == "f64" else np.float32
+    x = W.uniform_vector(A.n_cols, seed + 1, npdt)
+    if kw["load_policy"] != 0 and vec == "f64":
+        with pytest.raises(rg.RgcsrError) as e:
+            M.spmv(dev(x))
+        assert e.value.status == 6
+        return
+    y = host(M.spmv(dev(x)))
+    assert oracle.scaled_error(y, oracle.csr_spmv(B, x), oracle.csr_absmv(B, x)) <= tol
+    if kw["load_policy"] == 0:
+        k = int(rng.choice([2, 4, 8, 16, 32]))
+        X = W.uniform_matrix(A.n_cols, k, seed=seed + 2, dtype=npdt)
+        Y = host(M.spmm(dev(X)))
+        ref = oracle.csr_spmm(B, X)
+        for c in range(k):
+            assert oracle.scaled_error(Y[:, c], ref[:, c], oracle.csr_absmv(B, X[:, c])) <= tol, c
+    M.close()
+    del torch
