@@ -85,3 +85,55 @@ def test_random_layout_and_schedule(torch_cuda, oracle, seed):
             assert oracle.scaled_error(Y[:, c], ref[:, c], oracle.csr_absmv(B, X[:, c])) <= tol, c
     M.close()
     del torch
+
+
+@pytest.mark.parametrize("seed", range(16))
+def test_random_batch_and_backward(torch_cuda, oracle, seed):
+    """Seeded draws of small batches (per-matrix y within tolerance) and of
+    the backward pass and value update on one matrix (dvals bit-exact to the
+    rounded products, dx within tolerance, updated values bit-exact against
+    a fresh conversion)."""
+    torch = torch_cuda
+    rng = np.random.default_rng(7000 + seed)
+    kw, _ = draw(rng)
+    kw["value_dtype"] = "f32"
+    kw["load_policy"] = 0
+    if kw["pad_loads"] in (2, 3):
+        kw["pad_loads"] = -1
+    mats = [W.random_csr(int(rng.integers(1, 900)), int(rng.integers(1, 900)), seed=100 * seed + m,
+                         max_len=int(rng.integers(1, 40)), empty_frac=float(rng.choice([0.0, 0.2])),
+                         long_rows=int(rng.integers(0, 3)), long_len=int(rng.integers(1, 600)), dtype=np.float32)
+            for m in range(int(rng.integers(1, 9)))]
+    say("random batch", seed, [(M.n_rows, M.n_cols, M.nnz) for M in mats], kw)
+    B = rg.rgcsr_from_csr_batch(mats, **kw)
+    ro, co = B.batch_offsets()
+    x = W.uniform_vector(int(co[-1]), seed + 3, np.float32)
+    y = host(B.spmv(dev(x)))
+    for i, M in enumerate(mats):
+        xi = x[co[i]:co[i + 1]]
+        assert oracle.scaled_error(y[ro[i]:ro[i + 1]], oracle.csr_spmv(M, xi), oracle.csr_absmv(M, xi)) <= TOL_F32, i
+    B.close()
+    A = mats[0]
+    transpose = bool(rng.random() < 0.5)
+    say("random backward", seed, A.n_rows, A.n_cols, A.nnz, transpose)
+    M = rg.rgcsr_from_csr(A, keep_csr_map=True, build_transpose=transpose, **kw)
+    xa = W.normal_vector(A.n_cols, seed + 4, np.float32)
+    dy = dev(W.normal_vector(A.n_rows, seed + 5, np.float32))
+    dx = torch.empty(A.n_cols, device="cuda:0")
+    dv = torch.empty(max(1, A.nnz), device="cuda:0")
+    rg.rgcsr_spmv_transpose_grad(M, dev(xa), dy, dx, dv)
+    rows = np.repeat(np.arange(A.n_rows), np.diff(A.row_ptr))
+    exact = (host(dy)[rows] * xa[A.col]).astype(np.float32)
+    np.testing.assert_array_equal(host(dv)[:A.nnz].view(np.uint32), exact.view(np.uint32))
+    AT = W.CSR(A.n_cols, A.n_rows, *oracle.csr_transpose(A))
+    dyh = host(dy)
+    assert oracle.scaled_error(host(dx), oracle.csr_spmv(AT, dyh), oracle.csr_absmv(AT, dyh)) <= TOL_F32
+    theta = W.normal_vector(A.nnz, seed + 6, np.float32)
+    if A.nnz:
+        rg.rgcsr_set_values(M, dev(theta))
+        exp = oracle.rgcsr_layout(W.CSR(A.n_rows, A.n_cols, A.row_ptr, A.col, theta), kw["G"], kw["T"], kw["sigma"],
+                                  kw["tau"])
+        got = M.export()
+        for k in ("slot_val", "long_val"):
+            np.testing.assert_array_equal(got[k].view(np.uint32), exp[k].view(np.uint32), err_msg=k)
+    M.close()
