@@ -137,3 +137,38 @@ def test_random_batch_and_backward(torch_cuda, oracle, seed):
         for k in ("slot_val", "long_val"):
             np.testing.assert_array_equal(got[k].view(np.uint32), exp[k].view(np.uint32), err_msg=k)
     M.close()
+
+
+@pytest.mark.parametrize("seed", range(12))
+def test_random_hybrid(torch_cuda, oracle, seed):
+    """Seeded draws of the Hybrid comparison format: ELL width chosen by the
+    rule or forced (0, 1, wider than every row), storage and vector dtype;
+    arrays bit-exact against the oracle's Hybrid layout, SpMV within
+    tolerance."""
+    rng = np.random.default_rng(9000 + seed)
+    n_rows, n_cols = int(rng.integers(1, 5000)), int(rng.integers(1, 5000))
+    A = W.random_csr(n_rows, n_cols, seed=seed, max_len=int(rng.integers(1, min(n_cols, 60) + 1)),
+                     empty_frac=float(rng.choice([0.0, 0.2])), long_rows=int(rng.integers(0, 4)),
+                     long_len=int(rng.integers(1, n_cols + 1)), dtype=np.float32)
+    width = int(rng.choice([-1, -1, 0, 1, 3, 200]))
+    vd = str(rng.choice(["f32", "f64", "bf16"]))
+    vec = "f64" if vd == "f64" else "f32"
+    say("random hybrid", seed, n_rows, n_cols, A.nnz, width, vd)
+    H = rg.hyb_from_csr(A, value_dtype=vd, ell_width=width)
+    K1 = H.info["ell_width"]
+    if width >= 0:
+        assert K1 == width
+    else:
+        assert K1 == oracle.hyb_k1(A, {"f32": 4, "f64": 8, "bf16": 2}[vd])
+    exp = oracle.hyb_layout(A, K1)
+    got = rg.hyb_export(H)
+    for k in ("ell_col", "coo_row", "coo_col"):
+        np.testing.assert_array_equal(got[k], exp[k], err_msg=k)
+    vals64 = storage_values(oracle, A, vd) if vd == "bf16" else None
+    B = A if vals64 is None else W.CSR(A.n_rows, A.n_cols, A.row_ptr, A.col, vals64)
+    npdt = np.float64 if vec == "f64" else np.float32
+    x = W.uniform_vector(A.n_cols, seed + 7, npdt)
+    y = host(H.spmv(dev(x)))
+    tol = TOL_F64 if vec == "f64" else TOL_F32
+    assert oracle.scaled_error(y, oracle.csr_spmv(B, x), oracle.csr_absmv(B, x)) <= tol
+    H.close()
