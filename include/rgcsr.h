@@ -292,8 +292,9 @@ rgcsr_status rgcsr_info(rgcsr_handle A, rgcsr_info_t *out);
  * to rotate several copies of one matrix through the caches when timing. */
 rgcsr_status rgcsr_clone(rgcsr_handle A, void *stream, rgcsr_handle *out);
 
-/* Frees the device arrays and the handle (synchronises the device first).
- * NULL is accepted. */
+/* Synchronises the device, then frees the handle and the device block it
+ * owns; a block given to rgcsr_build stays allocated and may be released by
+ * its owner once this returns.  NULL is accepted. */
 rgcsr_status rgcsr_destroy(rgcsr_handle A);
 
 /* rgcsr_autotune: choose the layout for one host CSR matrix by a cost-model
