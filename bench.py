@@ -755,7 +755,11 @@ def main():
                      "traffic": tr,
                      "alg_bytes_per_launch": dc.bytes, "avg_launch_us": t_dom * 1e6,
                      "achievable_read_gbs": read_gbs, "frac_of_achievable_read": achieved / read_gbs,
-                     "gather_floor_us": floors[dc.name], "gather_floor_over_time": floors[dc.name] / (t_dom * 1e6)},
+                     "gather_floor_us": floors[dc.name], "gather_floor_over_time": floors[dc.name] / (t_dom * 1e6),
+                     # bytes the HBM counters saw per launch (x refetched into each XCD's L2 included),
+                     # over the same launch time
+                     "traffic_gbs": None if tr is None else tr / t_dom / 1e9,
+                     "traffic_frac": None if tr is None else tr / t_dom / 1e9 / HBM_PEAK_GBS},
         "launch": "eager launches; replaying each step from a HIP graph gives value_graph",
         "value_graph": value_graph,
         "ms_per_step_graph": graph_ms / K,
