@@ -101,6 +101,7 @@ struct rgcsr_matrix_s {
     size_t bytes = 0;
     bool owns_mem = true;  // false: the arrays live in caller memory (rgcsr_build)
     int64_t *gp = nullptr;
+    int64_t *gend = nullptr;  // group ends when they differ from the next group's start
     int32_t *grp_row0 = nullptr, *short_len = nullptr, *short_row = nullptr, *slot_col = nullptr;
     void *slot_val = nullptr;
     LongItem *wave_work = nullptr, *block_work = nullptr, *combine = nullptr;
@@ -234,7 +235,7 @@ std::vector<int32_t> wave_runs(const HostLayout &L, int32_t wpg) {
         const int64_t g = j / wpg;
         const int64_t row0 = L.ragged ? L.grp_row0[g] : g * L.G;
         const int64_t sg = L.ragged ? L.grp_row0[g + 1] - row0 : std::min<int64_t>(L.G, L.ns - row0);
-        width[j] = sg > 0 ? (L.gp[g + 1] - L.gp[g]) / (sg * L.T) : 0;
+        width[j] = sg > 0 ? (L.group_end(g) - L.gp[g]) / (sg * L.T) : 0;
     }
     std::vector<int32_t> runs;
     for (int64_t j = 0; j < n;) {
@@ -329,11 +330,12 @@ rgcsr_matrix_s *prepare_handle(const HostLayout &L, bool with_row_ptr, const Hos
         choose_schedule(h, L, short_nnz, no_empty, rows_per_lane, pad_loads, load_policy);
         // the kernels address a group's slots with 32-bit byte offsets
         int64_t max_group = 0;
-        for (size_t g = 0; g + 1 < L.gp.size(); g++) max_group = std::max(max_group, L.gp[g + 1] - L.gp[g]);
+        for (size_t g = 0; g + 1 < L.gp.size(); g++) max_group = std::max(max_group, L.group_end(g) - L.gp[g]);
         if (max_group * std::max(L.esz, 4) >= (int64_t(1) << 32))
             fail(RGCSR_EOVERFLOW, "a row group holds 4 GiB or more; use a long-row threshold");
 
         a.add(&h->gp, L.gp.size());
+        a.add(&h->gend, L.has_gaps() ? L.gend.size() : 0);
         a.add(&h->grp_row0, h->ragged ? L.grp_row0.size() : 0);
         a.add(&h->short_len, L.short_len.size());
         a.add(&h->short_row, h->perm ? L.short_row.size() : 0);
@@ -370,6 +372,7 @@ void place_and_upload(rgcsr_matrix_s *h, Arena &a, const HostLayout &L, const st
     h->owns_mem = buf == nullptr;
     h->mem = a.commit(buf);
     upload(h->gp, L.gp, st);
+    if (h->gend) upload(h->gend, L.gend, st);
     if (h->ragged) upload(h->grp_row0, L.grp_row0, st);
     upload(h->short_len, L.short_len, st);
     if (h->perm) upload(h->short_row, L.short_row, st);
@@ -446,7 +449,7 @@ rgcsr_matrix_s *make_device_on_device(DevPlan &P, const LayoutParams &p, int vdt
         h->gpw = GT < 64 ? (int32_t)(64 / GT) : 0;
         choose_schedule(h, L, P.nnz - P.long_nnz, P.no_empty, rows_per_lane, pad_loads, load_policy);
         int64_t max_group = 0;
-        for (size_t g = 0; g + 1 < L.gp.size(); g++) max_group = std::max(max_group, L.gp[g + 1] - L.gp[g]);
+        for (size_t g = 0; g + 1 < L.gp.size(); g++) max_group = std::max(max_group, L.group_end(g) - L.gp[g]);
         if (max_group * std::max(L.esz, 4) >= (int64_t(1) << 32))
             fail(RGCSR_EOVERFLOW, "a row group holds 4 GiB or more; use a long-row threshold");
         Arena a;
@@ -508,7 +511,7 @@ int32_t short_waves(const rgcsr_matrix_s *h, bool scheduled) {
 // right-hand side); otherwise one row per lane.
 SpmvParams params_of(const rgcsr_matrix_s *h, bool use_rows) {
     SpmvParams P{};
-    P.gp = h->gp; P.grp_row0 = h->grp_row0; P.short_len = h->short_len; P.short_row = h->short_row;
+    P.gp = h->gp; P.gend = h->gend; P.grp_row0 = h->grp_row0; P.short_len = h->short_len; P.short_row = h->short_row;
     P.slot_val = h->slot_val; P.slot_col = h->slot_col;
     P.ng = h->ng; P.ns = h->ns; P.G = h->prm.G; P.wpg = h->wpg; P.gpw = h->gpw;
     P.ragged = h->ragged; P.perm = h->perm; P.pad = h->pad;
@@ -1105,7 +1108,7 @@ rgcsr_matrix_s *clone_handle(const rgcsr_matrix_s *A, hipStream_t st) {
     try {
         if (A->bytes) HIPCHK(hipMalloc(&h->mem, A->bytes));
         if (A->bytes) HIPCHK(hipMemcpyAsync(h->mem, A->mem, A->bytes, hipMemcpyDeviceToDevice, st));
-        rebase(h, A, &rgcsr_matrix_s::gp, &rgcsr_matrix_s::grp_row0, &rgcsr_matrix_s::short_len,
+        rebase(h, A, &rgcsr_matrix_s::gp, &rgcsr_matrix_s::gend, &rgcsr_matrix_s::grp_row0, &rgcsr_matrix_s::short_len,
                &rgcsr_matrix_s::short_row, &rgcsr_matrix_s::slot_col, &rgcsr_matrix_s::slot_val,
                &rgcsr_matrix_s::short_items, &rgcsr_matrix_s::wave_work, &rgcsr_matrix_s::block_work,
                &rgcsr_matrix_s::combine,

@@ -56,6 +56,12 @@ void validate_csr(int64_t n_rows, int64_t n_cols, int64_t nnz, const int64_t *rp
     if (rp[n_rows] != nnz) fail(RGCSR_ECSR, "row_ptr[n_rows] != nnz");
 }
 
+bool HostLayout::has_gaps() const {
+    for (size_t g = 0; g < gend.size(); g++)
+        if (gend[g] != gp[g + 1]) return true;
+    return false;
+}
+
 bool HostLayout::short_identity() const {
     for (int64_t i = 0; i < ns; i++)
         if (short_row[i] != i) return false;
@@ -154,6 +160,18 @@ void append_layout(HostLayout &L, const LayoutParams &p, int64_t n_rows, int64_t
     std::vector<int32_t> sv, lv;
     order_and_split(p, n_rows, rp, sv, lv);
 
+    // A matrix after the first starts its groups at a multiple of 64 slots,
+    // so that a wavefront's 64 consecutive slots of a step stay within the
+    // fewest cache lines: a partial last group of the previous matrix would
+    // otherwise shift every later group off that alignment.  The skipped
+    // slots belong to no group (zero values, in-range columns).
+    if (L.n_matrices > 0 && ((int64_t)p.G * p.T) % 64 == 0 && L.slots % 64 != 0) {
+        const int64_t aligned = round_up(L.slots, 64);
+        L.slot_col.resize(aligned, (int32_t)cbase > 0 ? (int32_t)(cbase - 1) : 0);
+        if (vals) L.slot_val.resize((size_t)aligned * esz, pad_byte);
+        L.slots = aligned;
+        L.gp.back() = aligned;
+    }
     // groups of short rows
     const int64_t ng_before = L.ng;
     const int64_t n_short = (int64_t)sv.size();
@@ -167,6 +185,7 @@ void append_layout(HostLayout &L, const LayoutParams &p, int64_t n_rows, int64_t
         gstart.push_back(g0);
         slots += (g1 - g0) * round_up(w, p.T);
         L.gp.push_back(slots);
+        L.gend.push_back(slots);
         L.grp_row0.push_back((int32_t)(L.ns + g1));
         if (L.ns + g1 > INT32_MAX) fail(RGCSR_EOVERFLOW, "short rows exceed int32");
     }
@@ -188,7 +207,7 @@ void append_layout(HostLayout &L, const LayoutParams &p, int64_t n_rows, int64_t
     for (size_t gi = 0; gi < gstart.size(); gi++) {
         const int64_t g0 = gstart[gi];
         const int64_t s = std::min<int64_t>(n_short, g0 + p.G) - g0;
-        const int64_t gend = L.gp[L.gp.size() - gstart.size() + gi];
+        const int64_t gend = L.gend[L.gend.size() - gstart.size() + gi];
         const int64_t W = s ? (gend - gbase) / s : 0;
         for (int64_t t = 0; t < s; t++) {
             const int32_t r = sv[g0 + t];

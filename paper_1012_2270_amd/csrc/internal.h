@@ -128,7 +128,9 @@ struct HostLayout {
     int64_t ng = 0, ns = 0, nl = 0, slots = 0, long_nnz = 0;
     int64_t n_matrices = 0;
     bool ragged = false;  // some group other than the last has fewer than G rows
-    std::vector<int64_t> gp{0};
+    std::vector<int64_t> gp{0};       // gp[g]: first slot of group g; gp[ng]: slot count
+    std::vector<int64_t> gend;        // end slot of each group (a batch pads the slots
+                                      // before each matrix to a multiple of 64)
     std::vector<int32_t> grp_row0{0};
     std::vector<int32_t> short_len, short_row;
     std::vector<uint8_t> slot_val;
@@ -140,6 +142,8 @@ struct HostLayout {
     LongWork work;
     std::vector<int64_t> row_off{0}, col_off{0};  // per-matrix offsets (batch)
     bool short_identity() const;
+    int64_t group_end(int64_t g) const { return gend.empty() ? gp[g + 1] : gend[g]; }
+    bool has_gaps() const;  // some group ends before the next one starts
 };
 
 struct LayoutParams {

@@ -11,6 +11,7 @@ namespace rg {
 struct SpmvParams {
     // grouped (short) rows
     const int64_t *gp;         // [ng+1] group pointers (slot offsets)
+    const int64_t *gend;       // [ng] group ends, or null when group g ends at gp[g+1]
     const int32_t *grp_row0;   // [ng+1] first short row of each group (ragged only)
     const int32_t *short_len;  // [ns] row lengths
     const int32_t *short_row;  // [ns] output row of each short row (perm only)

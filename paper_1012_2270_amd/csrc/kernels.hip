@@ -168,7 +168,7 @@ __device__ __forceinline__ GroupMeta group_meta_uniform(const SpmvParams &P, int
             m.sg = (int)min((int64_t)P.G, P.ns - m.row0);
         }
         m.g0 = ldc(P.gp, g);
-        m.g1 = ldc(P.gp, g + 1);
+        m.g1 = ldc(P.gend ? P.gend : P.gp + 1, g);
     }
     return m;
 }
@@ -185,7 +185,7 @@ __device__ __forceinline__ GroupMeta group_meta_lane(const SpmvParams &P, int64_
             m.sg = (int)min((int64_t)P.G, P.ns - m.row0);
         }
         m.g0 = P.gp[g];
-        m.g1 = P.gp[g + 1];
+        m.g1 = (P.gend ? P.gend : P.gp + 1)[g];
     }
     return m;
 }

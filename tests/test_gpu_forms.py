@@ -369,3 +369,32 @@ def test_grad_rows_split_into_chunks(torch_cuda, oracle, transpose):
     got = M.export()
     np.testing.assert_array_equal(got["slot_val"].view(np.uint32), exp["slot_val"].view(np.uint32))
     np.testing.assert_array_equal(got["long_val"].view(np.uint32), exp["long_val"].view(np.uint32))
+
+
+@pytest.mark.parametrize("lay", [dict(G=64), dict(G=32, T=2), dict(G=128, sigma=50)])
+def test_batch_groups_start_aligned(torch_cuda, oracle, lay):
+    """Every matrix of a batch starts its groups at a multiple of 64 slots
+    (the slots skipped after a partial last group belong to no group), so
+    the batch multiplies and decodes exactly as its matrices do."""
+    sizes = [33, 70, 64, 1, 200, 5]
+    mats = [W.random_csr(n, 90, seed=60 + i, max_len=9, empty_frac=0.1, dtype=np.float32)
+            for i, n in enumerate(sizes)]
+    say("batch alignment", lay)
+    B = rg.rgcsr_from_csr_batch(mats, **lay)
+    G = lay["G"]
+    first = np.cumsum([0] + [-(-n // G) for n in sizes[:-1]])
+    gp = B.export()["gp"]
+    assert all(gp[g] % 64 == 0 for g in first), gp[first]
+    assert B.info["slots"] >= sum(oracle.rgcsr_sizes(M, G, lay.get("T", 1), lay.get("sigma", 1))["slots"]
+                                  for M in mats)
+    ro, co = B.batch_offsets()
+    xs = [W.uniform_vector(M.n_cols, 70 + i, np.float32) for i, M in enumerate(mats)]
+    y = host(B.spmv(dev(np.concatenate(xs))))
+    for i, M in enumerate(mats):
+        check_spmv(oracle, M, xs[i], y[ro[i]:ro[i + 1]])
+    rp, col, val = B.to_csr()
+    for i, M in enumerate(mats):
+        seg = slice(rp[ro[i]], rp[ro[i + 1]])
+        np.testing.assert_array_equal(col[seg] - co[i], M.col)
+        np.testing.assert_array_equal(val[seg], M.val)
+    B.close()
