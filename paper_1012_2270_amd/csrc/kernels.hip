@@ -460,7 +460,7 @@ __device__ __forceinline__ void spmv_short(const SpmvParams &P, int32_t w, int l
 template <int VD, class A, int K, int U, int LP>
 __device__ __forceinline__ void strided_dot32(const typename Val<VD>::S *vb, const int32_t *cb, const A *X,
                                               int64_t ldx, uint32_t xrow, int32_t o, int32_t e, int32_t stride,
-                                              A (&acc)[K]) {
+                                              A (&acc)[K], int32_t lo = 0) {
     using V = Val<VD>;
     using S = typename V::S;
     for (int32_t o0 = o; o0 < e; o0 += stride * U) {
@@ -480,7 +480,7 @@ __device__ __forceinline__ void strided_dot32(const typename Val<VD>::S *vb, con
         }
 #pragma unroll
         for (int u = 0; u < U; u++) {
-            const bool on = o0 + u * stride < e;
+            const bool on = o0 + u * stride < e && o0 + u * stride >= lo;
             const A a = V::template cvt<A>(v[u]);
 #pragma unroll
             for (int k = 0; k < K; k++) {
@@ -533,21 +533,25 @@ template <int VD, class A, int LP>
 __device__ __forceinline__ void spmv_wave_long_lds(const SpmvParams &P, int32_t w, int lane, A *buf) {
     using V = Val<VD>;
     using S = typename V::S;
-    constexpr int U = kWaveRowMax / 64;
+    // the load window starts at the 32-element boundary below the item (d
+    // elements early), so each load instruction covers the fewest cache lines
+    constexpr int U = (kWaveRowMax + 31 + 63) / 64;
     A *Y = (A *)P.y;
     const A *X = (const A *)P.x;
     const uint32_t xrow = (uint32_t)(P.ldx * (int64_t)sizeof(A));
     const LongItem it = ldc(P.wave_work, w);
     const int64_t item0 = ldc(P.long_ptr, (int64_t)it.a);
     const int32_t n = (int32_t)(ldc(P.long_ptr, (int64_t)it.a + it.b) - item0);
-    const S *vb = (const S *)P.long_val + item0;
-    const int32_t *cb = P.long_col + item0;
+    const int32_t d = (int32_t)(item0 & 31);
+    const S *vb = (const S *)P.long_val + (item0 - d);
+    const int32_t *cb = P.long_col + (item0 - d);
     S v[U];
     int32_t ci[U];
     A xv[U];
 #pragma unroll
     for (int u = 0; u < U; u++) {
-        const uint32_t o = lane + 64 * u < n ? (uint32_t)(lane + 64 * u) : 0u;
+        const int32_t p = lane + 64 * u;
+        const uint32_t o = p < n + d ? (uint32_t)p : (uint32_t)d;
         v[u] = ld_stream<LP>((const S *)((const char *)vb + o * (uint32_t)sizeof(S)));
         ci[u] = ld_stream<LP>((const int32_t *)((const char *)cb + o * 4u));
     }
@@ -562,7 +566,10 @@ __device__ __forceinline__ void spmv_wave_long_lds(const SpmvParams &P, int32_t 
 #pragma unroll
     for (int u = 0; u < U; u++) xv[u] = ldx32<LP>(X, ci[u], xrow);
 #pragma unroll
-    for (int u = 0; u < U; u++) buf[lane + 64 * u] = V::template cvt<A>(v[u]) * xv[u];
+    for (int u = 0; u < U; u++) {
+        const int32_t e = lane + 64 * u - d;  // element of the item
+        if (e >= 0 && e < n) buf[e] = V::template cvt<A>(v[u]) * xv[u];
+    }
     if (lane == 0) buf[kWaveRowMax] = A(0);  // terms past a row read this slot
     // the slice is private to this wavefront: LDS accesses of one wavefront
     // complete in order, only the compiler must not move the reads up
@@ -572,7 +579,7 @@ __device__ __forceinline__ void spmv_wave_long_lds(const SpmvParams &P, int32_t 
     const int32_t nj = ok && e - b > q ? (e - b - q + TL - 1) >> sh : 0;
     A acc = A(0);
 #pragma nounroll
-    for (int j0 = 0; j0 < U; j0 += 4)
+    for (int j0 = 0; j0 < kWaveUnroll; j0 += 4)
 #pragma unroll
         for (int j = j0; j < j0 + 4; j++) acc += buf[j < nj ? b + q + j * TL : kWaveRowMax];
 #pragma unroll
@@ -596,8 +603,13 @@ __device__ __forceinline__ void spmv_block_item(const SpmvParams &P, int32_t u, 
 #pragma unroll
     for (int k = 0; k < K; k++) acc[k] = A(0);
     constexpr int U = K == 1 ? 16 : unroll_for<K>();
-    strided_dot32<VD, A, K, U, LP>((const S *)P.long_val + beg, P.long_col + beg, X, P.ldx,
-                               (uint32_t)(P.ldx * (int64_t)sizeof(A)), (int32_t)threadIdx.x, n, kBlockThreads, acc);
+    // start the threads' walk at the 32-element boundary below the chunk, so
+    // each wavefront's 64 consecutive loads cover the fewest cache lines; the
+    // d elements before the chunk are loaded but not multiplied
+    const int32_t d = (int32_t)(beg & 31);
+    strided_dot32<VD, A, K, U, LP>((const S *)P.long_val + (beg - d), P.long_col + (beg - d), X, P.ldx,
+                                   (uint32_t)(P.ldx * (int64_t)sizeof(A)), (int32_t)threadIdx.x, n + d,
+                                   kBlockThreads, acc, d);
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1)
 #pragma unroll
