@@ -209,6 +209,8 @@ class RgCSRPlan:
         if buffer is None:
             buffer = torch.empty(max(1, self.device_bytes), dtype=torch.uint8, device="cuda")
         _dev_check(buffer, "buffer")
+        if buffer.device.index != torch.cuda.current_device():
+            raise ValueError("buffer must be on the current device")
         h = ctypes.c_void_p()
         _lib.call("rgcsr_build", self._p, _ptr(buffer), int(buffer.numel() * buffer.element_size()), _stream(stream),
                   ctypes.byref(h))
