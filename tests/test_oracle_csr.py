@@ -167,3 +167,38 @@ def test_adjoint_dot_product_identity(oracle):
     lhs = float(np.dot(oracle.csr_spmv(A, x), y))
     rhs = float(np.dot(x, ATy))
     assert abs(lhs - rhs) <= 1e-13 * max(1.0, abs(lhs))
+
+
+# ---------------------------------------------------------------------------
+# The tolerance judge: e = max_i |y_i - y_ref_i| / max_i s_i, with e = 0 or inf
+# when every s_i is zero.  Every expected value below is worked out by hand.
+# ---------------------------------------------------------------------------
+def test_scaled_error_hand_cases(oracle):
+    # largest difference 0.5 sits at row 1, largest s (4.0) also at row 1:
+    # e = 0.5 / 4 = 0.125.  Dividing by the sum of s (7) gives 0.0714...,
+    # averaging the differences (0.5 / 3) gives 0.0416...
+    assert oracle.scaled_error([1.0, 2.0, 3.0], [1.0, 2.5, 3.0], [1.0, 4.0, 2.0]) == 0.125
+    # largest difference (0.75, row 0) is not at the row of largest s (8.0, row 2):
+    # e = 0.75 / 8 = 0.09375; taking s at the row of the largest difference
+    # (1.0) would give 0.75, the mean of the differences 0.3125 / 8
+    assert oracle.scaled_error([0.75, 1.0, 1.0], [0.0, 1.0, 0.875], [1.0, 2.0, 8.0]) == 0.09375
+    # differences of both signs: |-0.25| is the largest; e = 0.25 / 2
+    assert oracle.scaled_error([-1.25, 0.5], [-1.0, 0.625], [2.0, 0.5]) == 0.125
+    # identical vectors
+    assert oracle.scaled_error([3.0, -2.0], [3.0, -2.0], [5.0, 1.0]) == 0.0
+
+
+def test_scaled_error_zero_scale(oracle):
+    # every s_i = 0 (e.g. x = 0): y must be exactly zero
+    assert oracle.scaled_error([0.0, -0.0], [0.0, 0.0], [0.0, 0.0]) == 0.0
+    assert oracle.scaled_error([0.0, 1e-300], [0.0, 0.0], [0.0, 0.0]) == float("inf")
+    assert oracle.scaled_error([], [], []) == 0.0
+
+
+def test_scaled_error_nan_fails_every_tolerance(oracle):
+    e = oracle.scaled_error([1.0, float("nan")], [1.0, 2.0], [1.0, 1.0])
+    assert not (e <= 1e-5)
+    e = oracle.scaled_error([float("nan")], [0.0], [0.0])
+    assert not (e <= 1e-5)
+    # an infinite result against a finite reference is an infinite error
+    assert oracle.scaled_error([float("inf")], [1.0], [1.0]) == float("inf")
