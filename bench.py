@@ -107,24 +107,48 @@ class Case:
         rg.hyb_spmv(self.hybs[j], self.xs[j], self.ys[j])
 
 
-def cpu_baseline(cases, budget_s=10.0):
+def host_threads() -> int:
+    """Host cores this process may use: the affinity mask, capped by
+    OMP_NUM_THREADS when that is set (the share a shared host grants)."""
+    n = len(os.sched_getaffinity(0))
+    env = os.environ.get("OMP_NUM_THREADS", "")
+    return max(1, min(n, int(env))) if env.isdigit() and int(env) > 0 else n
+
+
+def cpu_baseline(cases, budget_s=8.0):
     """The FP64 oracle (plain serial CSR SpMV) on the same matrices, upcast to
-    float64, repeated for about budget_s seconds on one host core."""
+    float64: about budget_s seconds with the rows statically split over every
+    host core this process may use (the reported value; each row keeps its
+    serial order, and the result is checked bit-identical to one core), then
+    about budget_s seconds on one core."""
     import oracle
     mats = [(c.A, c.A.astype(np.float64), c.x_host.astype(np.float64)) for c in cases]
-    oracle.csr_spmv(mats[0][1], mats[0][2])  # warm
-    passes, flops, t0 = 0, 0, time.perf_counter()
-    while True:
-        for A, A64, x64 in mats:
-            oracle.csr_spmv(A64, x64)
-            flops += 2 * A.nnz
-        passes += 1
-        el = time.perf_counter() - t0
-        if el >= budget_s:
-            break
-    out = {"value": flops / el / 1e9, "unit": "GFLOP/s", "cores": 1, "kind": "oracle",
-           "sample": f"{passes} full passes over both matrices (the whole step), float64, "
-                     f"{el:.1f} s on one core",
+    threads = host_threads()
+
+    def run(fn, budget):
+        fn(*mats[0][1:])  # warm
+        passes, flops, t0 = 0, 0, time.perf_counter()
+        while True:
+            for A, A64, x64 in mats:
+                fn(A64, x64)
+                flops += 2 * A.nnz
+            passes += 1
+            el = time.perf_counter() - t0
+            if el >= budget:
+                return flops / el / 1e9, passes, el
+
+    for A, A64, x64 in mats:
+        same = np.array_equal(oracle.csr_spmv_parallel(A64, x64, threads).view(np.uint64),
+                              oracle.csr_spmv(A64, x64).view(np.uint64))
+        if not same:
+            raise RuntimeError("the row-partitioned oracle differs from the serial one")
+    v_par, p_par, el_par = run(lambda A64, x64: oracle.csr_spmv_parallel(A64, x64, threads), budget_s)
+    v_one, p_one, el_one = run(oracle.csr_spmv, budget_s)
+    out = {"value": v_par, "unit": "GFLOP/s", "cores": threads, "kind": "oracle",
+           "sample": f"{p_par} full passes over both matrices (the whole step), float64, {el_par:.1f} s, "
+                     f"rows split statically over {threads} OpenMP threads (bit-identical to one thread)",
+           "single_core": {"value": v_one, "unit": "GFLOP/s", "cores": 1,
+                           "sample": f"{p_one} full passes, {el_one:.1f} s"},
            "host_cpu": host_cpu()}
     try:  # a library SpMV on the same host core, for context
         import scipy.sparse as sp

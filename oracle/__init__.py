@@ -36,7 +36,7 @@ def build(force: bool = True) -> str:
     if force or not os.path.exists(_LIB):
         tmp = _LIB + ".tmp"
         subprocess.check_call(["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-std=c11",
-                               "-fPIC", "-shared", "-o", tmp, _SRC, "-lm"])
+                               "-fopenmp", "-fPIC", "-shared", "-o", tmp, _SRC, "-lm"])
         os.replace(tmp, _LIB)
     return _LIB
 
@@ -48,6 +48,7 @@ def _load():
             build(force=True)
         lib = ctypes.CDLL(_LIB)
         lib.orc_csr_spmv.restype = None
+        lib.orc_csr_spmv_par.restype = None
         lib.orc_csr_absmv.restype = None
         lib.orc_csr_spmm.restype = None
         lib.orc_csr_check.restype = ctypes.c_int
@@ -84,7 +85,7 @@ def to_f64(v: np.ndarray, bf16_bits: bool = False) -> np.ndarray:
     v = np.asarray(v)
     if bf16_bits:
         return (v.astype(np.uint32) << 16).view(np.float32).astype(np.float64)
-    return v.astype(np.float64)
+    return v.astype(np.float64, copy=False)
 
 
 def round_values(v: np.ndarray, dtype: str) -> np.ndarray:
@@ -116,6 +117,20 @@ def csr_spmv(A, x, bf16_bits: bool = False) -> np.ndarray:
     y = np.empty(A.n_rows, dtype=np.float64)
     lib.orc_csr_spmv(ctypes.c_int64(A.n_rows), _p(rp, _I64P), _p(col, _I32P), _p(val, _F64P),
                      _p(x, _F64P), _p(y, _F64P))
+    return y
+
+
+def csr_spmv_parallel(A, x, threads: int, bf16_bits: bool = False) -> np.ndarray:
+    """csr_spmv with the rows split into `threads` equal contiguous ranges, one
+    OpenMP thread each; every row keeps its serial order, so the result is
+    bit-identical to csr_spmv (for timing the oracle on all host cores)."""
+    lib = _load()
+    rp, col = _i64(A.row_ptr), _i32(A.col)
+    val = np.ascontiguousarray(to_f64(A.val, bf16_bits))
+    x = np.ascontiguousarray(to_f64(x))
+    y = np.empty(A.n_rows, dtype=np.float64)
+    lib.orc_csr_spmv_par(ctypes.c_int64(A.n_rows), _p(rp, _I64P), _p(col, _I32P), _p(val, _F64P),
+                         _p(x, _F64P), _p(y, _F64P), ctypes.c_int(int(threads)))
     return y
 
 

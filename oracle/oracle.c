@@ -19,8 +19,9 @@
  * lanes per row, sort window, Hybrid K1 rule) are the project's documented
  * readings; each routine states the one it uses.
  *
- * Build: gcc -O2 -ffp-contract=off -fPIC -shared (no fast-math, no FMA
- * contraction, so a*b+c is two roundings exactly as written).
+ * Build: gcc -O2 -ffp-contract=off -fopenmp -fPIC -shared (no fast-math, no
+ * FMA contraction, so a*b+c is two roundings exactly as written; OpenMP only
+ * in orc_csr_spmv_par).
  */
 #include <stdint.h>
 #include <stdlib.h>
@@ -37,6 +38,22 @@
 void orc_csr_spmv(int64_t n_rows, const int64_t *rp, const int32_t *col,
                   const double *val, const double *x, double *y)
 {
+    for (int64_t i = 0; i < n_rows; i++) {
+        double acc = 0.0;
+        for (int64_t j = rp[i]; j < rp[i + 1]; j++)
+            acc += val[j] * x[col[j]];
+        y[i] = acc;
+    }
+}
+
+/* The same serial sum with the rows split into n_threads contiguous ranges
+ * of equal row count (a static partition), one OpenMP thread each: every row
+ * is still summed by one thread in ascending order, so y is bit-identical to
+ * orc_csr_spmv.  Used only to time the oracle on every host core. */
+void orc_csr_spmv_par(int64_t n_rows, const int64_t *rp, const int32_t *col,
+                      const double *val, const double *x, double *y, int n_threads)
+{
+#pragma omp parallel for schedule(static) num_threads(n_threads)
     for (int64_t i = 0; i < n_rows; i++) {
         double acc = 0.0;
         for (int64_t j = rp[i]; j < rp[i + 1]; j++)

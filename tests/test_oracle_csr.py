@@ -202,3 +202,12 @@ def test_scaled_error_nan_fails_every_tolerance(oracle):
     assert not (e <= 1e-5)
     # an infinite result against a finite reference is an infinite error
     assert oracle.scaled_error([float("inf")], [1.0], [1.0]) == float("inf")
+
+
+@pytest.mark.parametrize("threads", [1, 3, 8])
+def test_parallel_spmv_bit_identical_to_serial(oracle, threads):
+    """Row partition over threads changes no row's summation order."""
+    A = W.random_csr(5000, 4000, seed=11, max_len=50, empty_frac=0.1, long_rows=4, long_len=3000)
+    x = np.random.default_rng(11).standard_normal(A.n_cols)
+    np.testing.assert_array_equal(oracle.csr_spmv_parallel(A, x, threads).view(np.uint64),
+                                  oracle.csr_spmv(A, x).view(np.uint64))
