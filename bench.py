@@ -383,6 +383,40 @@ def bench_cg(args, torch, rg, W):
         out["results"].append({"storage": dt, **st, "oracle_relres": rel,
                                "max_abs_x_minus_1": float(np.max(np.abs(xh - 1.0))),
                                "spmv_us": us, "spmv_gbs": bb / us / 1e3})
+    # the same solver on a matrix whose values BF16/FP16 (and FP32) round:
+    # A_hi stored in FP64, so the refinement has to correct the storage
+    # rounding of A_lo; representation error reported apart from the solve
+    As = W.stencil_3d_27pt_spd(N, seed=W.SEEDS["cg_spd"])
+    # its rows sum to 1 (A 1 = 1), so the solution is a seeded random x*
+    xstar = W.uniform_vector(As.n_cols, W.SEEDS["cg_spd"] + 1)
+    bs = oracle.csr_spmv(As, xstar)
+    bsd = torch.from_numpy(bs).to("cuda:0")
+    Ahs = rg.rgcsr_from_csr(As, value_dtype="f64")
+    out["rounded_values"] = {"matrix": f"27-point pattern, off-diagonal -(1 + 0.25 u) symmetric, diagonal 1 + "
+                                       f"row sum of |off|, N={N}, A_hi FP64; b = A x*, x* ~ U[-1,1)",
+                             "results": []}
+    for dt in ("f32", "bf16", "f16", "fp64-cg"):
+        if dt == "fp64-cg":
+            rep, Al = 0.0, Ahs
+        else:
+            r16 = oracle.round_values(As.val.astype(np.float32) if dt != "f32" else As.val, dt)
+            lo = oracle.to_f64(r16, bf16_bits=(dt == "bf16"))
+            rep = float(np.max(np.abs(lo - As.val) / np.abs(As.val)))
+            Al = rg.rgcsr_from_csr(As, value_dtype=dt)
+        for _ in range(2):
+            x = torch.zeros(As.n_rows, dtype=torch.float64, device="cuda:0")
+            if dt == "fp64-cg":
+                st = rg.rgcsr_cg_solve_f64(Ahs, bsd, x, tol=1e-10, max_iter=2000)
+            else:
+                st = rg.rgcsr_cg_solve(Al, Ahs, bsd, x, tol=1e-10, inner_tol=1e-4)
+        xh = x.cpu().numpy()
+        r = bs - oracle.csr_spmv(As, xh)
+        out["rounded_values"]["results"].append({
+            "storage": dt, **st, "max_rel_representation_error": rep,
+            "oracle_relres": float(np.sqrt(np.dot(r, r)) / np.sqrt(np.dot(bs, bs))),
+            "max_abs_x_minus_xstar": float(np.max(np.abs(xh - xstar)))})
+        if Al is not Ahs:
+            Al.close()
     if not args.no_cpu:
         # the oracle's plain FP64 CG (serial CSR SpMV) to the same residual, one host core
         t0 = time.perf_counter()
@@ -408,6 +442,10 @@ def bench_grad(args, torch, rg, W):
     out = {"metric": "SpMV forward + backward, Zipf n=1e6, FP32", "results": [],
            "cpu_baseline": {"kind": "oracle", "seconds": cpu_s, "cores": 1,
                             "sample": "one FP64 forward (r = A x - b) and backward (dx = A^T r, dtheta) pass"}}
+    s = oracle.csr_absmv(A, x)
+    st = float(np.max(s + np.abs(bvec))) * float(np.max(np.abs(x)))
+    AT = W.CSR(A.n_cols, A.n_rows, *oracle.csr_transpose(A.astype(np.float64)))
+    sx = float(np.max(oracle.csr_absmv(AT, s + np.abs(bvec))))
     for transpose in (True, False):
         M = rg.rgcsr_from_csr(A, keep_csr_map=True, build_transpose=transpose, **LAYOUT_ZIPF)
         y = torch.empty(A.n_rows, device="cuda:0")
@@ -423,18 +461,21 @@ def bench_grad(args, torch, rg, W):
             step(i)
         t = _mean_launch_ms(torch, step, args.steps)
         fw = _mean_launch_ms(torch, lambda i: rg.rgcsr_spmv(M, xd, y), args.steps)
-        s = oracle.csr_absmv(A, x)
-        st = float(np.max(s + np.abs(bvec))) * float(np.max(np.abs(x)))
         out["results"].append({"dx": "transposed" if transpose else "atomic",
                                "step_us": float(np.mean(t)) * 1e3, "forward_spmv_us": float(np.mean(fw)) * 1e3,
                                "dtheta_err_scaled": float(np.max(np.abs(dv.cpu().numpy() - dv_ref))) / st,
+                               "dx_err_scaled": float(np.max(np.abs(dx.cpu().numpy() - dx_ref))) / sx,
                                "dx_err_abs": float(np.max(np.abs(dx.cpu().numpy() - dx_ref)))})
         M.close()
+    out["tolerance"] = ("dtheta: max|d| <= 1e-5 * max(s + |b|) * max|x|; dx: max|d| <= 1e-5 * "
+                        "max(|A|^T (s + |b|)), s = |A| |x|; the *_err_scaled fields are max|d| over those scales")
     rng = np.random.default_rng(W.SEEDS["grad_samples"])
+    ks = rng.choice(A.nnz, 64, replace=False)
+    js = rng.choice(A.n_cols, 64, replace=False)
     h = 1e-3
     A64 = A.astype(np.float64)
     worst = 0.0
-    for k in rng.choice(A.nnz, 64, replace=False):
+    for k in ks:
         tp, tm = A64.val.copy(), A64.val.copy()
         tp[k] += h
         tm[k] -= h
@@ -442,7 +483,51 @@ def bench_grad(args, torch, rg, W):
               - oracle.loss(W.CSR(A.n_rows, A.n_cols, A.row_ptr, A.col, tm), x, bvec)) / (2 * h)
         worst = max(worst, abs(fd - dv_ref[k]) / max(1.0, abs(dv_ref[k])))
     out["oracle_vs_central_difference_max_rel"] = worst
+    out["device_fp64_central_difference"] = device_central_differences(torch, rg, A64, x, bvec, ks, js, h)
     print(json.dumps(out), flush=True)
+
+
+def device_central_differences(torch, rg, A64, x, bvec, ks, js, h):
+    """Central differences of the device's own FP64 forward (FP64 storage and
+    vectors) at the given theta entries ks and x entries js, against the device
+    backward.  Only the rows a perturbation touches change; their share
+    (r+^2 - r-^2) / 2 of the loss difference is summed directly."""
+    M = rg.rgcsr_from_csr(A64, value_dtype="f64", keep_csr_map=True, build_transpose=True, **LAYOUT_ZIPF)
+    theta = torch.from_numpy(A64.val).to("cuda:0")
+    xd = torch.from_numpy(np.asarray(x, np.float64)).to("cuda:0")
+    bd = torch.from_numpy(np.asarray(bvec, np.float64)).to("cuda:0")
+    y = torch.empty(A64.n_rows, dtype=torch.float64, device="cuda:0")
+
+    def resid():
+        rg.rgcsr_spmv(M, xd, y)
+        return y - bd
+
+    r0 = resid().contiguous()
+    dx = torch.empty(A64.n_cols, dtype=torch.float64, device="cuda:0")
+    dv = torch.empty(A64.nnz, dtype=torch.float64, device="cuda:0")
+    rg.rgcsr_spmv_transpose_grad(M, xd, r0, dx, dv)
+    dxh, dvh = dx.cpu().numpy(), dv.cpu().numpy()
+
+    def central(vec, i, update):
+        orig = float(vec[i].item())
+        hi, lo = orig + h, orig - h
+        vec[i] = hi
+        update()
+        rp = resid()
+        vec[i] = lo
+        update()
+        rm = resid()
+        vec[i] = orig
+        update()
+        return 0.5 * float(((rp - rm) * (rp + rm)).sum().item()) / (hi - lo)
+
+    th = max(abs(central(theta, int(k), lambda: rg.rgcsr_set_values(M, theta)) - dvh[k]) / max(1.0, abs(dvh[k]))
+             for k in ks)
+    xx = max(abs(central(xd, int(j), lambda: None) - dxh[j]) / max(1.0, abs(dxh[j])) for j in js)
+    M.close()
+    return {"theta_entries": len(ks), "x_entries": len(js), "h": h,
+            "max_rel_theta": th, "max_rel_x": xx,
+            "note": "|fd - g| / max(1, |g|) with g the device FP64 backward"}
 
 
 def bench_fp64(args, torch, rg, W):

@@ -69,6 +69,22 @@ def _dev_check(t, name: str):
         raise ValueError(f"{name} must be contiguous")
 
 
+def _size_check(t, name: str, n: int, dtype=None) -> None:
+    """t must hold exactly n elements (of dtype, when given)."""
+    if t.numel() != n:
+        raise ValueError(f"{name} has {t.numel()} elements, expected {n}")
+    if dtype is not None and t.dtype != dtype:
+        raise ValueError(f"{name} has dtype {t.dtype}, expected {dtype}")
+
+
+def _on_device_of(A, t, name: str) -> None:
+    """t must be a contiguous device tensor on the device of matrix A."""
+    _dev_check(t, name)
+    dev = getattr(A, "device", None)
+    if dev is not None and t.device.index != dev:
+        raise ValueError(f"{name} is on cuda:{t.device.index}, the matrix on cuda:{dev}")
+
+
 def make_opts(G: int = 64, T: int = 1, sigma: int = 1, tau: int = -1, value_dtype: str = "f32",
               keep_csr_map: bool = False, build_transpose: bool = False, validate: bool = True,
               rows_per_lane: int = 0, pad_loads: int = -1, load_policy: int = 0) -> _lib.Opts:
@@ -136,6 +152,11 @@ class RgCSRMatrix:
         self.info = info.as_dict()
         self.n_rows, self.n_cols, self.nnz = self.info["n_rows"], self.info["n_cols"], self.info["nnz"]
         self.value_dtype = self.info["value_dtype"]
+        # the device the handle lives on (the current one when it was made)
+        self.device = _torch().cuda.current_device()
+        # bumped by every rgcsr_set_values; the autograd function uses it to
+        # see whether the stored values changed between forward and backward
+        self.value_version = 0
 
     @property
     def handle(self):
@@ -302,23 +323,43 @@ def rgcsr_spmv_batched(A: RgCSRMatrix, X, Y, persistent: bool = False, stream=No
 
 
 def rgcsr_spmv_transpose_grad(A: RgCSRMatrix, x, dy, dx=None, dvals=None, stream=None) -> None:
-    """dx = A^T dy and dvals[k] = dy[row(k)] * x[col(k)] (CSR order)."""
-    _dev_check(dy, "dy")
-    for t, nm in ((x, "x"), (dx, "dx"), (dvals, "dvals")):
+    """dx = A^T dy and dvals[k] = dy[row(k)] * x[col(k)] (CSR order).  x, dx
+    hold n_cols elements, dy n_rows, dvals nnz, all of dy's dtype (float32 or
+    float64) on the matrix's device; x is needed only for dvals."""
+    # every size and dtype first, then the devices
+    if dy.dtype not in (_torch().float32, _torch().float64):
+        raise ValueError(f"dy has dtype {dy.dtype}, expected float32 or float64")
+    _size_check(dy, "dy", A.n_rows)
+    if dvals is not None and x is None:
+        raise ValueError("dvals needs x")
+    for t, nm, n in ((x, "x", A.n_cols), (dx, "dx", A.n_cols), (dvals, "dvals", A.nnz)):
         if t is not None:
-            _dev_check(t, nm)
+            _size_check(t, nm, n, dy.dtype)
+    for t, nm in ((dy, "dy"), (x, "x"), (dx, "dx"), (dvals, "dvals")):
+        if t is not None:
+            _on_device_of(A, t, nm)
     _lib.call("rgcsr_spmv_transpose_grad", A.handle, _ptr(x), _ptr(dy), _ptr(dx), _ptr(dvals),
               _code_of_tensor(dy), _stream(stream))
 
 
 def rgcsr_set_values(A: RgCSRMatrix, vals, stream=None) -> None:
-    """Overwrite stored values from CSR-ordered values (device tensor or numpy array)."""
+    """Overwrite stored values from nnz CSR-ordered values (a float64/float32
+    device tensor on the matrix's device, or a float64/float32/float16 numpy
+    array)."""
     if isinstance(vals, np.ndarray):
         v = np.ascontiguousarray(vals)
+        if v.size != A.nnz:
+            raise ValueError(f"vals has {v.size} elements, expected {A.nnz}")
+        if v.dtype not in (np.float64, np.float32, np.float16):
+            raise ValueError(f"vals has dtype {v.dtype}, expected float64, float32 or float16")
         _lib.call("rgcsr_set_values", A.handle, _ptr(v), _code_of_numpy(v), 0, _stream(stream))
     else:
-        _dev_check(vals, "vals")
+        if vals.dtype not in (_torch().float32, _torch().float64):
+            raise ValueError(f"vals has dtype {vals.dtype}, expected float32 or float64")
+        _size_check(vals, "vals", A.nnz)
+        _on_device_of(A, vals, "vals")
         _lib.call("rgcsr_set_values", A.handle, _ptr(vals), _code_of_tensor(vals), 1, _stream(stream))
+    A.value_version = getattr(A, "value_version", 0) + 1
 
 
 def rgcsr_export(A: RgCSRMatrix, stream=None) -> dict:
@@ -589,15 +630,21 @@ def spmv_function():
             y = torch.empty(A.n_rows, dtype=x.dtype, device=x.device)
             rgcsr_spmv(A, x.detach().contiguous(), y)
             ctx.A = A
-            ctx.save_for_backward(x)
+            ctx.version = A.value_version
+            ctx.save_for_backward(x, theta)
             return y
 
         @staticmethod
         def backward(ctx, dy):
-            (x,) = ctx.saved_tensors
+            x, theta = ctx.saved_tensors
             A = ctx.A
             dy = dy.contiguous()
             need_theta, need_x = ctx.needs_input_grad[0], ctx.needs_input_grad[1]
+            # dx = A(theta)^T dy reads the stored values: when another forward
+            # (or any value update) has replaced them since this forward, put
+            # this call's theta back first; dvals do not depend on them
+            if need_x and A.value_version != ctx.version:
+                rgcsr_set_values(A, theta.detach().contiguous())
             dvals = torch.empty(A.nnz, dtype=dy.dtype, device=dy.device) if need_theta else None
             dx = torch.empty(A.n_cols, dtype=dy.dtype, device=dy.device) if need_x else None
             if dvals is not None or dx is not None:

@@ -104,6 +104,29 @@ def stencil_3d_27pt(N: int, diag: float = 27.0, off: float = -1.0, dtype=np.floa
     return _stencil((N, N, N), offs, diag, off, dtype)
 
 
+def stencil_3d_27pt_spd(N: int, seed: int, spread: float = 0.25) -> CSR:
+    """27-point pattern on N^3 with values that are not exact in BF16/FP16:
+    each off-diagonal pair a_ij = a_ji = -(1 + spread * u), u ~ U[0, 1) drawn
+    per stored entry above the diagonal in CSR order; the diagonal is 1 plus
+    the row's sum of |a_ij| (float64), so the matrix is symmetric and strictly
+    diagonally dominant with eigenvalues >= 1 (Gershgorin): SPD."""
+    A = stencil_3d_27pt(N)
+    n = A.n_rows
+    rows = np.repeat(np.arange(n, dtype=np.int64), np.diff(A.row_ptr))
+    cols = A.col.astype(np.int64)
+    upper = cols > rows
+    val = np.empty(A.nnz, dtype=np.float64)
+    val[upper] = -(1.0 + spread * np.random.default_rng(seed).uniform(size=int(upper.sum())))
+    # a lower entry (i, j), j < i, takes the value of the upper entry (j, i);
+    # upper keys j * n + i are ascending in CSR order
+    ukey = rows[upper] * n + cols[upper]
+    lower = cols < rows
+    val[lower] = val[upper][np.searchsorted(ukey, cols[lower] * n + rows[lower])]
+    offd = ~(upper | lower)
+    val[offd] = 1.0 + np.bincount(rows[~offd], weights=np.abs(val[~offd]), minlength=n)
+    return CSR(n, n, A.row_ptr, A.col, val)
+
+
 # ----------------------------------------------------------------------------
 # Random-pattern matrices
 # ----------------------------------------------------------------------------
@@ -284,6 +307,7 @@ SEEDS = {
     "grad_x": 5,
     "grad_b": 6,
     "grad_samples": 7,
+    "cg_spd": 8,
 }
 
 

@@ -238,6 +238,40 @@ def test_autograd_function_fd_and_oracle(torch_cuda, oracle):
         assert abs(fd - dv_ref[k]) <= 1e-5 * max(1.0, abs(dv_ref[k]))
 
 
+@pytest.mark.parametrize("transpose", [True, False])
+def test_autograd_two_value_sets_on_one_handle(torch_cuda, oracle, transpose):
+    """A(t1) x + A(t2) x through one handle: the second forward replaces the
+    stored values before either backward runs, and dx of each application
+    must still use its own values."""
+    torch = torch_cuda
+    A = W.random_csr(3000, 2500, seed=17, max_len=25, long_rows=2, long_len=2000, dtype=np.float32)
+    M = rg.rgcsr_from_csr(A, keep_csr_map=True, build_transpose=transpose, sigma=3000, tau=24)
+    t1 = W.normal_vector(A.nnz, 18, np.float32)
+    t2 = W.normal_vector(A.nnz, 19, np.float32)
+    x = W.normal_vector(A.n_cols, 20, np.float32)
+    b = W.normal_vector(A.n_rows, 21, np.float32)
+    F = rg.spmv_function()
+    th1, th2, xt = dev(t1).requires_grad_(True), dev(t2).requires_grad_(True), dev(x).requires_grad_(True)
+    say("autograd two value sets", transpose)
+    y = F.apply(th1, xt, M) + F.apply(th2, xt, M)
+    loss = 0.5 * ((y.double() - dev(b).double()) ** 2).sum()
+    loss.backward()
+    A1 = W.CSR(A.n_rows, A.n_cols, A.row_ptr, A.col, t1)
+    A2 = W.CSR(A.n_rows, A.n_cols, A.row_ptr, A.col, t2)
+    r = oracle.csr_spmv(A1, x) + oracle.csr_spmv(A2, x) - b
+    AT1 = W.CSR(A.n_cols, A.n_rows, *oracle.csr_transpose(A1))
+    AT2 = W.CSR(A.n_cols, A.n_rows, *oracle.csr_transpose(A2))
+    dx_ref = oracle.csr_spmv(AT1, r) + oracle.csr_spmv(AT2, r)
+    rows = np.repeat(np.arange(A.n_rows), np.diff(A.row_ptr))
+    dv_ref = r[rows] * x[A.col].astype(np.float64)
+    s = oracle.csr_absmv(A1, x) + oracle.csr_absmv(A2, x) + np.abs(b)
+    dx_scale = float(np.max(oracle.csr_absmv(AT1, s) + oracle.csr_absmv(AT2, s)))
+    dv_scale = float(np.max(s)) * float(np.max(np.abs(x)))
+    assert np.max(np.abs(host(xt.grad) - dx_ref)) <= 1e-5 * dx_scale
+    assert np.max(np.abs(host(th1.grad) - dv_ref)) <= 1e-5 * dv_scale
+    assert np.max(np.abs(host(th2.grad) - dv_ref)) <= 1e-5 * dv_scale
+
+
 def test_gradcheck_fp64_tiny(torch_cuda):
     torch = torch_cuda
     A = W.random_csr(24, 20, seed=16, max_len=6, long_rows=1, long_len=18)
@@ -268,6 +302,40 @@ def test_cg_mixed_reaches_1e10(torch_cuda, oracle, dt):
     say("  ", st, "oracle relres", rel, "max|x-1|", float(np.max(np.abs(xh - 1))))
     assert st["converged"] and rel <= 1e-10
     assert np.max(np.abs(xh - 1.0)) <= 1e-8
+
+
+def test_cg_mixed_on_values_16_bit_storage_rounds(torch_cuda, oracle):
+    """SPD 27-point matrix whose values BF16 and FP16 round, A_hi stored in
+    FP64: the refinement must correct the storage rounding of A_lo.  The
+    representation error of each storage type is measured apart from the
+    solve; the FP64 residual is recomputed by the oracle on the FP64 values."""
+    torch = torch_cuda
+    A = W.stencil_3d_27pt_spd(40, seed=W.SEEDS["cg_spd"])
+    # every row of this matrix sums to 1 (A 1 = 1, an eigenvector), so b = A 1
+    # would make the solve one Krylov step; a random solution exercises CG
+    xs = W.uniform_vector(A.n_cols, W.SEEDS["cg_spd"] + 1)
+    b = oracle.csr_spmv(A, xs)
+    bd = dev(b)
+    Ahi = rg.rgcsr_from_csr(A, value_dtype="f64")
+    outer = {}
+    for dt in ("f32", "bf16", "f16"):
+        lo = storage_values(oracle, A, dt)
+        rep = float(np.max(np.abs(lo - A.val) / np.abs(A.val)))
+        r1 = b - oracle.csr_spmv(W.CSR(A.n_rows, A.n_cols, A.row_ptr, A.col, lo), xs)
+        rel_lo = math.sqrt(float(np.dot(r1, r1)) / float(np.dot(b, b)))
+        assert rep > 0.0 and rel_lo > 1e-10   # A_lo differs from A_hi
+        say("cg rounded values", dt, "max relative representation error", rep, "relres of x* on A_lo", rel_lo)
+        Alo = rg.rgcsr_from_csr(A, value_dtype=dt)
+        xd = torch.zeros(A.n_rows, dtype=torch.float64, device="cuda:0")
+        st = rg.rgcsr_cg_solve(Alo, Ahi, bd, xd, tol=1e-10, inner_tol=1e-4)
+        xh = host(xd)
+        r = b - oracle.csr_spmv(A, xh)
+        rel = math.sqrt(float(np.dot(r, r))) / math.sqrt(float(np.dot(b, b)))
+        say("  ", st, "oracle relres", rel, "max|x-x*|", float(np.max(np.abs(xh - xs))))
+        assert st["converged"] and rel <= 1e-10
+        assert np.max(np.abs(xh - xs)) <= 1e-8
+        outer[dt] = st["outer_iterations"]
+    assert outer["bf16"] > outer["f32"]
 
 
 def test_cg_f64(torch_cuda, oracle):
@@ -398,3 +466,73 @@ def test_batch_groups_start_aligned(torch_cuda, oracle, lay):
         np.testing.assert_array_equal(col[seg] - co[i], M.col)
         np.testing.assert_array_equal(val[seg], M.val)
     B.close()
+
+
+@pytest.mark.slow
+def test_grad_full_size_zipf_fd_of_device_forward(torch_cuda, oracle):
+    """Config 5 at full size (Zipf n = 1e6).  FP32: dtheta and dx against the
+    FP64 oracle gradient with their scaled tolerances.  FP64 storage and
+    vectors: central differences (h = 1e-3) of the device's own forward on 64
+    seeded theta entries and 64 seeded x entries against the device backward.
+    The loss is quadratic in each entry, so the central difference is exact up
+    to rounding; only the rows a perturbation touches change, and their
+    contribution (r+^2 - r-^2) / 2 is summed directly."""
+    torch = torch_cuda
+    from bench import LAYOUT_ZIPF
+    A, _ = W.workload_zipf(1_000_000)
+    x32 = W.normal_vector(A.n_cols, W.SEEDS["grad_x"], np.float32)
+    b32 = W.normal_vector(A.n_rows, W.SEEDS["grad_b"], np.float32)
+    say("full-size gradient, FP32 against the oracle")
+    M = rg.rgcsr_from_csr(A, keep_csr_map=True, build_transpose=True, **LAYOUT_ZIPF)
+    xd, bd = dev(x32), dev(b32)
+    dy = (M.spmv(xd) - bd).contiguous()
+    dx = torch.empty(A.n_cols, device="cuda:0")
+    dv = torch.empty(A.nnz, device="cuda:0")
+    rg.rgcsr_spmv_transpose_grad(M, xd, dy, dx, dv)
+    r, dx_ref, dv_ref, _ = oracle.adjoint(A, x32, b32)
+    st, sx = grad_tolerances(oracle, A, x32, b32)
+    e_th = float(np.max(np.abs(host(dv) - dv_ref))) / st
+    e_x = float(np.max(np.abs(host(dx) - dx_ref))) / sx
+    say("  dtheta scaled error", e_th, "dx scaled error", e_x)
+    assert e_th <= 1e-5 and e_x <= 1e-5
+    M.close()
+
+    say("full-size gradient, FP64 central differences of the device forward")
+    A64 = A.astype(np.float64)
+    x, b = x32.astype(np.float64), b32.astype(np.float64)
+    M = rg.rgcsr_from_csr(A64, value_dtype="f64", keep_csr_map=True, build_transpose=True, **LAYOUT_ZIPF)
+    theta, xd, bd = dev(A64.val), dev(x), dev(b)
+    y = torch.empty(A.n_rows, dtype=torch.float64, device="cuda:0")
+
+    def resid():
+        rg.rgcsr_spmv(M, xd, y)
+        return y - bd
+
+    r0 = resid()
+    dx = torch.empty(A.n_cols, dtype=torch.float64, device="cuda:0")
+    dv = torch.empty(A.nnz, dtype=torch.float64, device="cuda:0")
+    rg.rgcsr_spmv_transpose_grad(M, xd, r0.contiguous(), dx, dv)
+    dxh, dvh = host(dx), host(dv)
+    rng = np.random.default_rng(W.SEEDS["grad_samples"])
+    ks = rng.choice(A.nnz, 64, replace=False)
+    js = rng.choice(A.n_cols, 64, replace=False)
+    h = 1e-3
+
+    def central(vec, i, update):
+        orig = float(vec[i].item())
+        hi, lo = orig + h, orig - h
+        vec[i] = hi
+        update()
+        rp = resid()
+        vec[i] = lo
+        update()
+        rm = resid()
+        vec[i] = orig
+        update()
+        return 0.5 * float(((rp - rm) * (rp + rm)).sum().item()) / (hi - lo)
+
+    worst_th = max(abs(central(theta, int(k), lambda: rg.rgcsr_set_values(M, theta)) - dvh[k])
+                   / max(1.0, abs(dvh[k])) for k in ks)
+    worst_x = max(abs(central(xd, int(j), lambda: None) - dxh[j]) / max(1.0, abs(dxh[j])) for j in js)
+    say("  central difference vs device backward, max relative:", worst_th, worst_x)
+    assert worst_th <= 1e-5 and worst_x <= 1e-5

@@ -133,3 +133,26 @@ def test_k1_tie_goes_to_smallest_width(oracle):
     A = W.CSR(576, 4, rp, np.concatenate([np.arange(l) for l in lens]).astype(np.int32),
               np.ones(rp[-1]))
     assert oracle.hyb_k1(A, 4) == 1
+
+
+def test_cg_on_values_that_16_bit_storage_rounds(oracle):
+    """The SPD 27-point matrix with perturbed values (the mixed-precision CG
+    case whose values BF16/FP16 round): exactly symmetric, eigenvalues >= 1,
+    and the oracle's CG agrees with a direct solve."""
+    A = W.stencil_3d_27pt_spd(8, seed=3)
+    S = sp.csr_matrix((A.val, A.col, A.row_ptr), shape=(A.n_rows, A.n_cols))
+    D = S.toarray()
+    assert np.array_equal(D, D.T)
+    ev = np.linalg.eigvalsh(D)
+    assert ev.min() >= 1.0 - 1e-12
+    # the values are not all exact in bfloat16 (8 significant bits)
+    assert np.any(oracle.to_f64(oracle.round_values(A.val.astype(np.float32), "bf16"), bf16_bits=True) != A.val)
+    # every row sums to 1: the ones vector is an eigenvector (eigenvalue 1)
+    np.testing.assert_allclose(D.sum(axis=1), 1.0, rtol=0, atol=1e-13)
+    xstar = np.random.default_rng(4).uniform(-1, 1, A.n_cols)
+    b = oracle.csr_spmv(A, xstar)
+    x, it, rel = oracle.cg(A, b, tol=1e-12)
+    assert rel <= 1e-12 and it > 10
+    xs = spla.spsolve(S.tocsc(), b)
+    assert np.max(np.abs(x - xs)) <= 1e-10
+    assert np.max(np.abs(x - xstar)) <= 1e-10
