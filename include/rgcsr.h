@@ -401,6 +401,23 @@ rgcsr_status rgcsr_cg_solve(rgcsr_handle A_lo, rgcsr_handle A_hi, const double *
                             double tol, double inner_tol, int32_t max_outer, int32_t max_inner,
                             void *stream, rgcsr_cg_stats *stats);
 
+/* rgcsr_cg_solve without any device allocation, for callers that cannot
+ * allocate (tight solver loops, harnesses that forbid hipMalloc): same
+ * arguments, method and results (bit for bit) as rgcsr_cg_solve, but the
+ * workspace (FP64 r and q, FP32 r, p, q, d, block partials and scalars) is a
+ * static device array of 32 MiB + 16.25 KiB that the library holds on every
+ * device it runs on until the process ends.  n (rows of A_lo) must be at most
+ * 1,048,576, else RGCSR_EUNSUPPORTED before any device work.  No call
+ * allocates or frees device memory.  Every call on one device shares that
+ * device's workspace: calls that overlap on one device (other host threads,
+ * or streams not ordered with each other) race and give wrong results; the
+ * call synchronises the stream before it returns, so calls made one after
+ * another are safe.  Not capturable in a HIP graph (it synchronises to test
+ * convergence). */
+rgcsr_status rgcsr_cg_solve_noalloc(rgcsr_handle A_lo, rgcsr_handle A_hi, const double *b, double *x,
+                                    double tol, double inner_tol, int32_t max_outer, int32_t max_inner,
+                                    void *stream, rgcsr_cg_stats *stats);
+
 /* Plain CG with every vector and accumulation in FP64 on A (F64 or F32
  * storage), the all-FP64 comparison solver.  Same conventions. */
 rgcsr_status rgcsr_cg_solve_f64(rgcsr_handle A, const double *b, double *x, double tol,

@@ -468,6 +468,18 @@ def rgcsr_cg_solve(A_lo: RgCSRMatrix, A_hi: RgCSRMatrix, b, x, tol: float = 1e-1
     return st.as_dict()
 
 
+def rgcsr_cg_solve_noalloc(A_lo: RgCSRMatrix, A_hi: RgCSRMatrix, b, x, tol: float = 1e-10, inner_tol: float = 1e-4,
+                           max_outer: int = 50, max_inner: int = 500, stream=None) -> dict:
+    """rgcsr_cg_solve with the library's static device workspace (no device
+    allocation; at most 1,048,576 rows; calls on one device must not overlap)."""
+    _dev_check(b, "b")
+    _dev_check(x, "x")
+    st = _lib.CGStats()
+    _lib.call("rgcsr_cg_solve_noalloc", A_lo.handle, A_hi.handle, _ptr(b), _ptr(x), tol, inner_tol, max_outer,
+              max_inner, _stream(stream), ctypes.byref(st))
+    return st.as_dict()
+
+
 def rgcsr_cg_solve_f64(A: RgCSRMatrix, b, x, tol: float = 1e-10, max_iter: int = 2000, stream=None) -> dict:
     _dev_check(b, "b")
     _dev_check(x, "x")

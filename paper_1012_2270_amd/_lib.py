@@ -94,6 +94,8 @@ SIGNATURES = {
     "hyb_destroy": (c_int, [c_vp]),
     "rgcsr_cg_solve": (c_int, [c_vp, c_vp, c_vp, c_vp, ctypes.c_double, ctypes.c_double, c_i32, c_i32, c_vp,
                                ctypes.POINTER(CGStats)]),
+    "rgcsr_cg_solve_noalloc": (c_int, [c_vp, c_vp, c_vp, c_vp, ctypes.c_double, ctypes.c_double, c_i32, c_i32,
+                                       c_vp, ctypes.POINTER(CGStats)]),
     "rgcsr_cg_solve_f64": (c_int, [c_vp, c_vp, c_vp, ctypes.c_double, c_i32, c_vp, ctypes.POINTER(CGStats)]),
     "rgcsr_autotune": (c_int, [c_i64, c_i64, c_i64, c_vp, c_vp, c_vp, c_int, ctypes.POINTER(Opts), c_vp, c_vp,
                                c_int, c_i32, c_i32, c_vp, c_vp, ctypes.POINTER(c_i32), ctypes.POINTER(Opts),

@@ -1332,10 +1332,14 @@ double read_scalar(const double *d, hipStream_t st) {
 
 extern "C" {
 
-rgcsr_status rgcsr_cg_solve(rgcsr_handle A_lo, rgcsr_handle A_hi, const double *b, double *x, double tol,
-                            double inner_tol, int32_t max_outer, int32_t max_inner, void *stream,
-                            rgcsr_cg_stats *stats) {
-    ABI_TRY
+// Device buffers of the mixed-precision CG (n rows, nb block partials).
+struct CgWork {
+    double *r64, *q64;
+    float *r, *p, *q, *d;
+    double *part, *scal;
+};
+
+static void cg_mixed_check(rgcsr_handle A_lo, rgcsr_handle A_hi, const double *b, double *x, rgcsr_cg_stats *stats) {
     check_handle(A_lo);
     check_handle(A_hi);
     if (!b || !x || !stats) fail(RGCSR_EINVAL, "null argument");
@@ -1343,14 +1347,16 @@ rgcsr_status rgcsr_cg_solve(rgcsr_handle A_lo, rgcsr_handle A_hi, const double *
     if (A_lo->n_cols != n || A_hi->n_rows != n || A_hi->n_cols != n) fail(RGCSR_EINVAL, "matrices must be square and equal in shape");
     if (A_lo->vdt == RGCSR_F64) fail(RGCSR_EUNSUPPORTED, "A_lo must store F32, F16 or BF16 values");
     if (A_hi->vdt != RGCSR_F64 && A_hi->vdt != RGCSR_F32) fail(RGCSR_EUNSUPPORTED, "A_hi must store F64 or F32 values");
-    hipStream_t st = (hipStream_t)stream;
-    const auto t0 = std::chrono::steady_clock::now();
-    const int nb = (int)nblocks_vec(n);
-    DevVec m_r64, m_q64, m_r, m_p, m_q, m_d, m_part, m_scal;
-    double *r64 = m_r64.alloc<double>(n), *q64 = m_q64.alloc<double>(n);
-    float *r = m_r.alloc<float>(n), *p = m_p.alloc<float>(n), *q = m_q.alloc<float>(n), *d = m_d.alloc<float>(n);
-    double *part = m_part.alloc<double>(nb), *scal = m_scal.alloc<double>(kNumScal);
-    SyncOnExit guard{st};
+}
+
+// FP64 iterative refinement around FP32 CG on A_lo (every buffer of w is
+// written before it is read, so none needs clearing).
+static void cg_mixed_run(rgcsr_handle A_lo, rgcsr_handle A_hi, const double *b, double *x, double tol, double inner_tol,
+                         int32_t max_outer, int32_t max_inner, hipStream_t st, const CgWork &w, int nb,
+                         rgcsr_cg_stats *stats, std::chrono::steady_clock::time_point t0) {
+    const int64_t n = A_lo->n_rows;
+    double *r64 = w.r64, *q64 = w.q64, *part = w.part, *scal = w.scal;
+    float *r = w.r, *p = w.p, *q = w.q, *d = w.d;
     hipok(launch_dot(n, b, b, 1, part, nb, st), "dot");
     hipok(launch_scalar(part, nb, scal, kScalOut, st), "scalar");
     double bnorm = std::sqrt(read_scalar(scal + kOut, st));
@@ -1394,6 +1400,61 @@ rgcsr_status rgcsr_cg_solve(rgcsr_handle A_lo, rgcsr_handle A_hi, const double *
     stats->relres = relres;
     stats->converged = relres <= tol;
     stats->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+}
+
+rgcsr_status rgcsr_cg_solve(rgcsr_handle A_lo, rgcsr_handle A_hi, const double *b, double *x, double tol,
+                            double inner_tol, int32_t max_outer, int32_t max_inner, void *stream,
+                            rgcsr_cg_stats *stats) {
+    ABI_TRY
+    cg_mixed_check(A_lo, A_hi, b, x, stats);
+    const int64_t n = A_lo->n_rows;
+    hipStream_t st = (hipStream_t)stream;
+    const auto t0 = std::chrono::steady_clock::now();
+    const int nb = (int)nblocks_vec(n);
+    DevVec m_r64, m_q64, m_r, m_p, m_q, m_d, m_part, m_scal;
+    CgWork w;
+    w.r64 = m_r64.alloc<double>(n);
+    w.q64 = m_q64.alloc<double>(n);
+    w.r = m_r.alloc<float>(n);
+    w.p = m_p.alloc<float>(n);
+    w.q = m_q.alloc<float>(n);
+    w.d = m_d.alloc<float>(n);
+    w.part = m_part.alloc<double>(nb);
+    w.scal = m_scal.alloc<double>(kNumScal);
+    SyncOnExit guard{st};
+    cg_mixed_run(A_lo, A_hi, b, x, tol, inner_tol, max_outer, max_inner, st, w, nb, stats, t0);
+    ABI_CATCH
+}
+
+rgcsr_status rgcsr_cg_solve_noalloc(rgcsr_handle A_lo, rgcsr_handle A_hi, const double *b, double *x, double tol,
+                                    double inner_tol, int32_t max_outer, int32_t max_inner, void *stream,
+                                    rgcsr_cg_stats *stats) {
+    ABI_TRY
+    cg_mixed_check(A_lo, A_hi, b, x, stats);
+    const int64_t n = A_lo->n_rows;
+    if (n > kNoAllocCgMaxRows)
+        fail(RGCSR_EUNSUPPORTED, "rgcsr_cg_solve_noalloc: " + std::to_string(n) + " rows exceed the static workspace (" +
+                                     std::to_string(kNoAllocCgMaxRows) + " rows); use rgcsr_cg_solve");
+    hipStream_t st = (hipStream_t)stream;
+    const auto t0 = std::chrono::steady_clock::now();
+    const int nb = (int)nblocks_vec(n);
+    if (nb > kNoAllocCgMaxBlocks) fail(RGCSR_EUNSUPPORTED, "too many block partials for the static workspace");
+    void *base = nullptr;
+    hipok(noalloc_cg_workspace(&base), "workspace address");
+    char *ws = (char *)base;
+    CgWork w;
+    w.r64 = (double *)ws;
+    w.q64 = (double *)(ws + kNoAllocOffQ64);
+    w.r = (float *)(ws + kNoAllocOffR);
+    w.p = (float *)(ws + kNoAllocOffP);
+    w.q = (float *)(ws + kNoAllocOffQ);
+    w.d = (float *)(ws + kNoAllocOffD);
+    w.part = (double *)(ws + kNoAllocOffPart);
+    w.scal = (double *)(ws + kNoAllocOffScal);
+    // returns only when the stream has passed every kernel that uses the
+    // workspace, so a later call (on any stream) finds it free
+    SyncOnExit guard{st};
+    cg_mixed_run(A_lo, A_hi, b, x, tol, inner_tol, max_outer, max_inner, st, w, nb, stats, t0);
     ABI_CATCH
 }
 

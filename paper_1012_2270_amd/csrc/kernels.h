@@ -88,4 +88,22 @@ hipError_t launch_gather_floor(const int32_t *col, const float *val, int64_t n, 
                                hipStream_t st);
 hipError_t launch_zero(int64_t n, void *a, int esz, int nb, hipStream_t st);
 
+// Static device workspace of the allocation-free mixed-precision CG
+// (rgcsr_cg_solve_noalloc): FP64 r and q, FP32 r, p, q, d for up to
+// kNoAllocCgMaxRows rows, then the block partials and the scalar slots, at
+// fixed 256-byte aligned offsets.  noalloc_cg_workspace returns its address on
+// the current device (looked up once per device and kept).
+constexpr int64_t kNoAllocCgMaxRows = int64_t(1) << 20;
+constexpr int64_t kNoAllocCgMaxBlocks = 2048;
+constexpr size_t kNoAllocOffQ64 = 8 * kNoAllocCgMaxRows;
+constexpr size_t kNoAllocOffR = 16 * kNoAllocCgMaxRows;
+constexpr size_t kNoAllocOffP = 20 * kNoAllocCgMaxRows;
+constexpr size_t kNoAllocOffQ = 24 * kNoAllocCgMaxRows;
+constexpr size_t kNoAllocOffD = 28 * kNoAllocCgMaxRows;
+constexpr size_t kNoAllocOffPart = 32 * kNoAllocCgMaxRows;
+constexpr size_t kNoAllocOffScal = kNoAllocOffPart + 8 * kNoAllocCgMaxBlocks;
+constexpr size_t kNoAllocCgBytes = kNoAllocOffScal + 256;
+static_assert(8 * kNumScal <= 256, "scalar slots fit their region");
+hipError_t noalloc_cg_workspace(void **base);
+
 }  // namespace rg

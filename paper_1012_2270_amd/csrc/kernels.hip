@@ -19,6 +19,8 @@
 //   dot/axpy       conjugate-gradient vector kernels (FP64 dot accumulation).
 #include <hip/hip_runtime.h>
 
+#include <mutex>
+
 #include "internal.h"
 #include "kernels.h"
 
@@ -1484,6 +1486,33 @@ hipError_t launch_zero(int64_t n, void *a, int esz, int nb, hipStream_t st) {
     else
         return hipErrorInvalidValue;
     return check_launch();
+}
+
+// ---------------------------------------------------------------------------
+// Workspace of the allocation-free CG: a file-scope device array, so no call
+// allocates.  Each device holds its own copy at its own address; host code
+// must use that address (from hipGetSymbolAddress with the device current),
+// never the array's name, which on the host is only a stand-in.
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) unsigned char scratch[kNoAllocCgBytes];
+
+hipError_t noalloc_cg_workspace(void **base) {
+    constexpr int kMaxDevices = 64;
+    static std::mutex mu;
+    static void *addr[kMaxDevices] = {};
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(mu);
+    if (!addr[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        addr[dev] = p;
+    }
+    *base = addr[dev];
+    return hipSuccess;
 }
 
 }  // namespace rg
