@@ -578,8 +578,9 @@ def bench_variants(args, torch, rg, W):
     the row length, loads over the group width, sliced ELLPACK (no row
     lengths, padding multiplied), each under three load policies (nontemporal
     matrix streams with cached x, everything cached, x nontemporal too), and
-    row lengths read off the columns (default policy), from HBM (rotating
-    copies) and from the 256 MB cache (one copy)."""
+    row lengths read off the columns (default policy), and x staged in LDS
+    per column tile for the long rows, from HBM (rotating copies) and from
+    the 256 MB cache (one copy)."""
     A1, x1 = W.workload_laplace3d(128)
     A2, x2 = W.workload_zipf(1_000_000)
     A3 = W.stencil_3d_27pt(160, dtype=np.float32)
@@ -589,31 +590,38 @@ def bench_variants(args, torch, rg, W):
                             ("stencil27_160", A3, x3, LAYOUT_STENCIL)):
         xd = torch.from_numpy(x).to("cuda:0")
         ref = None
-        for pad in (0, 1, 2, 3):
-            for lp in ((0, 1, 2) if pad != 3 else (0,)):
-                base = rg.rgcsr_from_csr(A, pad_loads=pad, load_policy=lp, **lay)
-                per = base.info["device_bytes"] + 4 * (A.n_rows + A.n_cols)
-                copies = max(1, math.ceil(ROTATE_BYTES / per))
-                mats = [base] + [base.clone() for _ in range(copies - 1)]
-                xs = [xd.clone() for _ in range(copies)]
-                ys = [torch.empty(A.n_rows, device="cuda:0") for _ in range(copies)]
-                for i in range(args.warmup):
-                    rg.rgcsr_spmv(mats[i % copies], xs[i % copies], ys[i % copies])
-                cold = float(np.mean(_mean_launch_ms(torch, lambda i: rg.rgcsr_spmv(mats[i % copies], xs[i % copies],
-                                                                             ys[i % copies]), args.steps)))
-                warm = float(np.mean(_mean_launch_ms(torch, lambda i: rg.rgcsr_spmv(mats[0], xs[0], ys[0]), args.steps)))
-                rg.rgcsr_spmv(mats[0], xs[0], ys[0])
-                y = ys[0].cpu().numpy()
-                if ref is None:
-                    ref = y
-                b = alg_bytes(A.nnz, A.n_rows, A.n_cols, base.info["n_groups"])
-                out["results"].append({"matrix": name, "pad_loads": pad, "load_policy": lp,
-                                       "slots": base.info["slots"], "us_hbm": cold * 1e3, "us_cache": warm * 1e3,
-                                       "gbs_hbm": b / (cold * 1e-3) / 1e9, "copies_rotated": copies,
-                                       "equal_to_first_variant": bool(np.array_equal(y, ref))})
-                for m in mats[1:]:
-                    m.close()
-                base.close()
+        # the cache-policy legs with the column tiles off, then the LDS leg:
+        # x staged in LDS per column tile for the long rows (matrices that
+        # have long rows)
+        combos = [(pad, lp, 0) for pad in (0, 1, 2, 3) for lp in ((0, 1, 2) if pad != 3 else (0,))]
+        if lay.get("tau", -1) >= 0:
+            combos += [(0, 0, 256), (3, 0, 256)]
+        for pad, lp, tiles in combos:
+            base = rg.rgcsr_from_csr(A, pad_loads=pad, load_policy=lp, tile_min_len=tiles, **lay)
+            per = base.info["device_bytes"] + 4 * (A.n_rows + A.n_cols)
+            copies = max(1, math.ceil(ROTATE_BYTES / per))
+            mats = [base] + [base.clone() for _ in range(copies - 1)]
+            xs = [xd.clone() for _ in range(copies)]
+            ys = [torch.empty(A.n_rows, device="cuda:0") for _ in range(copies)]
+            for i in range(args.warmup):
+                rg.rgcsr_spmv(mats[i % copies], xs[i % copies], ys[i % copies])
+            cold = float(np.mean(_mean_launch_ms(torch, lambda i: rg.rgcsr_spmv(mats[i % copies], xs[i % copies],
+                                                                         ys[i % copies]), args.steps)))
+            warm = float(np.mean(_mean_launch_ms(torch, lambda i: rg.rgcsr_spmv(mats[0], xs[0], ys[0]), args.steps)))
+            rg.rgcsr_spmv(mats[0], xs[0], ys[0])
+            y = ys[0].cpu().numpy()
+            if ref is None:
+                ref = y
+            b = alg_bytes(A.nnz, A.n_rows, A.n_cols, base.info["n_groups"])
+            out["results"].append({"matrix": name, "pad_loads": pad, "load_policy": lp,
+                                   "x_in_lds_tiles": {"min_len": tiles, "rows": base.info["tiled_rows"],
+                                                      "entries": base.info["tile_entries"]},
+                                   "slots": base.info["slots"], "us_hbm": cold * 1e3, "us_cache": warm * 1e3,
+                                   "gbs_hbm": b / (cold * 1e-3) / 1e9, "copies_rotated": copies,
+                                   "equal_to_first_variant": bool(np.array_equal(y, ref))})
+            for m in mats[1:]:
+                m.close()
+            base.close()
         hyb = rg.hyb_from_csr(A)
         per = hyb.info["device_bytes"] + 4 * (A.n_rows + A.n_cols)
         copies = max(1, math.ceil(ROTATE_BYTES / per))

@@ -111,11 +111,25 @@ typedef struct {
                                2 = x gathers nontemporal too.  1 and 2 need F32 values,
                                lanes_per_row = 1 and F32 vectors, and apply to single
                                right-hand-side launches */
+    int32_t tile_min_len;   /* kernel schedule: long rows of at least this many nonzeros
+                               (and at least 4 per column tile) are also stored split
+                               by column tile of 32,768 columns; a launch with one F32
+                               vector of unit stride and load policy 0 first runs one
+                               workgroup per (tile, run of those rows) that stages the
+                               tile of x in LDS and writes one partial sum per (row,
+                               tile), then the SpMV kernel adds each row's partials in
+                               tile order (x is kept in LDS instead of the caches, after
+                               the texture-cache study of Section 4.3).  Rows with more
+                               than 8,192 nonzeros in one tile stay on the long-row
+                               path.  0 = off; -1 (default) = 256, used only when the
+                               tiled rows hold at least 262,144 nonzeros.  F64 storage
+                               never tiles. */
 } rgcsr_opts;
 
 /* Fills *opts with the paper's layout: G = 64, T = 1, sigma = 1, no long
  * rows, float32 storage, no CSR map, no transpose, validation on, automatic
- * kernel schedule (rows_per_lane = 0, pad_loads = -1, load_policy = 0). */
+ * kernel schedule (rows_per_lane = 0, pad_loads = -1, load_policy = 0,
+ * tile_min_len = -1). */
 void rgcsr_default_opts(rgcsr_opts *opts);
 
 typedef struct rgcsr_matrix_s *rgcsr_handle;
@@ -135,6 +149,7 @@ typedef struct {
     int64_t sort_window, long_row_threshold;
     int64_t device_bytes; /* device memory the handle owns */
     int32_t rows_per_lane, pad_loads, load_policy; /* kernel schedule in use */
+    int64_t tiled_rows, tile_entries, n_tiles;     /* column-tiled long rows (tile_min_len) */
 } rgcsr_info_t;
 
 /* ---- Host-only layout (no GPU needed; used to check the layout on CPU) ---- */

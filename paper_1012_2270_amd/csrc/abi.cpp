@@ -15,11 +15,10 @@
 #include "convert.h"
 #include "internal.h"
 #include "kernels.h"
+#include "tiles.h"
 
 namespace rg {
 
-static thread_local std::string g_last_error;
-void set_last_error(const std::string &msg) { g_last_error = msg; }
 
 #define HIPCHK(expr)                                                                                   \
     do {                                                                                               \
@@ -113,6 +112,19 @@ struct rgcsr_matrix_s {
     int64_t *row_ptr = nullptr;  // CSR map, nullable
     rgcsr_matrix_s *AT = nullptr;
     int32_t *t_map_slot = nullptr, *t_map_long = nullptr;
+    // column-tiled long rows (tiles.h); their arrays live in `mem`, or in
+    // tile_mem for handles converted on the device
+    int64_t n_tiles = 0, n_trows = 0, n_tent = 0, n_tunits = 0;
+    int64_t n_rest_wave = 0, n_rest_block = 0, n_rest_combine = 0;
+    TileUnit *tile_units = nullptr;
+    int32_t *tile_ptr = nullptr, *tile_src = nullptr, *tile_orow = nullptr;
+    uint16_t *tile_lcol = nullptr;
+    void *tile_val = nullptr;
+    float *tile_partial = nullptr;
+    LongItem *rest_wave = nullptr, *rest_block = nullptr, *rest_combine = nullptr;
+    void *tile_mem = nullptr;
+    size_t tile_bytes = 0;
+    std::shared_ptr<HostTiles> pending_tiles;  // host arrays until they are uploaded
 };
 
 struct hyb_matrix_s {
@@ -125,43 +137,13 @@ struct hyb_matrix_s {
     void *ell_val = nullptr, *coo_val = nullptr;
 };
 
-#define ABI_TRY try {
-#define ABI_CATCH                                                                                      \
-    }                                                                                                  \
-    catch (const rg::Error &e) {                                                                       \
-        rg::set_last_error(e.msg);                                                                     \
-        return e.st;                                                                                   \
-    }                                                                                                  \
-    catch (const std::bad_alloc &) {                                                                   \
-        rg::set_last_error("host allocation failed");                                                  \
-        return RGCSR_ENOMEM;                                                                           \
-    }                                                                                                  \
-    catch (...) {                                                                                      \
-        rg::set_last_error("unexpected internal error");                                               \
-        return RGCSR_EINVAL;                                                                           \
-    }                                                                                                  \
-    return RGCSR_OK;
-
 namespace {
-
-void check_dtype(int dt, const char *what) {
-    if (dtype_size(dt) == 0) fail(RGCSR_EINVAL, std::string("bad dtype for ") + what);
-}
 
 void check_device_geometry(const LayoutParams &p) {
     const int64_t GT = (int64_t)p.G * p.T;
     if (!(GT % 64 == 0 || 64 % GT == 0))
         fail(RGCSR_EUNSUPPORTED, "device kernels need group_size * lanes_per_row to be a multiple or a divisor of 64");
 }
-
-// Host layout (+ transposed layout) for one or more CSR matrices.
-struct Built {
-    HostLayout L;
-    bool has_T = false;
-    HostLayout LT;       // layout of A^T with values
-    HostLayout LTmap;    // layout of A^T whose "values" are source indices
-    std::vector<int64_t> row_ptr;  // global CSR row pointers
-};
 
 }  // namespace
 
@@ -179,50 +161,6 @@ struct rgcsr_plan_s {
 };
 
 namespace {
-
-void build_host(Built &B, const LayoutParams &p, int vdt, int32_t count, const int64_t *n_rows,
-                const int64_t *n_cols, const int64_t *const *rp, const int32_t *const *col,
-                const void *const *vals, int vals_dt, bool validate, bool keep_map, bool transpose) {
-    const int esz = dtype_size(vdt);
-    B.L.G = p.G; B.L.T = p.T; B.L.sigma = p.sigma; B.L.tau = p.tau; B.L.vdt = vdt; B.L.esz = esz;
-    B.has_T = transpose;
-    if (transpose) {
-        B.LT = B.L;
-        B.LTmap = B.L;
-        B.LTmap.esz = 4;
-    }
-    if (keep_map || transpose) B.row_ptr.assign(1, 0);
-    int64_t nnz_base = 0;
-    std::vector<uint8_t> conv;
-    for (int32_t m = 0; m < count; m++) {
-        const int64_t nr = n_rows[m], nc = n_cols[m];
-        if (nr < 0 || nc < 0) fail(RGCSR_EINVAL, "negative matrix size");
-        if (!rp[m]) fail(RGCSR_EINVAL, "row_ptr is null");
-        const int64_t nnz = rp[m][nr];
-        if (validate) validate_csr(nr, nc, nnz, rp[m], col[m]);
-        if (nnz > 0 && !vals[m]) fail(RGCSR_EINVAL, "vals is null");
-        conv.resize((size_t)nnz * esz);
-        if (nnz) convert_values(vals[m], vals_dt, conv.data(), vdt, nnz);
-        append_layout(B.L, p, nr, nc, rp[m], col[m], conv.data(), esz, 0);
-        if (!B.row_ptr.empty())
-            for (int64_t r = 0; r < nr; r++) B.row_ptr.push_back(nnz_base + rp[m][r + 1]);
-        if (transpose) {
-            std::vector<int64_t> rpT;
-            std::vector<int32_t> colT, srcT;
-            transpose_csr(nr, nc, rp[m], col[m], rpT, colT, srcT);
-            std::vector<uint8_t> valsT((size_t)nnz * esz);
-            for (int64_t k = 0; k < nnz; k++) memcpy(&valsT[(size_t)k * esz], &conv[(size_t)srcT[k] * esz], esz);
-            std::vector<int32_t> mapT(nnz);
-            if (nnz_base + nnz > INT32_MAX) fail(RGCSR_EOVERFLOW, "transpose map needs total nnz < 2^31");
-            for (int64_t k = 0; k < nnz; k++) mapT[k] = (int32_t)(srcT[k] + nnz_base);
-            append_layout(B.LT, p, nc, nr, rpT.data(), colT.data(), valsT.data(), esz, 0);
-            append_layout(B.LTmap, p, nc, nr, rpT.data(), colT.data(), (const uint8_t *)mapT.data(), 4, 0xff);
-        }
-        nnz_base += nnz;
-    }
-    build_long_work(B.L.long_ptr, B.L.work);
-    if (transpose) build_long_work(B.LT.long_ptr, B.LT.work);
-}
 
 // Runs of wave items, one per wavefront: starting at wave item j, the
 // longest run R in {8, 4, 2} whose widest group times R is at most
@@ -300,8 +238,49 @@ void choose_schedule(rgcsr_matrix_s *h, const HostLayout &L, int64_t short_nnz, 
 // A handle whose fields describe the host layout and whose device arrays are
 // listed in `a` but not yet placed (plan step of rgcsr_plan_from_csr and of
 // make_device).  Host work only.
+// Tile arrays of the handle, listed in arena a (counts set on h).
+void add_tile_arrays(rgcsr_matrix_s *h, const HostTiles &T, Arena &a) {
+    h->n_tiles = T.n_tiles;
+    h->n_trows = T.n_trows;
+    h->n_tent = T.n_ent;
+    h->n_tunits = (int64_t)T.units.size();
+    h->n_rest_wave = (int64_t)T.rest.wave.size();
+    h->n_rest_block = (int64_t)T.rest.block.size();
+    h->n_rest_combine = (int64_t)T.rest.combine.size();
+    if (!T.active()) return;
+    a.add(&h->tile_units, T.units.size());
+    a.add(&h->tile_ptr, T.ptr.size());
+    a.add(&h->tile_lcol, (size_t)T.n_ent);
+    a.add((uint8_t **)&h->tile_val, (size_t)T.n_ent * h->esz);
+    a.add(&h->tile_src, (size_t)T.n_ent);
+    a.add(&h->tile_orow, (size_t)T.n_trows);
+    a.add(&h->tile_partial, (size_t)(T.n_tiles * T.n_trows));
+    a.add(&h->rest_wave, T.rest.wave.size());
+    a.add(&h->rest_block, T.rest.block.size());
+    a.add(&h->rest_combine, T.rest.combine.size());
+}
+
+// Uploads the tile arrays; values come from the handle's long-row segment
+// (already on the device) through the source map.
+void upload_tiles(rgcsr_matrix_s *h, const HostTiles &T, const std::vector<int32_t> &long_row, hipStream_t st) {
+    if (!T.active()) return;
+    upload(h->tile_units, T.units, st);
+    upload(h->tile_ptr, T.ptr, st);
+    upload(h->tile_lcol, T.lcol, st);
+    upload(h->tile_src, T.src, st);
+    std::vector<int32_t> orow(T.n_trows);
+    for (int64_t k = 0; k < T.n_trows; k++) orow[k] = long_row[T.trow[k]];
+    upload(h->tile_orow, orow, st);
+    upload(h->rest_wave, T.rest.wave, st);
+    upload(h->rest_block, T.rest.block, st);
+    upload(h->rest_combine, T.rest.combine, st);
+    HIPCHK(launch_tile_values(T.n_ent, h->tile_src, h->long_val, h->tile_val, h->esz, st));
+    // orow is a host temporary: wait for its copy
+    HIPCHK(hipStreamSynchronize(st));
+}
+
 rgcsr_matrix_s *prepare_handle(const HostLayout &L, bool with_row_ptr, const HostLayout *map, Arena &a,
-                               int32_t rows_per_lane, int32_t pad_loads, int32_t load_policy) {
+                               int32_t rows_per_lane, int32_t pad_loads, int32_t load_policy, int32_t tile_min_len) {
     auto *h = new rgcsr_matrix_s();
     try {
         h->prm = LayoutParams{L.G, L.T, L.sigma, L.tau};
@@ -355,6 +334,11 @@ rgcsr_matrix_s *prepare_handle(const HostLayout &L, bool with_row_ptr, const Hos
             a.add(&h->t_map_slot, (size_t)map->slots);
             a.add(&h->t_map_long, (size_t)map->long_nnz);
         }
+        // the column-tiled path takes FP32 vectors, so F64 storage has none
+        auto tiles = std::make_shared<HostTiles>();
+        if (L.vdt != RGCSR_F64) build_tiles(L, tile_min_len, *tiles);
+        add_tile_arrays(h, *tiles, a);
+        if (tiles->active()) h->pending_tiles = tiles;
         h->bytes = a.total;
     } catch (...) {
         delete h;
@@ -391,14 +375,17 @@ void place_and_upload(rgcsr_matrix_s *h, Arena &a, const HostLayout &L, const st
         if (map->slots) HIPCHK(hipMemcpyAsync(h->t_map_slot, map->slot_val.data(), (size_t)map->slots * 4, hipMemcpyHostToDevice, st));
         if (map->long_nnz) HIPCHK(hipMemcpyAsync(h->t_map_long, map->long_val.data(), (size_t)map->long_nnz * 4, hipMemcpyHostToDevice, st));
     }
+    if (h->pending_tiles) upload_tiles(h, *h->pending_tiles, L.long_row, st);
     HIPCHK(hipStreamSynchronize(st));
+    h->pending_tiles.reset();
 }
 
 rgcsr_matrix_s *make_device(const HostLayout &L, const std::vector<int64_t> *row_ptr,
                             const HostLayout *map, hipStream_t st, int32_t rows_per_lane = 0,
-                            int32_t pad_loads = -1, int32_t load_policy = 0) {
+                            int32_t pad_loads = -1, int32_t load_policy = 0, int32_t tile_min_len = 0) {
     Arena a;
-    rgcsr_matrix_s *h = prepare_handle(L, row_ptr != nullptr, map, a, rows_per_lane, pad_loads, load_policy);
+    rgcsr_matrix_s *h = prepare_handle(L, row_ptr != nullptr, map, a, rows_per_lane, pad_loads, load_policy,
+                                       tile_min_len);
     try {
         place_and_upload(h, a, L, row_ptr, map, nullptr, st);
     } catch (...) {
@@ -416,7 +403,7 @@ rgcsr_matrix_s *make_device(const HostLayout &L, const std::vector<int64_t> *row
 rgcsr_matrix_s *make_device_on_device(DevPlan &P, const LayoutParams &p, int vdt, const int64_t *rp,
                                       const int32_t *col, const void *vals, int vals_dt, bool keep_map,
                                       hipStream_t st, int32_t rows_per_lane, int32_t pad_loads,
-                                      int32_t load_policy) {
+                                      int32_t load_policy, int32_t tile_min_len) {
     HostLayout L;  // sizes and host-side offsets only
     L.G = p.G; L.T = p.T; L.sigma = p.sigma; L.tau = p.tau; L.vdt = vdt; L.esz = dtype_size(vdt);
     L.n_rows = P.n_rows; L.n_cols = P.n_cols; L.nnz = P.nnz;
@@ -479,9 +466,31 @@ rgcsr_matrix_s *make_device_on_device(DevPlan &P, const LayoutParams &p, int vdt
         if (keep_map)
             HIPCHK(hipMemcpyAsync(h->row_ptr, rp, ((size_t)P.n_rows + 1) * 8, hipMemcpyDeviceToDevice, st));
         HIPCHK(hipStreamSynchronize(st));
+        // column tiles from the converted long-row segment: its columns come
+        // back to the host, the tile arrays go to a block of their own
+        if (tile_min_len != 0 && vdt != RGCSR_F64 && L.nl > 0) {
+            L.nl = P.nl;
+            L.long_ptr = P.long_ptr_host;
+            L.long_col.resize((size_t)L.long_nnz);
+            L.long_row.resize((size_t)L.nl);
+            if (L.long_nnz)
+                HIPCHK(hipMemcpyAsync(L.long_col.data(), h->long_col, (size_t)L.long_nnz * 4, hipMemcpyDeviceToHost, st));
+            HIPCHK(hipMemcpyAsync(L.long_row.data(), h->long_row, (size_t)L.nl * 4, hipMemcpyDeviceToHost, st));
+            HIPCHK(hipStreamSynchronize(st));
+            HostTiles T;
+            build_tiles(L, tile_min_len, T);
+            Arena ta;
+            add_tile_arrays(h, T, ta);
+            if (T.active()) {
+                h->tile_mem = ta.commit();
+                h->tile_bytes = ta.total;
+                upload_tiles(h, T, L.long_row, st);
+            }
+        }
     } catch (...) {
         (void)hipStreamSynchronize(st);
         if (h->mem) (void)hipFree(h->mem);
+        if (h->tile_mem) (void)hipFree(h->tile_mem);
         delete h;
         throw;
     }
@@ -492,6 +501,7 @@ void free_handle(rgcsr_matrix_s *h) {
     if (!h) return;
     if (h->AT) free_handle(h->AT);
     if (h->mem && h->owns_mem) (void)hipFree(h->mem);
+    if (h->tile_mem) (void)hipFree(h->tile_mem);
     delete h;
 }
 
@@ -508,8 +518,10 @@ int32_t short_waves(const rgcsr_matrix_s *h, bool scheduled) {
 }
 
 // use_rows: the launch uses the handle's rows-per-lane schedule (single
-// right-hand side); otherwise one row per lane.
-SpmvParams params_of(const rgcsr_matrix_s *h, bool use_rows) {
+// right-hand side); otherwise one row per lane.  tiled: the tile kernel has
+// written the partial sums of the column-tiled rows, so the long-row work
+// covers the other long rows and the first wavefront items add the partials.
+SpmvParams params_of(const rgcsr_matrix_s *h, bool use_rows, bool tiled = false) {
     SpmvParams P{};
     P.gp = h->gp; P.gend = h->gend; P.grp_row0 = h->grp_row0; P.short_len = h->short_len; P.short_row = h->short_row;
     P.slot_val = h->slot_val; P.slot_col = h->slot_col;
@@ -519,17 +531,30 @@ SpmvParams params_of(const rgcsr_matrix_s *h, bool use_rows) {
     P.wave_work = h->wave_work; P.block_work = h->block_work;
     P.long_row = h->long_row; P.long_ptr = h->long_ptr; P.long_val = h->long_val;
     P.long_col = h->long_col; P.partial = h->partial;
+    int64_t n_block = h->n_block, n_wave_long = h->n_wave_long, n_comb = 0;
+    if (tiled) {
+        P.wave_work = h->rest_wave;
+        P.block_work = h->rest_block;
+        n_block = h->n_rest_block;
+        n_wave_long = h->n_rest_wave;
+        n_comb = (h->n_trows + 63) / 64;
+        P.tile_partial = h->tile_partial;
+        P.tile_orow = h->tile_orow;
+        P.n_comb_units = (int32_t)n_comb;
+        P.n_tiles = (int32_t)h->n_tiles;
+        P.n_trows = (int32_t)h->n_trows;
+    }
     const int64_t sw = short_waves(h, use_rows);
-    const int64_t wave_items = h->n_wave_long + sw;
-    const int64_t units = h->n_block + (wave_items + kBlockWaves - 1) / kBlockWaves;
+    const int64_t wave_items = n_wave_long + sw;
+    const int64_t units = n_comb + n_block + (wave_items + kBlockWaves - 1) / kBlockWaves;
     const int64_t tot = h->nl + short_waves(h, false);
     if (wave_items > INT32_MAX / 2 || units > INT32_MAX / 2 || tot > INT32_MAX / 2)
         fail(RGCSR_EOVERFLOW, "too many wavefronts");
-    P.n_block_items = (int32_t)h->n_block;
-    P.n_wave_long = (int32_t)h->n_wave_long;
+    P.n_block_items = (int32_t)n_block;
+    P.n_wave_long = (int32_t)n_wave_long;
     P.n_wave_items = (int32_t)wave_items;
     P.total_units = (int32_t)units;
-    P.n_long_units = (int32_t)(h->n_block + (h->n_wave_long + kBlockWaves - 1) / kBlockWaves);
+    P.n_long_units = (int32_t)(n_comb + n_block + (n_wave_long + kBlockWaves - 1) / kBlockWaves);
     P.n_long_waves = (int32_t)h->nl;
     P.total_waves = (int32_t)tot;
     return P;
@@ -544,7 +569,10 @@ int vec_is_f64(rgcsr_dtype vt) {
 void spmv_launch(const rgcsr_matrix_s *h, int K, const void *X, int64_t ldx, void *Y, int64_t ldy, int f64,
                  bool persistent, hipStream_t st) {
     if (h->n_rows == 0) return;
-    SpmvParams P = params_of(h, K == 1);
+    // the column-tiled rows take one FP32 vector with unit stride and the
+    // default load policy; everything else runs them on the long-row path
+    const bool tiled = h->n_trows > 0 && K == 1 && !f64 && ldx == 1 && h->lp == 0;
+    SpmvParams P = params_of(h, K == 1, tiled);
     P.x = X; P.y = Y; P.ldx = ldx; P.ldy = ldy;
     int64_t nwg = P.total_units;
     // a persistent launch (several right-hand sides only) keeps two 256-thread
@@ -561,10 +589,27 @@ void spmv_launch(const rgcsr_matrix_s *h, int K, const void *X, int64_t ldx, voi
     if (K == 1 && h->n_cols * ldx * (f64 ? 8 : 4) >= (int64_t(1) << 32))
         fail(RGCSR_EUNSUPPORTED, "x (n_cols * ldx elements) of 4 GiB or more");
     if (K == 1 && h->lp != 0 && f64) fail(RGCSR_EUNSUPPORTED, "load policies 1 and 2 need F32 vectors");
-    hipError_t e = launch_spmv(P, vd, f64, h->prm.T, K, K == 1 ? h->R : 1, K == 1 ? h->lp : 0, (int)nwg, st);
+    hipError_t e = hipSuccess;
+    if (tiled) {
+        TileParams TP{};
+        TP.units = h->tile_units;
+        TP.ptr = h->tile_ptr;
+        TP.lcol = h->tile_lcol;
+        TP.val = h->tile_val;
+        TP.x = (const float *)X;
+        TP.partial = h->tile_partial;
+        TP.n_cols = h->n_cols;
+        TP.n_trows = (int32_t)h->n_trows;
+        TP.x_aligned = ((uintptr_t)X % 16) == 0;
+        e = launch_tile_spmv(TP, vd, (int)h->n_tunits, st);
+        if (e != hipSuccess) fail(RGCSR_EHIP, std::string("tile launch: ") + hipGetErrorString(e));
+    }
+    e = launch_spmv(P, vd, f64, h->prm.T, K, K == 1 ? h->R : 1, K == 1 ? h->lp : 0, (int)nwg, st);
     if (e != hipSuccess) fail(RGCSR_EHIP, std::string("spmv launch: ") + hipGetErrorString(e));
-    if (h->n_combine) {
-        e = launch_combine(h->combine, (int32_t)h->n_combine, h->long_row, h->partial, Y, ldy, f64, K, st);
+    const int64_t n_comb = tiled ? h->n_rest_combine : h->n_combine;
+    if (n_comb) {
+        e = launch_combine(tiled ? h->rest_combine : h->combine, (int32_t)n_comb, h->long_row, h->partial, Y, ldy,
+                           f64, K, st);
         if (e != hipSuccess) fail(RGCSR_EHIP, std::string("combine launch: ") + hipGetErrorString(e));
     }
 }
@@ -577,47 +622,6 @@ int64_t nblocks_vec(int64_t n) { return std::max<int64_t>(1, std::min<int64_t>(2
 }  // namespace
 
 extern "C" {
-
-void rgcsr_default_opts(rgcsr_opts *o) {
-    if (!o) return;
-    o->group_size = 64;
-    o->lanes_per_row = 1;
-    o->sort_window = 1;
-    o->long_row_threshold = -1;
-    o->value_dtype = RGCSR_F32;
-    o->keep_csr_map = 0;
-    o->build_transpose = 0;
-    o->validate = 1;
-    o->rows_per_lane = 0;
-    o->pad_loads = -1;
-    o->load_policy = 0;
-}
-
-const char *rgcsr_status_string(rgcsr_status s) {
-    switch (s) {
-    case RGCSR_OK: return "ok";
-    case RGCSR_EINVAL: return "invalid argument";
-    case RGCSR_ECSR: return "malformed CSR input";
-    case RGCSR_ENOMEM: return "out of memory";
-    case RGCSR_EOVERFLOW: return "size overflow";
-    case RGCSR_EHIP: return "HIP runtime error";
-    case RGCSR_EUNSUPPORTED: return "unsupported";
-    }
-    return "unknown status";
-}
-
-const char *rgcsr_last_error(void) { return g_last_error.c_str(); }
-
-const char *rgcsr_version(void) { return "rgcsr 0.1 gfx950"; }
-
-rgcsr_status rgcsr_rcm_order(int64_t n, int64_t nnz, const int64_t *row_ptr, const int32_t *col_idx,
-                             int32_t *perm) {
-    ABI_TRY
-    if (n < 0 || (n > 0 && (!row_ptr || !perm)) || (nnz > 0 && !col_idx)) fail(RGCSR_EINVAL, "bad argument");
-    validate_csr(n, n, nnz, row_ptr, col_idx);
-    rcm_order(n, row_ptr, col_idx, perm);
-    ABI_CATCH
-}
 
 rgcsr_status rgcsr_gather_floor(const int32_t *col, const float *val, int64_t n, const float *x, int64_t n_cols,
                                 float *out, void *stream) {
@@ -637,66 +641,6 @@ rgcsr_status rgcsr_stream_read(const void *buf, int64_t bytes, void *sink, void 
     // eight 256-thread workgroups per CU stride over the buffer
     const int nb = (int)std::min<int64_t>(std::max<int64_t>(1, bytes / 4096), (int64_t)cu_count(current_device()) * 8);
     HIPCHK(launch_stream_read(buf, bytes / 16, (int32_t *)sink, nb, (hipStream_t)stream));
-    ABI_CATCH
-}
-
-rgcsr_status rgcsr_layout_sizes(int64_t n_rows, int64_t n_cols, int64_t nnz, const int64_t *row_ptr,
-                                const int32_t *col_idx, const rgcsr_opts *opts, rgcsr_info_t *out) {
-    ABI_TRY
-    if (!out) fail(RGCSR_EINVAL, "out is null");
-    const LayoutParams p = resolve_opts(opts);
-    const bool validate = opts ? opts->validate != 0 : true;
-    if (validate) validate_csr(n_rows, n_cols, nnz, row_ptr, col_idx);
-    else if (!row_ptr) fail(RGCSR_EINVAL, "row_ptr is null");
-    std::vector<int64_t> lens;
-    int64_t ng, ns, nl, slots, lz;
-    layout_sizes(p, n_rows, row_ptr, &ng, &ns, &nl, &slots, &lz, &lens);
-    std::vector<int64_t> lp(1, 0);
-    for (int64_t l : lens) lp.push_back(lp.back() + l);
-    LongWork work;
-    build_long_work(lp, work);
-    *out = rgcsr_info_t{};
-    out->n_rows = n_rows; out->n_cols = n_cols; out->nnz = nnz;
-    out->n_groups = ng; out->n_short = ns; out->n_long = nl; out->slots = slots; out->long_nnz = lz;
-    out->n_matrices = 1; out->long_work = (int64_t)(work.wave.size() + work.block.size());
-    out->partials = work.n_partials;
-    out->group_size = p.G; out->lanes_per_row = p.T;
-    out->value_dtype = opts ? opts->value_dtype : RGCSR_F32;
-    out->sort_window = p.sigma; out->long_row_threshold = p.tau;
-    ABI_CATCH
-}
-
-rgcsr_status rgcsr_layout_host(int64_t n_rows, int64_t n_cols, int64_t nnz, const int64_t *row_ptr,
-                               const int32_t *col_idx, const void *vals, rgcsr_dtype vals_dtype,
-                               const rgcsr_opts *opts, int64_t *gp, int32_t *short_len, int32_t *short_row,
-                               void *slot_val, int32_t *slot_col, int32_t *long_row, int64_t *long_ptr,
-                               void *long_val, int32_t *long_col) {
-    ABI_TRY
-    const LayoutParams p = resolve_opts(opts);
-    const int vdt = opts ? opts->value_dtype : RGCSR_F32;
-    check_dtype(vdt, "value_dtype");
-    check_dtype(vals_dtype, "vals");
-    const bool validate = opts ? opts->validate != 0 : true;
-    Built B;
-    const int64_t *rps[1] = {row_ptr};
-    const int32_t *cols[1] = {col_idx};
-    const void *vs[1] = {vals};
-    (void)nnz;
-    if (validate) validate_csr(n_rows, n_cols, nnz, row_ptr, col_idx);
-    build_host(B, p, vdt, 1, &n_rows, &n_cols, rps, cols, vs, vals_dtype, false, false, false);
-    const HostLayout &L = B.L;
-    auto put = [](auto *dst, const auto &v) {
-        if (dst && !v.empty()) memcpy(dst, v.data(), v.size() * sizeof(v[0]));
-    };
-    put(gp, L.gp);
-    put(short_len, L.short_len);
-    put(short_row, L.short_row);
-    put((uint8_t *)slot_val, L.slot_val);
-    put(slot_col, L.slot_col);
-    put(long_row, L.long_row);
-    put(long_ptr, L.long_ptr);
-    put((uint8_t *)long_val, L.long_val);
-    put(long_col, L.long_col);
     ABI_CATCH
 }
 
@@ -726,7 +670,7 @@ rgcsr_status rgcsr_from_csr(int64_t n_rows, int64_t n_cols, int64_t nnz, const i
         P.scratch.st = st;
         device_plan(P, p, n_rows, n_cols, nnz, row_ptr, col_idx, true, st);
         *out = make_device_on_device(P, p, o.value_dtype, row_ptr, col_idx, vals, vals_dtype, o.keep_csr_map != 0, st,
-                                     o.rows_per_lane, o.pad_loads, o.load_policy);
+                                     o.rows_per_lane, o.pad_loads, o.load_policy, o.tile_min_len);
         return RGCSR_OK;
     }
     if (inputs_on_device) {
@@ -750,10 +694,11 @@ rgcsr_status rgcsr_from_csr(int64_t n_rows, int64_t n_cols, int64_t nnz, const i
     const bool keep = o.keep_csr_map != 0, tr = o.build_transpose != 0;
     build_host(B, p, o.value_dtype, 1, &n_rows, &n_cols, &rp, &col, &val, vals_dtype, o.validate != 0, keep, tr);
     rgcsr_matrix_s *h = make_device(B.L, (keep || tr) ? &B.row_ptr : nullptr, nullptr, st, o.rows_per_lane,
-                                    o.pad_loads, o.load_policy);
+                                    o.pad_loads, o.load_policy, o.tile_min_len);
     if (tr) {
         try {
-            h->AT = make_device(B.LT, nullptr, &B.LTmap, st, o.rows_per_lane, o.pad_loads, o.load_policy);
+            h->AT = make_device(B.LT, nullptr, &B.LTmap, st, o.rows_per_lane, o.pad_loads, o.load_policy,
+                                o.tile_min_len);
         } catch (...) {
             free_handle(h);
             throw;
@@ -783,8 +728,11 @@ rgcsr_status rgcsr_plan_from_csr(int64_t n_rows, int64_t n_cols, int64_t nnz, co
     const bool tr = o.build_transpose != 0;
     build_host(P->B, p, o.value_dtype, 1, &n_rows, &n_cols, &row_ptr, &col_idx, &vals, vals_dtype, o.validate != 0,
                o.keep_csr_map != 0, tr);
-    P->h = prepare_handle(P->B.L, P->with_row_ptr, nullptr, P->a, o.rows_per_lane, o.pad_loads, o.load_policy);
-    if (tr) P->hT = prepare_handle(P->B.LT, false, &P->B.LTmap, P->aT, o.rows_per_lane, o.pad_loads, o.load_policy);
+    P->h = prepare_handle(P->B.L, P->with_row_ptr, nullptr, P->a, o.rows_per_lane, o.pad_loads, o.load_policy,
+                          o.tile_min_len);
+    if (tr)
+        P->hT = prepare_handle(P->B.LT, false, &P->B.LTmap, P->aT, o.rows_per_lane, o.pad_loads, o.load_policy,
+                               o.tile_min_len);
     *out = P.release();
     ABI_CATCH
 }
@@ -860,10 +808,11 @@ rgcsr_status rgcsr_from_csr_batch(int32_t count, const int64_t *n_rows, const in
     build_host(B, p, o.value_dtype, count, n_rows, n_cols, row_ptr, col_idx, vals, vals_dtype, o.validate != 0,
                keep, tr);
     rgcsr_matrix_s *h = make_device(B.L, (keep || tr) ? &B.row_ptr : nullptr, nullptr, st, o.rows_per_lane,
-                                    o.pad_loads, o.load_policy);
+                                    o.pad_loads, o.load_policy, o.tile_min_len);
     if (tr) {
         try {
-            h->AT = make_device(B.LT, nullptr, &B.LTmap, st, o.rows_per_lane, o.pad_loads, o.load_policy);
+            h->AT = make_device(B.LT, nullptr, &B.LTmap, st, o.rows_per_lane, o.pad_loads, o.load_policy,
+                                o.tile_min_len);
         } catch (...) {
             free_handle(h);
             throw;
@@ -979,10 +928,16 @@ rgcsr_status rgcsr_set_values(rgcsr_handle A, const void *vals, rgcsr_dtype vals
             hipError_t e = launch_setval(P, A->vdt, A->prm.T, theta, theta_f64, A->row_ptr, st);
             if (e != hipSuccess) fail(RGCSR_EHIP, std::string("set_values: ") + hipGetErrorString(e));
         }
+        if (A->n_tent) {
+            hipError_t e = launch_tile_values(A->n_tent, A->tile_src, A->long_val, A->tile_val, A->esz, st);
+            if (e != hipSuccess) fail(RGCSR_EHIP, std::string("set_values (tiles): ") + hipGetErrorString(e));
+        }
         if (A->AT) {
             hipError_t e = launch_gather_map(A->AT->slots, A->vdt, A->AT->t_map_slot, theta, theta_f64, A->AT->slot_val, st);
             if (e == hipSuccess)
                 e = launch_gather_map(A->AT->long_nnz, A->vdt, A->AT->t_map_long, theta, theta_f64, A->AT->long_val, st);
+            if (e == hipSuccess && A->AT->n_tent)
+                e = launch_tile_values(A->AT->n_tent, A->AT->tile_src, A->AT->long_val, A->AT->tile_val, A->esz, st);
             if (e != hipSuccess) fail(RGCSR_EHIP, std::string("set_values (transpose): ") + hipGetErrorString(e));
         }
         if (tmp) {
@@ -1084,6 +1039,10 @@ rgcsr_status rgcsr_info(rgcsr_handle A, rgcsr_info_t *out) {
     out->rows_per_lane = A->R;
     out->pad_loads = A->pad;
     out->load_policy = A->lp;
+    out->device_bytes += (int64_t)A->tile_bytes + (A->AT ? (int64_t)A->AT->tile_bytes : 0);
+    out->tiled_rows = A->n_trows;
+    out->tile_entries = A->n_tent;
+    out->n_tiles = A->n_tiles;
     ABI_CATCH
 }
 
@@ -1091,11 +1050,14 @@ rgcsr_status rgcsr_info(rgcsr_handle A, rgcsr_info_t *out) {
 
 namespace {
 
-// Rebase every device pointer of a copied struct from one arena to another.
-template <class H, class... P> void rebase(H *dst, const H *src, P H::*...members) {
+// Rebase every device pointer of a copied struct from one block (the member
+// `block` of src) to the same member of dst.
+template <class H, class... P> void rebase(H *dst, const H *src, void *H::*block, P H::*...members) {
     auto fix = [&](auto H::*m) {
         auto &p = dst->*m;
-        if (p) p = (std::remove_reference_t<decltype(p)>)((char *)dst->mem + ((const char *)(src->*m) - (const char *)src->mem));
+        if (p)
+            p = (std::remove_reference_t<decltype(p)>)((char *)(dst->*block) +
+                                                         ((const char *)(src->*m) - (const char *)(src->*block)));
     };
     (fix(members), ...);
 }
@@ -1105,10 +1067,12 @@ rgcsr_matrix_s *clone_handle(const rgcsr_matrix_s *A, hipStream_t st) {
     h->mem = nullptr;
     h->owns_mem = true;
     h->AT = nullptr;
+    h->tile_mem = nullptr;
     try {
         if (A->bytes) HIPCHK(hipMalloc(&h->mem, A->bytes));
         if (A->bytes) HIPCHK(hipMemcpyAsync(h->mem, A->mem, A->bytes, hipMemcpyDeviceToDevice, st));
-        rebase(h, A, &rgcsr_matrix_s::gp, &rgcsr_matrix_s::gend, &rgcsr_matrix_s::grp_row0, &rgcsr_matrix_s::short_len,
+        rebase(h, A, &rgcsr_matrix_s::mem, &rgcsr_matrix_s::gp, &rgcsr_matrix_s::gend, &rgcsr_matrix_s::grp_row0,
+               &rgcsr_matrix_s::short_len,
                &rgcsr_matrix_s::short_row, &rgcsr_matrix_s::slot_col, &rgcsr_matrix_s::slot_val,
                &rgcsr_matrix_s::short_items, &rgcsr_matrix_s::wave_work, &rgcsr_matrix_s::block_work,
                &rgcsr_matrix_s::combine,
@@ -1116,6 +1080,21 @@ rgcsr_matrix_s *clone_handle(const rgcsr_matrix_s *A, hipStream_t st) {
                &rgcsr_matrix_s::long_ptr, &rgcsr_matrix_s::long_val, &rgcsr_matrix_s::partial,
                &rgcsr_matrix_s::row_ptr, &rgcsr_matrix_s::t_map_slot,
                &rgcsr_matrix_s::t_map_long);
+        // tile arrays: in the same block, or in a block of their own
+        auto tile_rebase = [&](void *rgcsr_matrix_s::*block) {
+            rebase(h, A, block, &rgcsr_matrix_s::tile_units, &rgcsr_matrix_s::tile_ptr, &rgcsr_matrix_s::tile_src,
+                   &rgcsr_matrix_s::tile_orow, &rgcsr_matrix_s::tile_lcol, &rgcsr_matrix_s::tile_val,
+                   &rgcsr_matrix_s::tile_partial, &rgcsr_matrix_s::rest_wave, &rgcsr_matrix_s::rest_block,
+                   &rgcsr_matrix_s::rest_combine);
+        };
+        if (A->tile_mem) {
+            h->tile_mem = nullptr;
+            HIPCHK(hipMalloc(&h->tile_mem, A->tile_bytes));
+            HIPCHK(hipMemcpyAsync(h->tile_mem, A->tile_mem, A->tile_bytes, hipMemcpyDeviceToDevice, st));
+            tile_rebase(&rgcsr_matrix_s::tile_mem);
+        } else {
+            tile_rebase(&rgcsr_matrix_s::mem);
+        }
         if (A->AT) h->AT = clone_handle(A->AT, st);
         HIPCHK(hipStreamSynchronize(st));
     } catch (...) {
@@ -1148,14 +1127,6 @@ rgcsr_status rgcsr_destroy(rgcsr_handle A) {
 // ---------------------------------------------------------------------------
 // Hybrid
 // ---------------------------------------------------------------------------
-rgcsr_status hyb_choose_width(int64_t n_rows, const int64_t *row_ptr, rgcsr_dtype value_dtype, int64_t *k1) {
-    ABI_TRY
-    if (!row_ptr || !k1 || n_rows < 0) fail(RGCSR_EINVAL, "bad argument");
-    check_dtype(value_dtype, "value_dtype");
-    *k1 = hyb_width_rule(n_rows, row_ptr, dtype_size(value_dtype));
-    ABI_CATCH
-}
-
 rgcsr_status hyb_from_csr(int64_t n_rows, int64_t n_cols, int64_t nnz, const int64_t *row_ptr,
                           const int32_t *col_idx, const void *vals, rgcsr_dtype vals_dtype, rgcsr_dtype value_dtype,
                           int64_t ell_width, int validate, void *stream, hyb_handle *out) {
@@ -1271,7 +1242,7 @@ rgcsr_status hyb_clone(hyb_handle A, void *stream, hyb_handle *out) {
     try {
         if (A->bytes) HIPCHK(hipMalloc(&h->mem, A->bytes));
         if (A->bytes) HIPCHK(hipMemcpyAsync(h->mem, A->mem, A->bytes, hipMemcpyDeviceToDevice, st));
-        rebase(h, A, &hyb_matrix_s::ell_col, &hyb_matrix_s::coo_row, &hyb_matrix_s::coo_col,
+        rebase(h, A, &hyb_matrix_s::mem, &hyb_matrix_s::ell_col, &hyb_matrix_s::coo_row, &hyb_matrix_s::coo_col,
                &hyb_matrix_s::ell_val, &hyb_matrix_s::coo_val);
         HIPCHK(hipStreamSynchronize(st));
     } catch (...) {

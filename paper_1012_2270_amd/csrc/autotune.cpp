@@ -212,10 +212,10 @@ template <class F> rgcsr_status guarded(F f) {
         set_last_error(e.msg);
         return e.st;
     } catch (const std::bad_alloc &) {
-        set_last_error("host allocation failed");
+        set_last_error_static("host allocation failed");
         return RGCSR_ENOMEM;
     } catch (...) {
-        set_last_error("unexpected internal error");
+        set_last_error_static("unexpected internal error");
         return RGCSR_EINVAL;
     }
     return RGCSR_OK;

@@ -317,6 +317,54 @@ void transpose_csr(int64_t n_rows, int64_t n_cols, const int64_t *rp, const int3
         }
 }
 
+void check_dtype(int dt, const char *what) {
+    if (dtype_size(dt) == 0) fail(RGCSR_EINVAL, std::string("bad dtype for ") + what);
+}
+
+void build_host(Built &B, const LayoutParams &p, int vdt, int32_t count, const int64_t *n_rows,
+                const int64_t *n_cols, const int64_t *const *rp, const int32_t *const *col,
+                const void *const *vals, int vals_dt, bool validate, bool keep_map, bool transpose) {
+    const int esz = dtype_size(vdt);
+    B.L.G = p.G; B.L.T = p.T; B.L.sigma = p.sigma; B.L.tau = p.tau; B.L.vdt = vdt; B.L.esz = esz;
+    B.has_T = transpose;
+    if (transpose) {
+        B.LT = B.L;
+        B.LTmap = B.L;
+        B.LTmap.esz = 4;
+    }
+    if (keep_map || transpose) B.row_ptr.assign(1, 0);
+    int64_t nnz_base = 0;
+    std::vector<uint8_t> conv;
+    for (int32_t m = 0; m < count; m++) {
+        const int64_t nr = n_rows[m], nc = n_cols[m];
+        if (nr < 0 || nc < 0) fail(RGCSR_EINVAL, "negative matrix size");
+        if (!rp[m]) fail(RGCSR_EINVAL, "row_ptr is null");
+        const int64_t nnz = rp[m][nr];
+        if (validate) validate_csr(nr, nc, nnz, rp[m], col[m]);
+        if (nnz > 0 && !vals[m]) fail(RGCSR_EINVAL, "vals is null");
+        conv.resize((size_t)nnz * esz);
+        if (nnz) convert_values(vals[m], vals_dt, conv.data(), vdt, nnz);
+        append_layout(B.L, p, nr, nc, rp[m], col[m], conv.data(), esz, 0);
+        if (!B.row_ptr.empty())
+            for (int64_t r = 0; r < nr; r++) B.row_ptr.push_back(nnz_base + rp[m][r + 1]);
+        if (transpose) {
+            std::vector<int64_t> rpT;
+            std::vector<int32_t> colT, srcT;
+            transpose_csr(nr, nc, rp[m], col[m], rpT, colT, srcT);
+            std::vector<uint8_t> valsT((size_t)nnz * esz);
+            for (int64_t k = 0; k < nnz; k++) memcpy(&valsT[(size_t)k * esz], &conv[(size_t)srcT[k] * esz], esz);
+            std::vector<int32_t> mapT(nnz);
+            if (nnz_base + nnz > INT32_MAX) fail(RGCSR_EOVERFLOW, "transpose map needs total nnz < 2^31");
+            for (int64_t k = 0; k < nnz; k++) mapT[k] = (int32_t)(srcT[k] + nnz_base);
+            append_layout(B.LT, p, nc, nr, rpT.data(), colT.data(), valsT.data(), esz, 0);
+            append_layout(B.LTmap, p, nc, nr, rpT.data(), colT.data(), (const uint8_t *)mapT.data(), 4, 0xff);
+        }
+        nnz_base += nnz;
+    }
+    build_long_work(B.L.long_ptr, B.L.work);
+    if (transpose) build_long_work(B.LT.long_ptr, B.LT.work);
+}
+
 int64_t hyb_width_rule(int64_t n_rows, const int64_t *rp, int s_v) {
     // cost(k) = k * n_pad * (s_v + 4) + 3 * (s_v + 8) * excess(k),
     // excess(k) = sum_i max(0, len_i - k), updated incrementally.

@@ -4,6 +4,7 @@
 
 #include <cstdint>
 #include <cstring>
+#include <new>
 #include <string>
 #include <vector>
 
@@ -26,7 +27,10 @@ struct Error {
     std::string msg;
 };
 [[noreturn]] void fail(rgcsr_status st, const std::string &msg);
-void set_last_error(const std::string &msg);
+// Both never throw: when copying msg fails for lack of memory, the message
+// becomes a fixed string.  The second keeps a pointer to a string literal.
+void set_last_error(const std::string &msg) noexcept;
+void set_last_error_static(const char *msg) noexcept;
 
 inline int dtype_size(int dt) {
     switch (dt) {
@@ -194,4 +198,45 @@ void transpose_csr(int64_t n_rows, int64_t n_cols, const int64_t *rp, const int3
 // Hybrid ELL width rule and arrays.
 int64_t hyb_width_rule(int64_t n_rows, const int64_t *rp, int s_v);
 
+// Throws RGCSR_EINVAL for a dtype code outside rgcsr_dtype.
+void check_dtype(int dt, const char *what);
+
+// Host layout (+ transposed layout) for one or more CSR matrices.
+struct Built {
+    HostLayout L;
+    bool has_T = false;
+    HostLayout LT;       // layout of A^T with values
+    HostLayout LTmap;    // layout of A^T whose "values" are source indices
+    std::vector<int64_t> row_ptr;  // global CSR row pointers
+};
+
+// Host layout of `count` CSR matrices (a block-diagonal batch when count > 1)
+// with values converted to vdt; the CSR row pointers when keep_map or
+// transpose, and the layouts of A^T (values, and source indices) when
+// transpose.  Validates each matrix when validate is set.
+void build_host(Built &B, const LayoutParams &p, int vdt, int32_t count, const int64_t *n_rows,
+                const int64_t *n_cols, const int64_t *const *rp, const int32_t *const *col,
+                const void *const *vals, int vals_dt, bool validate, bool keep_map, bool transpose);
+
 }  // namespace rg
+
+// Every C entry point runs its body between ABI_TRY and ABI_CATCH: internal
+// errors become a status code and the thread-local message, allocation
+// failures RGCSR_ENOMEM, and nothing else escapes.
+#define ABI_TRY try {
+#define ABI_CATCH                                                                                      \
+    }                                                                                                  \
+    catch (const rg::Error &e) {                                                                       \
+        rg::set_last_error(e.msg);                                                                     \
+        return e.st;                                                                                   \
+    }                                                                                                  \
+    catch (const std::bad_alloc &) {                                                                   \
+        rg::set_last_error_static("host allocation failed");                                           \
+        return RGCSR_ENOMEM;                                                                           \
+    }                                                                                                  \
+    catch (...) {                                                                                      \
+        rg::set_last_error_static("unexpected internal error");                                        \
+        return RGCSR_EINVAL;                                                                           \
+    }                                                                                                  \
+    return RGCSR_OK;
+

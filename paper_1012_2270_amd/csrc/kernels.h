@@ -4,6 +4,7 @@
 #include <hip/hip_runtime_api.h>
 
 #include "internal.h"
+#include "tiles.h"
 
 namespace rg {
 
@@ -41,6 +42,12 @@ struct SpmvParams {
     // total_waves - n_long_waves (n_long_waves = long rows)
     int32_t n_long_waves;
     int32_t total_waves;
+    // column-tiled long rows (FP32 vectors, one right-hand side): the tile
+    // kernel has written one partial sum per (tile, tiled row); units
+    // [0, n_comb_units) of the launch add them, 64 rows each
+    const float *tile_partial;   // [n_tiles * n_trows]
+    const int32_t *tile_orow;    // [n_trows] output row of each tiled row
+    int32_t n_comb_units, n_tiles, n_trows;
     // vectors
     const void *x;
     void *y;
@@ -87,6 +94,23 @@ hipError_t launch_stream_read(const void *a, int64_t n16, int32_t *sink, int nb,
 hipError_t launch_gather_floor(const int32_t *col, const float *val, int64_t n, const float *x, float *out,
                                hipStream_t st);
 hipError_t launch_zero(int64_t n, void *a, int esz, int nb, hipStream_t st);
+// Tile kernel: one workgroup per unit, partial[t * n_trows + row] for the
+// rows of every unit.
+struct TileParams {
+    const TileUnit *units;
+    const int32_t *ptr;      // [n_tiles * (n_trows + 1)]
+    const uint16_t *lcol;    // [n_ent] column within the tile
+    const void *val;         // [n_ent] storage dtype
+    const float *x;
+    float *partial;          // [n_tiles * n_trows]
+    int64_t n_cols;
+    int32_t n_trows;
+    int32_t x_aligned;       // x is 16-byte aligned (vector loads of a tile)
+};
+hipError_t launch_tile_spmv(const TileParams &P, int vdt, int n_units, hipStream_t st);
+// tile values <- long-row segment values (after a value update)
+hipError_t launch_tile_values(int64_t n, const int32_t *src, const void *long_val, void *tile_val, int esz,
+                              hipStream_t st);
 
 // Static device workspace of the allocation-free mixed-precision CG
 // (rgcsr_cg_solve_noalloc): FP64 r and q, FP32 r, p, q, d for up to

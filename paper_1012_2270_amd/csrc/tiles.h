@@ -1,0 +1,62 @@
+// Column tiles of the longest rows: x staged in LDS.  Internal.
+//
+// Rows of the long-row segment with at least `min_len` nonzeros are also
+// stored split by column tile (kTileCols columns per tile).  A tile kernel
+// runs first: each workgroup stages a tile of x in LDS with coalesced loads,
+// streams the tile's entries of a range of those rows, multiplies them
+// against x read from LDS and writes one partial sum per (row, tile).  The
+// SpMV kernel that follows adds each row's partial sums in a fixed order
+// (its first units), beside its other work.  The random x gathers of these rows thus move
+// from the L2/Infinity-Cache path into LDS (the paper's texture-cache study,
+// Section 4.3, asks where x is kept; its Table 6 shows the long rows as the
+// case the row-grouped kernel handles worst).
+#pragma once
+
+#include <cstdint>
+#include <vector>
+
+#include "internal.h"
+
+namespace rg {
+
+constexpr int kTileCols = 8192;      // x columns per tile: 32 KB of FP32 in LDS
+constexpr int kTileUnitMax = 8192;   // entries per unit: 32 KB of FP32 products in LDS
+constexpr int kTileThreads = 512;    // one workgroup per unit, two per CU
+constexpr int kTilePasses = 4;       // passes over a unit's rows (512 / lanes rows per pass)
+constexpr int kTileLaneSteps = 16;   // products a lane adds per row segment, at most
+constexpr int64_t kTileMinEntries = int64_t(1) << 18;  // automatic choice: tile only this many entries or more
+
+// One unit of the tile kernel (a workgroup): tile t, tiled rows [r0, r1),
+// `lanes` lanes per row (a power of two, at most 64, so that no lane adds
+// more than kTileLaneSteps products of a segment, and the rows fit
+// kTilePasses passes); t < 0 marks an empty unit.
+struct TileUnit {
+    int32_t t, r0, r1, lanes;
+};
+
+struct HostTiles {
+    int64_t n_tiles = 0, n_trows = 0, n_ent = 0;
+    int64_t min_len = 0;               // threshold that selected the rows
+    std::vector<int32_t> trow;         // [n_trows] long-list index of each tiled row
+    std::vector<int32_t> ptr;          // [n_tiles * (n_trows + 1)] first entry of (tile, row)
+    std::vector<uint16_t> lcol;        // [n_ent] column - tile * kTileCols
+    std::vector<int32_t> src;          // [n_ent] position of the entry in the long-row segment
+    std::vector<TileUnit> units;
+    std::vector<uint8_t> tiled;        // [nl] 1 when long row i is tiled
+    LongWork rest;                     // long-row work of the rows that are not tiled
+    bool active() const { return n_trows > 0; }
+};
+
+// Selects the tiled rows of layout L (long rows of at least
+// max(min_len, tiles / 2) nonzeros, so the partial sums never outnumber the
+// entries twice over;
+// min_len < 0 picks 256 and keeps the tiles only when they hold at least
+// kTileMinEntries entries; 0 disables) and builds their index arrays and
+// units (values are copied on the device through src).  Needs L.long_ptr and
+// L.long_col.
+void build_tiles(const HostLayout &L, int64_t min_len, HostTiles &T);
+
+// Long-row work items of the rows not tiled (the tiled ones skipped).
+void build_long_work_except(const std::vector<int64_t> &long_ptr, const std::vector<uint8_t> &skip, LongWork &W);
+
+}  // namespace rg

@@ -199,7 +199,9 @@ def test_sliced_ellpack_mode(torch_cuda, oracle, G, T, sigma, tau):
 
 def test_load_policies_same_result(torch_cuda, oracle):
     """Cached streams (1) and nontemporal x (2) change only cache hints: the
-    bits equal the default policy's; unsupported combinations are errors."""
+    bits equal the default policy's; unsupported combinations are errors.
+    (The column-tiled long rows run with policy 0 only, so they are off here:
+    with them the default policy sums those rows in another order.)"""
     torch = torch_cuda
     A = W.zipf_matrix(120_000, seed=10)
     x = W.uniform_vector(A.n_cols, 18, np.float32)
@@ -207,7 +209,7 @@ def test_load_policies_same_result(torch_cuda, oracle):
     for lay in (dict(sigma=1, tau=-1), dict(sigma=512, tau=16)):
         for lp in (0, 1, 2):
             say("load policy", lay, lp)
-            M = rg.rgcsr_from_csr(A, G=64, load_policy=lp, **lay)
+            M = rg.rgcsr_from_csr(A, G=64, load_policy=lp, tile_min_len=0, **lay)
             assert M.info["load_policy"] == lp
             y = host(M.spmv(dev(x)))
             M.close()
