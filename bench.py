@@ -49,10 +49,20 @@ def alg_bytes(nnz, n_rows, n_cols, groups, s_v=4, s_x=4, s_y=4, k=1):
 
 def kernel_source_hash() -> str:
     h = hashlib.sha256()
-    for f in ("kernels.hip", "kernels.h", "internal.h"):
+    for f in ("kernels.hip", "kernels.h", "internal.h", "tiles.hip", "tiles.h"):
         with open(os.path.join(ROOT, "paper_1012_2270_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
+
+
+def traffic_kernels(kernel_key: str):
+    """The kernels one SpMV of this case launches, as the counter summary
+    names them (a list when the column-tiled rows add the tile kernel)."""
+    try:
+        with open(os.path.join(ROOT, "profiles", "traffic.json")) as f:
+            return json.load(f).get(kernel_key, {}).get("kernel")
+    except (OSError, ValueError):
+        return None
 
 
 def traffic_record(kernel_key: str):
@@ -849,6 +859,7 @@ def main():
     t_dom = per_launch[dom] * 1e-3
     achieved = dc.bytes / t_dom / 1e9
     tr = traffic_record(dc.name)
+    tr_kernels = traffic_kernels(dc.name)
     out = {
         "metric": METRIC,
         "value": value,
@@ -867,7 +878,9 @@ def main():
                    "matrices": [c.name for c in cases], "parallelism": "single GPU"},
         "hbm_gbs": sum(c.bytes for c in cases) * K / (total_ms * 1e-3) / 1e9,
         "hbm_frac": sum(c.bytes for c in cases) * K / (total_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
-        "roofline": {"bound": "hbm", "kernel": dc.name, "achieved": achieved, "peak": HBM_PEAK_GBS,
+        "roofline": {"bound": "hbm", "kernel": dc.name,
+                     "kernels": (tr_kernels if tr_kernels else None),
+                     "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "traffic": tr,
                      "alg_bytes_per_launch": dc.bytes, "avg_launch_us": t_dom * 1e6,
