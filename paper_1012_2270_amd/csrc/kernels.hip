@@ -250,7 +250,7 @@ template <int LP, class A> __device__ __forceinline__ A ldx32(const A *X, int32_
 // repeats the row's last column, so a step is multiplied exactly when its
 // column exceeds the previous step's (one lane per row, no empty rows; the
 // host checks both).
-template <int VD, class A, int K, int T, int R, int PAD, int LP>
+template <int VD, class A, int K, int T, int R, int PAD, int LP, int SB>
 __device__ __forceinline__ void spmv_groups_uniform(const SpmvParams &P, int32_t first, int lane) {
     using V = Val<VD>;
     using S = typename V::S;
@@ -307,7 +307,9 @@ __device__ __forceinline__ void spmv_groups_uniform(const SpmvParams &P, int32_t
     for (int r = 0; r < R; r++)
 #pragma unroll
         for (int k = 0; k < K; k++) acc[r][k] = A(0);
-    constexpr int U = K == 1 ? 16 / R : unroll_for<K>();
+    // steps per pass: SB / R (the host's rows-per-lane choice uses the same
+    // step budget)
+    constexpr int U = K == 1 ? SB / R : unroll_for<K>();
     // Inside the unrolled body every load is issued unconditionally (steps past
     // the bound read the group's first slot and x[0], in bounds whenever the
     // loop runs) and results are masked with selects, so the loads of a phase
@@ -424,13 +426,13 @@ __device__ __forceinline__ void spmv_groups_lane(const SpmvParams &P, int32_t w,
     }
 }
 
-template <int VD, class A, int K, int T, int R, int LP>
+template <int VD, class A, int K, int T, int R, int LP, int SB>
 __device__ __forceinline__ void spmv_groups_fixed(const SpmvParams &P, int32_t first, int lane) {
     if (P.pad == 3) {
-        if constexpr (T == 1) spmv_groups_uniform<VD, A, K, T, R, 3, LP>(P, first, lane);
-    } else if (P.pad == 2) spmv_groups_uniform<VD, A, K, T, R, 2, LP>(P, first, lane);
-    else if (P.pad) spmv_groups_uniform<VD, A, K, T, R, 1, LP>(P, first, lane);
-    else spmv_groups_uniform<VD, A, K, T, R, 0, LP>(P, first, lane);
+        if constexpr (T == 1) spmv_groups_uniform<VD, A, K, T, R, 3, LP, SB>(P, first, lane);
+    } else if (P.pad == 2) spmv_groups_uniform<VD, A, K, T, R, 2, LP, SB>(P, first, lane);
+    else if (P.pad) spmv_groups_uniform<VD, A, K, T, R, 1, LP, SB>(P, first, lane);
+    else spmv_groups_uniform<VD, A, K, T, R, 0, LP, SB>(P, first, lane);
 }
 
 // R > 0: every wavefront takes R consecutive wave items.  R = 0: wavefront w
@@ -443,13 +445,16 @@ __device__ __forceinline__ void spmv_short(const SpmvParams &P, int32_t w, int l
         const int32_t it = ldc(P.short_items, w);
         const int32_t first = it >> 2;
         switch (it & 3) {
-            case 0: spmv_groups_fixed<VD, A, K, T, 1, LP>(P, first, lane); break;
-            case 1: spmv_groups_fixed<VD, A, K, T, 2, LP>(P, first, lane); break;
-            case 2: spmv_groups_fixed<VD, A, K, T, 4, LP>(P, first, lane); break;
-            default: spmv_groups_fixed<VD, A, K, T, 8, LP>(P, first, lane); break;
+            case 0: spmv_groups_fixed<VD, A, K, T, 1, LP, kLaneSteps>(P, first, lane); break;
+            case 1: spmv_groups_fixed<VD, A, K, T, 2, LP, kLaneSteps>(P, first, lane); break;
+            case 2: spmv_groups_fixed<VD, A, K, T, 4, LP, kLaneSteps>(P, first, lane); break;
+            default: spmv_groups_fixed<VD, A, K, T, 8, LP, kLaneSteps>(P, first, lane); break;
         }
     } else if (P.wpg > 0) {
-        spmv_groups_fixed<VD, A, K, T, R, LP>(P, w * R, lane);
+        // one rows-per-lane count for every wavefront (uniform widths): 8-byte
+        // values take half the step budget, whose loads and x gathers need
+        // twice the registers
+        spmv_groups_fixed<VD, A, K, T, R, LP, VD == RGCSR_F64 ? kLaneSteps / 2 : kLaneSteps>(P, w * R, lane);
     } else if constexpr (R == 1) {
         spmv_groups_lane<VD, A, K, T, LP>(P, w, lane);
     }
@@ -976,14 +981,34 @@ __global__ __launch_bounds__(256) void hyb_coo_k(int64_t m, const int32_t *crow,
     const int64_t e0 = base + (int64_t)lane * 8;
     S v[8];
     int32_t r[8], c[8];
+    if (e0 + 8 <= m) {
+        // a lane's 8 consecutive entries as 16-byte loads (the arrays are
+        // 256-byte aligned and e0 is a multiple of 8), so each load
+        // instruction of the wavefront covers whole cache lines once
+        i32x4 rv[2], cw[2];
+        i32x4 vv[(8 * sizeof(S)) / 16];
 #pragma unroll
-    for (int u = 0; u < 8; u++) {
-        const int64_t e = e0 + u;
-        r[u] = -1;
-        if (e < m) {
-            r[u] = ldnt(crow + e);
-            c[u] = ldnt(ccol + e);
-            v[u] = ldnt(cv + e);
+        for (int h = 0; h < 2; h++) {
+            rv[h] = ldnt(reinterpret_cast<const i32x4 *>(crow + e0) + h);
+            cw[h] = ldnt(reinterpret_cast<const i32x4 *>(ccol + e0) + h);
+        }
+#pragma unroll
+        for (int h = 0; h < (int)((8 * sizeof(S)) / 16); h++) vv[h] = ldnt(reinterpret_cast<const i32x4 *>(cv + e0) + h);
+        __builtin_memcpy(r, rv, sizeof(r));
+        __builtin_memcpy(c, cw, sizeof(c));
+        __builtin_memcpy(v, vv, sizeof(v));
+    } else {
+#pragma unroll
+        for (int u = 0; u < 8; u++) {
+            const int64_t e = e0 + u;
+            r[u] = -1;
+            c[u] = 0;
+            v[u] = S(0);
+            if (e < m) {
+                r[u] = ldnt(crow + e);
+                c[u] = ldnt(ccol + e);
+                v[u] = ldnt(cv + e);
+            }
         }
     }
     A p[8];
