@@ -117,7 +117,7 @@ struct rgcsr_matrix_s {
     int64_t n_tiles = 0, n_trows = 0, n_tent = 0, n_tunits = 0;
     int64_t n_rest_wave = 0, n_rest_block = 0, n_rest_combine = 0;
     TileUnit *tile_units = nullptr;
-    int32_t *tile_ptr = nullptr, *tile_src = nullptr, *tile_orow = nullptr;
+    int32_t *tile_ptr = nullptr, *tile_dst = nullptr, *tile_orow = nullptr;
     uint16_t *tile_lcol = nullptr;
     void *tile_val = nullptr;
     float *tile_partial = nullptr;
@@ -266,7 +266,7 @@ void add_tile_arrays(rgcsr_matrix_s *h, const HostTiles &T, Arena &a) {
     a.add(&h->tile_ptr, T.ptr.size());
     a.add(&h->tile_lcol, (size_t)T.n_ent);
     a.add((uint8_t **)&h->tile_val, (size_t)T.n_ent * h->esz);
-    a.add(&h->tile_src, (size_t)T.n_ent);
+    a.add(&h->tile_dst, T.dst.size());
     a.add(&h->tile_orow, (size_t)T.n_trows);
     a.add(&h->tile_partial, (size_t)(T.n_tiles * T.n_trows));
     a.add(&h->rest_wave, T.rest.wave.size());
@@ -281,14 +281,14 @@ void upload_tiles(rgcsr_matrix_s *h, const HostTiles &T, const std::vector<int32
     upload(h->tile_units, T.units, st);
     upload(h->tile_ptr, T.ptr, st);
     upload(h->tile_lcol, T.lcol, st);
-    upload(h->tile_src, T.src, st);
+    upload(h->tile_dst, T.dst, st);
     std::vector<int32_t> orow(T.n_trows);
     for (int64_t k = 0; k < T.n_trows; k++) orow[k] = long_row[T.trow[k]];
     upload(h->tile_orow, orow, st);
     upload(h->rest_wave, T.rest.wave, st);
     upload(h->rest_block, T.rest.block, st);
     upload(h->rest_combine, T.rest.combine, st);
-    HIPCHK(launch_tile_values(T.n_ent, h->tile_src, h->long_val, h->tile_val, h->esz, st));
+    HIPCHK(launch_tile_values((int64_t)T.dst.size(), h->tile_dst, h->long_val, h->tile_val, h->esz, st));
     // orow is a host temporary: wait for its copy
     HIPCHK(hipStreamSynchronize(st));
 }
@@ -545,6 +545,8 @@ SpmvParams params_of(const rgcsr_matrix_s *h, bool use_rows, bool tiled = false)
     P.wave_work = h->wave_work; P.block_work = h->block_work;
     P.long_row = h->long_row; P.long_ptr = h->long_ptr; P.long_val = h->long_val;
     P.long_col = h->long_col; P.partial = h->partial;
+    P.tile_dst = h->n_tent ? h->tile_dst : nullptr;
+    P.tile_vals = h->n_tent ? h->tile_val : nullptr;
     int64_t n_block = h->n_block, n_wave_long = h->n_wave_long, n_comb = 0;
     if (tiled) {
         P.wave_work = h->rest_wave;
@@ -942,16 +944,12 @@ rgcsr_status rgcsr_set_values(rgcsr_handle A, const void *vals, rgcsr_dtype vals
             hipError_t e = launch_setval(P, A->vdt, A->prm.T, theta, theta_f64, A->row_ptr, st);
             if (e != hipSuccess) fail(RGCSR_EHIP, std::string("set_values: ") + hipGetErrorString(e));
         }
-        if (A->n_tent) {
-            hipError_t e = launch_tile_values(A->n_tent, A->tile_src, A->long_val, A->tile_val, A->esz, st);
-            if (e != hipSuccess) fail(RGCSR_EHIP, std::string("set_values (tiles): ") + hipGetErrorString(e));
-        }
         if (A->AT) {
             hipError_t e = launch_gather_map(A->AT->slots, A->vdt, A->AT->t_map_slot, theta, theta_f64, A->AT->slot_val, st);
             if (e == hipSuccess)
                 e = launch_gather_map(A->AT->long_nnz, A->vdt, A->AT->t_map_long, theta, theta_f64, A->AT->long_val, st);
             if (e == hipSuccess && A->AT->n_tent)
-                e = launch_tile_values(A->AT->n_tent, A->AT->tile_src, A->AT->long_val, A->AT->tile_val, A->esz, st);
+                e = launch_tile_values(A->AT->long_nnz, A->AT->tile_dst, A->AT->long_val, A->AT->tile_val, A->esz, st);
             if (e != hipSuccess) fail(RGCSR_EHIP, std::string("set_values (transpose): ") + hipGetErrorString(e));
         }
         if (tmp) {
@@ -1096,7 +1094,7 @@ rgcsr_matrix_s *clone_handle(const rgcsr_matrix_s *A, hipStream_t st) {
                &rgcsr_matrix_s::t_map_long);
         // tile arrays: in the same block, or in a block of their own
         auto tile_rebase = [&](void *rgcsr_matrix_s::*block) {
-            rebase(h, A, block, &rgcsr_matrix_s::tile_units, &rgcsr_matrix_s::tile_ptr, &rgcsr_matrix_s::tile_src,
+            rebase(h, A, block, &rgcsr_matrix_s::tile_units, &rgcsr_matrix_s::tile_ptr, &rgcsr_matrix_s::tile_dst,
                    &rgcsr_matrix_s::tile_orow, &rgcsr_matrix_s::tile_lcol, &rgcsr_matrix_s::tile_val,
                    &rgcsr_matrix_s::tile_partial, &rgcsr_matrix_s::rest_wave, &rgcsr_matrix_s::rest_block,
                    &rgcsr_matrix_s::rest_combine);

@@ -48,6 +48,10 @@ struct SpmvParams {
     const float *tile_partial;   // [n_tiles * n_trows]
     const int32_t *tile_orow;    // [n_trows] output row of each tiled row
     int32_t n_comb_units, n_tiles, n_trows;
+    // value updates: position of each long-row element in the tiled copy
+    // (-1 when its row is not tiled) and the tiled values; null without tiles
+    const int32_t *tile_dst;     // [long_nnz]
+    void *tile_vals;             // [tile entries] storage dtype
     // vectors
     const void *x;
     void *y;
@@ -108,8 +112,9 @@ struct TileParams {
     int32_t x_aligned;       // x is 16-byte aligned (vector loads of a tile)
 };
 hipError_t launch_tile_spmv(const TileParams &P, int vdt, int n_units, hipStream_t st);
-// tile values <- long-row segment values (after a value update)
-hipError_t launch_tile_values(int64_t n, const int32_t *src, const void *long_val, void *tile_val, int esz,
+// tile_val[dst[q]] = long_val[q] for the n long-row elements whose row is
+// tiled (dst[q] >= 0)
+hipError_t launch_tile_values(int64_t n, const int32_t *dst, const void *long_val, void *tile_val, int esz,
                               hipStream_t st);
 
 // Static device workspace of the allocation-free mixed-precision CG

@@ -747,16 +747,28 @@ __device__ __forceinline__ typename Val<VD>::S to_store(SRC v) {
 // Value update over the SpMV work split (workgroup chunks of the longest
 // rows, wavefront items of long rows, then row groups one row per lane); each
 // lane loads up to U source values before it stores them.
+// tdst (nullable): position of each element in the column-tiled copy of the
+// long rows, -1 when its row is not tiled; tv: the tiled values.
 template <int VD, class SRC, int U>
 __device__ __forceinline__ void copy_elems(const SRC *src, typename Val<VD>::S *dst, int32_t o, int32_t e,
-                                           int32_t stride) {
+                                           int32_t stride, const int32_t *tdst = nullptr,
+                                           typename Val<VD>::S *tv = nullptr) {
     for (int32_t o0 = o; o0 < e; o0 += stride * U) {
         SRC t[U];
+        int32_t d[U];
 #pragma unroll
-        for (int u = 0; u < U; u++) t[u] = src[o0 + u * stride < e ? o0 + u * stride : o];
+        for (int u = 0; u < U; u++) {
+            const int32_t i = o0 + u * stride < e ? o0 + u * stride : o;
+            t[u] = src[i];
+            d[u] = tdst ? tdst[i] : -1;
+        }
 #pragma unroll
         for (int u = 0; u < U; u++)
-            if (o0 + u * stride < e) dst[o0 + u * stride] = to_store<VD>(t[u]);
+            if (o0 + u * stride < e) {
+                const typename Val<VD>::S v = to_store<VD>(t[u]);
+                dst[o0 + u * stride] = v;
+                if (d[u] >= 0) tv[d[u]] = v;
+            }
     }
 }
 
@@ -774,7 +786,7 @@ __global__ __launch_bounds__(256) void setval_k(SpmvParams P, const SRC *theta, 
         const int32_t n = (int32_t)min(ldc(P.long_ptr, li + 1) - beg, kBlockChunk);
         const int64_t row = ldc(P.long_row, li);
         copy_elems<VD, SRC, 16>(theta + (row_ptr[row] + (beg - lb)), lv + beg, (int32_t)threadIdx.x, n,
-                                kBlockThreads);
+                                kBlockThreads, P.tile_dst ? P.tile_dst + beg : nullptr, (S *)P.tile_vals);
         return;
     }
     const int32_t w = __builtin_amdgcn_readfirstlane((u - P.n_block_items) * 4 + (int)(threadIdx.x >> 6));
@@ -788,7 +800,8 @@ __global__ __launch_bounds__(256) void setval_k(SpmvParams P, const SRC *theta, 
         const int64_t beg = P.long_ptr[li];
         const int32_t n = (int32_t)(P.long_ptr[li + 1] - beg);
         const int64_t row = P.long_row[li];
-        copy_elems<VD, SRC, kWaveUnroll>(theta + row_ptr[row], lv + beg, q, n, TL);
+        copy_elems<VD, SRC, kWaveUnroll>(theta + row_ptr[row], lv + beg, q, n, TL,
+                                         P.tile_dst ? P.tile_dst + beg : nullptr, (S *)P.tile_vals);
         return;
     }
     const int32_t ws = w - P.n_wave_long;

@@ -69,7 +69,7 @@ void build_tiles(const HostLayout &L, int64_t min_len, HostTiles &T) {
         T.trow.push_back((int32_t)i);
         n_ent += len;
     }
-    if (T.trow.empty() || (automatic && n_ent < kTileMinEntries) || n_ent > INT32_MAX ||
+    if (T.trow.empty() || (automatic && n_ent < kTileMinEntries) || n_ent > INT32_MAX || L.long_nnz > INT32_MAX ||
         n_tiles * ((int64_t)T.trow.size() + 1) > INT32_MAX) {
         T = HostTiles{};
         return;
@@ -96,6 +96,7 @@ void build_tiles(const HostLayout &L, int64_t min_len, HostTiles &T) {
     }
     T.lcol.resize(n_ent);
     T.src.resize(n_ent);
+    T.dst.assign((size_t)L.long_nnz, -1);
     std::vector<int32_t> fill(T.ptr);
     for (int64_t k = 0; k < nt; k++) {
         const int64_t i = T.trow[k];
@@ -104,6 +105,7 @@ void build_tiles(const HostLayout &L, int64_t min_len, HostTiles &T) {
             const int32_t d = fill[t * (nt + 1) + k]++;
             T.lcol[d] = (uint16_t)(L.long_col[q] - t * kTileCols);
             T.src[d] = (int32_t)q;
+            T.dst[q] = d;
         }
     }
     // units: consecutive rows of one tile, at most kTileUnitMax entries; the

@@ -41,6 +41,7 @@ struct HostTiles {
     std::vector<int32_t> ptr;          // [n_tiles * (n_trows + 1)] first entry of (tile, row)
     std::vector<uint16_t> lcol;        // [n_ent] column - tile * kTileCols
     std::vector<int32_t> src;          // [n_ent] position of the entry in the long-row segment
+    std::vector<int32_t> dst;          // [long_nnz] inverse: position in the tiled copy, -1 if not tiled
     std::vector<TileUnit> units;
     std::vector<uint8_t> tiled;        // [nl] 1 when long row i is tiled
     LongWork rest;                     // long-row work of the rows that are not tiled

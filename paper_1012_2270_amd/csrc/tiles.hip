@@ -113,20 +113,22 @@ hipError_t launch_tile_spmv(const TileParams &P, int vdt, int n_units, hipStream
 }
 
 template <class E>
-__global__ __launch_bounds__(256) void tile_values_k(int64_t n, const int32_t *src, const E *lv, E *tv) {
+__global__ __launch_bounds__(256) void tile_values_k(int64_t n, const int32_t *dst, const E *lv, E *tv) {
     const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (i < n) tv[i] = lv[src[i]];
+    if (i >= n) return;
+    const int32_t d = dst[i];
+    if (d >= 0) tv[d] = lv[i];
 }
 
-hipError_t launch_tile_values(int64_t n, const int32_t *src, const void *long_val, void *tile_val, int esz,
+hipError_t launch_tile_values(int64_t n, const int32_t *dst, const void *long_val, void *tile_val, int esz,
                               hipStream_t st) {
     if (n == 0) return hipSuccess;
     const int nb = (int)((n + 255) / 256);
     if (esz == 4)
-        hipLaunchKernelGGL(tile_values_k<uint32_t>, dim3(nb), dim3(256), 0, st, n, src, (const uint32_t *)long_val,
+        hipLaunchKernelGGL(tile_values_k<uint32_t>, dim3(nb), dim3(256), 0, st, n, dst, (const uint32_t *)long_val,
                            (uint32_t *)tile_val);
     else if (esz == 2)
-        hipLaunchKernelGGL(tile_values_k<uint16_t>, dim3(nb), dim3(256), 0, st, n, src, (const uint16_t *)long_val,
+        hipLaunchKernelGGL(tile_values_k<uint16_t>, dim3(nb), dim3(256), 0, st, n, dst, (const uint16_t *)long_val,
                            (uint16_t *)tile_val);
     else
         return hipErrorInvalidValue;
