@@ -258,41 +258,56 @@ def gather_floor_us(torch, rg, c, reps):
 
 def bench_spmm(args, torch, rg, W):
     """Multi-RHS SpMM on the Zipf matrix, k in {1, 4, 16, 32}, one launch per k,
-    against k sequential single-vector SpMVs."""
+    against k sequential single-vector SpMVs; the same with a handle that also
+    keeps the eight-panel column split (col_panels = 8), which the launches
+    use where a panel's slice of X fits one XCD's L2 (k <= 4 here)."""
     import oracle
     A, _ = W.workload_zipf(1_000_000)
     base = rg.rgcsr_from_csr(A, **LAYOUT_ZIPF)
-    out = {"metric": "SpMM GFLOP/s and GB/s, Zipf n=1e6, FP32", "results": []}
-    for k in (1, 4, 16, 32):
-        X0 = torch.from_numpy(W.uniform_matrix(A.n_cols, k, W.SEEDS["spmm_X"])).to("cuda:0")
-        per = base.info["device_bytes"] + 4 * k * (A.n_rows + A.n_cols)
+    pbase = rg.rgcsr_from_csr(A, col_panels=8, **LAYOUT_ZIPF)
+    out = {"metric": "SpMM GFLOP/s and GB/s, Zipf n=1e6, FP32", "results": [],
+           "panel_pieces": pbase.info["panel_pieces"]}
+
+    def timed(h, k, X0, reps):
+        per = h.info["device_bytes"] + 4 * k * (A.n_rows + A.n_cols)
         copies = max(1, math.ceil(ROTATE_BYTES / per))
-        mats = [base] + [base.clone() for _ in range(copies - 1)]
+        mats = [h] + [h.clone() for _ in range(copies - 1)]
         Xs = [X0.clone() for _ in range(copies)]
         Ys = [torch.empty((A.n_rows, k), device="cuda:0") for _ in range(copies)]
         for i in range(args.warmup):
             rg.rgcsr_spmv_batched(mats[i % copies], Xs[i % copies], Ys[i % copies])
-        t = _mean_launch_ms(torch, lambda i: rg.rgcsr_spmv_batched(mats[i % copies], Xs[i % copies], Ys[i % copies]),
-                    args.steps)
-        ms = float(np.mean(t))
-        xcols = [X0[:, c].contiguous() for c in range(k)]
-        ycol = torch.empty(A.n_rows, device="cuda:0")
-        t1 = _mean_launch_ms(torch, lambda i: [rg.rgcsr_spmv(mats[i % copies], xcols[c], ycol) for c in range(k)],
-                     max(10, args.steps // 4))
+        ms = float(np.mean(_mean_launch_ms(
+            torch, lambda i: rg.rgcsr_spmv_batched(mats[i % copies], Xs[i % copies], Ys[i % copies]), reps)))
         Y = Ys[0]
         rg.rgcsr_spmv_batched(mats[0], Xs[0], Y)
         torch.cuda.synchronize()
+        Yh = Y.cpu().numpy()
+        for m in mats[1:]:
+            m.close()
+        return ms, Yh, copies
+
+    for k in (1, 4, 16, 32):
+        X0 = torch.from_numpy(W.uniform_matrix(A.n_cols, k, W.SEEDS["spmm_X"])).to("cuda:0")
+        ms, Yh, copies = timed(base, k, X0, args.steps)
+        pms, pYh, pcopies = timed(pbase, k, X0, args.steps)
+        xcols = [X0[:, c].contiguous() for c in range(k)]
+        ycol = torch.empty(A.n_rows, device="cuda:0")
+        t1 = _mean_launch_ms(torch, lambda i: [rg.rgcsr_spmv(base, xcols[c], ycol) for c in range(k)],
+                             max(10, args.steps // 4))
         Xh = X0.cpu().numpy()
         ref = oracle.csr_spmm(A, Xh)
-        err = max(oracle.scaled_error(Y[:, c].cpu().numpy(), ref[:, c], oracle.csr_absmv(A, Xh[:, c]))
-                  for c in range(k))
+        s = [oracle.csr_absmv(A, Xh[:, c]) for c in range(k)]
+        err = max(oracle.scaled_error(Yh[:, c], ref[:, c], s[c]) for c in range(k))
+        perr = max(oracle.scaled_error(pYh[:, c], ref[:, c], s[c]) for c in range(k))
         b = alg_bytes(A.nnz, A.n_rows, A.n_cols, base.info["n_groups"], k=k)
         out["results"].append({"k": k, "us": ms * 1e3, "gflops": 2 * A.nnz * k / (ms * 1e-3) / 1e9,
                                "gbs": b / (ms * 1e-3) / 1e9, "alg_bytes": b,
                                "k_sequential_spmv_us": float(np.mean(t1)) * 1e3, "max_scaled_error": err,
-                               "copies_rotated": copies})
-        for m in mats[1:]:
-            m.close()
+                               "copies_rotated": copies,
+                               "col_panels_8": {"us": pms * 1e3, "gflops": 2 * A.nnz * k / (pms * 1e-3) / 1e9,
+                                                "gbs": b / (pms * 1e-3) / 1e9, "max_scaled_error": perr,
+                                                "copies_rotated": pcopies}})
+        print(json.dumps(out["results"][-1]), file=sys.stderr, flush=True)
     print(json.dumps(out), flush=True)
 
 

@@ -113,7 +113,7 @@ typedef struct {
                                right-hand-side launches */
     int32_t tile_min_len;   /* kernel schedule: long rows of at least this many nonzeros
                                (and at least 4 per column tile) are also stored split
-                               by column tile of 32,768 columns; a launch with one F32
+                               by column tile of 8,192 columns; a launch with one F32
                                vector of unit stride and load policy 0 first runs one
                                workgroup per (tile, run of those rows) that stages the
                                tile of x in LDS and writes one partial sum per (row,
@@ -124,12 +124,32 @@ typedef struct {
                                path.  0 = off; -1 (default) = 256, used only when the
                                tiled rows hold at least 262,144 nonzeros.  F64 storage
                                never tiles. */
+    int32_t col_panels;     /* 0 (default) = off.  P = 8, 16, ..., 64: the handle also
+                               keeps a copy of the matrix split by column into P panels
+                               of about equal nonzero count, the panels stacked as P
+                               row-compressed matrices (a row's entries in one panel's
+                               columns form one piece; rows without such entries have
+                               none) in the layout above, with each element's CSR index
+                               so rgcsr_set_values refreshes it.  A launch whose x rows
+                               (ldx elements) give at most 3 MiB of x per panel and whose
+                               column block has at most 32 bytes of accumulators per row
+                               (K <= 8 with F32 vectors, K <= 4 with F64) runs on the
+                               copy: panel q's workgroups run on XCD (q * 8 / P) of the
+                               eight, so each XCD's L2 keeps that panel's slice of x (the
+                               x reuse through a cache that Section 4.3 studies), write
+                               one sum per piece to a device buffer of the handle, and a
+                               second kernel adds each row's piece sums in panel order
+                               (deterministic).  Other launches use the layout itself.
+                               The copy doubles the stored matrix and adds 32 bytes per
+                               piece.  Host conversion only (device inputs are copied
+                               to the host); rgcsr_plan_from_csr and batches return
+                               RGCSR_EUNSUPPORTED. */
 } rgcsr_opts;
 
 /* Fills *opts with the paper's layout: G = 64, T = 1, sigma = 1, no long
  * rows, float32 storage, no CSR map, no transpose, validation on, automatic
  * kernel schedule (rows_per_lane = 0, pad_loads = -1, load_policy = 0,
- * tile_min_len = -1). */
+ * tile_min_len = -1), no column panels. */
 void rgcsr_default_opts(rgcsr_opts *opts);
 
 typedef struct rgcsr_matrix_s *rgcsr_handle;
@@ -150,6 +170,7 @@ typedef struct {
     int64_t device_bytes; /* device memory the handle owns */
     int32_t rows_per_lane, pad_loads, load_policy; /* kernel schedule in use */
     int64_t tiled_rows, tile_entries, n_tiles;     /* column-tiled long rows (tile_min_len) */
+    int64_t col_panels, panel_pieces;              /* column panels and their pieces (col_panels) */
 } rgcsr_info_t;
 
 /* ---- Host-only layout (no GPU needed; used to check the layout on CPU) ---- */

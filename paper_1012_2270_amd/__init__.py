@@ -88,13 +88,14 @@ def _on_device_of(A, t, name: str) -> None:
 def make_opts(G: int = 64, T: int = 1, sigma: int = 1, tau: int = -1, value_dtype: str = "f32",
               keep_csr_map: bool = False, build_transpose: bool = False, validate: bool = True,
               rows_per_lane: int = 0, pad_loads: int = -1, load_policy: int = 0,
-              tile_min_len: int = -1) -> _lib.Opts:
+              tile_min_len: int = -1, col_panels: int = 0) -> _lib.Opts:
     o = _lib.Opts()
     o.group_size, o.lanes_per_row, o.sort_window, o.long_row_threshold = G, T, sigma, tau
     o.value_dtype = DTYPE_CODES[value_dtype]
     o.keep_csr_map, o.build_transpose, o.validate = int(keep_csr_map), int(build_transpose), int(validate)
     o.rows_per_lane, o.pad_loads, o.load_policy = rows_per_lane, pad_loads, load_policy
     o.tile_min_len = tile_min_len
+    o.col_panels = col_panels
     return o
 
 

@@ -26,7 +26,8 @@ class Opts(ctypes.Structure):
     _fields_ = [("group_size", c_i32), ("lanes_per_row", c_i32), ("sort_window", c_i64),
                 ("long_row_threshold", c_i64), ("value_dtype", c_i32), ("keep_csr_map", c_i32),
                 ("build_transpose", c_i32), ("validate", c_i32), ("rows_per_lane", c_i32),
-                ("pad_loads", c_i32), ("load_policy", c_i32), ("tile_min_len", c_i32)]
+                ("pad_loads", c_i32), ("load_policy", c_i32), ("tile_min_len", c_i32),
+                ("col_panels", c_i32)]
 
 
 class Info(ctypes.Structure):
@@ -36,7 +37,8 @@ class Info(ctypes.Structure):
                 ("group_size", c_i32), ("lanes_per_row", c_i32), ("value_dtype", c_i32),
                 ("has_transpose", c_i32), ("sort_window", c_i64), ("long_row_threshold", c_i64),
                 ("device_bytes", c_i64), ("rows_per_lane", c_i32), ("pad_loads", c_i32),
-                ("load_policy", c_i32), ("tiled_rows", c_i64), ("tile_entries", c_i64), ("n_tiles", c_i64)]
+                ("load_policy", c_i32), ("tiled_rows", c_i64), ("tile_entries", c_i64), ("n_tiles", c_i64),
+                ("col_panels", c_i64), ("panel_pieces", c_i64)]
 
     def as_dict(self) -> dict:
         return {f: getattr(self, f) for f, _ in self._fields_}

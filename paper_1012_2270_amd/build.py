@@ -16,7 +16,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "librgcsr.so")
 BUILD_DIR = os.path.join(HERE, "_build")
-SOURCES = ["host_layout.cpp", "ordering.cpp", "tile_layout.cpp", "abi_host.cpp", "abi.cpp", "autotune.cpp", "kernels.hip",
+SOURCES = ["host_layout.cpp", "ordering.cpp", "tile_layout.cpp", "panel_layout.cpp", "abi_host.cpp", "abi.cpp", "autotune.cpp", "kernels.hip",
            "convert.hip", "tiles.hip"]
 ARCH = os.environ.get("RGCSR_OFFLOAD_ARCH", "gfx950")
 

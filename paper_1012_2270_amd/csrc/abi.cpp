@@ -125,6 +125,19 @@ struct rgcsr_matrix_s {
     void *tile_mem = nullptr;
     size_t tile_bytes = 0;
     std::shared_ptr<HostTiles> pending_tiles;  // host arrays until they are uploaded
+    // column panels (panel_layout.cpp): PN is a handle of its own over the
+    // stacked pieces, used by launches whose x slice per panel fits an L2;
+    // the arrays below belong to PN and live in its block
+    rgcsr_matrix_s *PN = nullptr;
+    int32_t n_panels = 0;
+    int64_t panel_cols = 0;                    // widest panel, in columns
+    int64_t n_out_rows = 0;                    // rows of the matrix the pieces add up to
+    int32_t *unit_map_rows = nullptr;          // [n_map_rows] workgroup -> unit, rows-per-lane schedule
+    int32_t *unit_map_one = nullptr;           // [n_map_one] workgroup -> unit, one row per lane
+    int32_t n_map_rows = 0, n_map_one = 0;
+    int32_t *pan_vptr = nullptr, *pan_vidx = nullptr;  // pieces of each output row, in panel order
+    void *pan_y = nullptr;                     // [pieces * kPanelRowBytes] per-piece sums
+    std::shared_ptr<std::vector<int32_t>> pending_maps[4];  // host copies until they are uploaded
 };
 
 struct hyb_matrix_s {
@@ -138,6 +151,11 @@ struct hyb_matrix_s {
 };
 
 namespace {
+
+void check_panels(int32_t P) {
+    if (P != 0 && (P < kPanelXcds || P > kPanelMax || P % kPanelXcds != 0))
+        fail(RGCSR_EINVAL, "col_panels must be 0 or a multiple of 8 from 8 to 64");
+}
 
 void check_device_geometry(const LayoutParams &p) {
     const int64_t GT = (int64_t)p.G * p.T;
@@ -293,8 +311,12 @@ void upload_tiles(rgcsr_matrix_s *h, const HostTiles &T, const std::vector<int32
     HIPCHK(hipStreamSynchronize(st));
 }
 
+std::vector<int32_t> panel_unit_map(const rgcsr_matrix_s *h, const HostLayout &L, const PanelBuilt &pb,
+                                    bool use_rows);
+
 rgcsr_matrix_s *prepare_handle(const HostLayout &L, bool with_row_ptr, const HostLayout *map, Arena &a,
-                               int32_t rows_per_lane, int32_t pad_loads, int32_t load_policy, int32_t tile_min_len) {
+                               int32_t rows_per_lane, int32_t pad_loads, int32_t load_policy, int32_t tile_min_len,
+                               const PanelBuilt *pb = nullptr) {
     auto *h = new rgcsr_matrix_s();
     try {
         h->prm = LayoutParams{L.G, L.T, L.sigma, L.tau};
@@ -353,6 +375,26 @@ rgcsr_matrix_s *prepare_handle(const HostLayout &L, bool with_row_ptr, const Hos
         if (L.vdt != RGCSR_F64) build_tiles(L, tile_min_len, *tiles);
         add_tile_arrays(h, *tiles, a);
         if (tiles->active()) h->pending_tiles = tiles;
+        if (pb) {
+            // panel copy: workgroup tables for both schedules, the pieces of
+            // each output row, and the per-piece sums
+            h->n_panels = pb->P;
+            for (int32_t q = 0; q < pb->P; q++) h->panel_cols = std::max(h->panel_cols, pb->cb[q + 1] - pb->cb[q]);
+            h->n_out_rows = (int64_t)pb->vptr.size() - 1;
+            auto rows = std::make_shared<std::vector<int32_t>>(panel_unit_map(h, L, *pb, true));
+            auto one = std::make_shared<std::vector<int32_t>>(panel_unit_map(h, L, *pb, false));
+            h->n_map_rows = (int32_t)rows->size();
+            h->n_map_one = (int32_t)one->size();
+            a.add(&h->unit_map_rows, rows->size());
+            a.add(&h->unit_map_one, one->size());
+            a.add(&h->pan_vptr, pb->vptr.size());
+            a.add(&h->pan_vidx, pb->vidx.size());
+            a.add((uint8_t **)&h->pan_y, (size_t)L.n_rows * kPanelRowBytes);
+            h->pending_maps[0] = rows;
+            h->pending_maps[1] = one;
+            h->pending_maps[2] = std::make_shared<std::vector<int32_t>>(pb->vptr);
+            h->pending_maps[3] = std::make_shared<std::vector<int32_t>>(pb->vidx);
+        }
         h->bytes = a.total;
     } catch (...) {
         delete h;
@@ -390,16 +432,21 @@ void place_and_upload(rgcsr_matrix_s *h, Arena &a, const HostLayout &L, const st
         if (map->long_nnz) HIPCHK(hipMemcpyAsync(h->t_map_long, map->long_val.data(), (size_t)map->long_nnz * 4, hipMemcpyHostToDevice, st));
     }
     if (h->pending_tiles) upload_tiles(h, *h->pending_tiles, L.long_row, st);
+    int32_t *const map_dst[4] = {h->unit_map_rows, h->unit_map_one, h->pan_vptr, h->pan_vidx};
+    for (int i = 0; i < 4; i++)
+        if (h->pending_maps[i]) upload(map_dst[i], *h->pending_maps[i], st);
     HIPCHK(hipStreamSynchronize(st));
     h->pending_tiles.reset();
+    for (auto &m : h->pending_maps) m.reset();
 }
 
 rgcsr_matrix_s *make_device(const HostLayout &L, const std::vector<int64_t> *row_ptr,
                             const HostLayout *map, hipStream_t st, int32_t rows_per_lane = 0,
-                            int32_t pad_loads = -1, int32_t load_policy = 0, int32_t tile_min_len = 0) {
+                            int32_t pad_loads = -1, int32_t load_policy = 0, int32_t tile_min_len = 0,
+                            const PanelBuilt *pb = nullptr) {
     Arena a;
     rgcsr_matrix_s *h = prepare_handle(L, row_ptr != nullptr, map, a, rows_per_lane, pad_loads, load_policy,
-                                       tile_min_len);
+                                       tile_min_len, pb);
     try {
         place_and_upload(h, a, L, row_ptr, map, nullptr, st);
     } catch (...) {
@@ -514,6 +561,7 @@ rgcsr_matrix_s *make_device_on_device(DevPlan &P, const LayoutParams &p, int vdt
 void free_handle(rgcsr_matrix_s *h) {
     if (!h) return;
     if (h->AT) free_handle(h->AT);
+    if (h->PN) free_handle(h->PN);
     if (h->mem && h->owns_mem) (void)hipFree(h->mem);
     if (h->tile_mem) (void)hipFree(h->tile_mem);
     delete h;
@@ -529,6 +577,52 @@ int32_t short_waves(const rgcsr_matrix_s *h, bool scheduled) {
     if (scheduled) w = h->R == 0 ? (int64_t)h->items.size() : (w + h->R - 1) / h->R;
     if (w > INT32_MAX / 2) fail(RGCSR_EOVERFLOW, "too many wavefronts");
     return (int32_t)w;
+}
+
+// Workgroup -> unit table of a panel copy.  Units are formed as params_of
+// forms them (block items, then wavefront items four to a unit); each unit
+// belongs to the panel of its first item.  The hardware deals workgroup b to
+// XCD b % 8, so panel q's units go to the workgroups b with b % 8 == q * 8 / P
+// in unit order (long-row units first, as in every launch), and -1 fills the
+// tail of XCDs with fewer units than the busiest one.
+std::vector<int32_t> panel_unit_map(const rgcsr_matrix_s *h, const HostLayout &L, const PanelBuilt &pb,
+                                    bool use_rows) {
+    const int64_t n_block = h->n_block, n_wave_long = h->n_wave_long;
+    const int64_t sw = short_waves(h, use_rows);
+    const int64_t units = n_block + (n_wave_long + sw + kBlockWaves - 1) / kBlockWaves;
+    auto panel_in = [](const std::vector<int64_t> &off, int64_t i) {
+        return (int32_t)(std::upper_bound(off.begin() + 1, off.end(), i) - (off.begin() + 1));
+    };
+    const int32_t R = use_rows ? h->R : 1;
+    std::vector<std::vector<int32_t>> per(kPanelXcds);
+    for (int64_t u = 0; u < units; u++) {
+        int32_t q;
+        if (u < n_block) {
+            q = panel_in(pb.long_off, L.work.block[u].a);
+        } else {
+            const int64_t w = (u - n_block) * kBlockWaves;
+            if (w < n_wave_long) {
+                q = panel_in(pb.long_off, L.work.wave[w].a);
+            } else {
+                // first row group of short wavefront s (as spmv_short reads it)
+                const int64_t s = w - n_wave_long;
+                int64_t g;
+                if (h->wpg > 0)
+                    g = (R == 0 ? (int64_t)(h->items[s] >> 2) : s * R) / h->wpg;
+                else
+                    g = s * h->gpw;
+                q = panel_in(pb.grp_off, g);
+            }
+        }
+        per[(size_t)q * kPanelXcds / pb.P].push_back((int32_t)u);
+    }
+    size_t longest = 0;
+    for (auto &v : per) longest = std::max(longest, v.size());
+    if (longest * kPanelXcds > (size_t)INT32_MAX / 2) fail(RGCSR_EOVERFLOW, "too many workgroups");
+    std::vector<int32_t> map(longest * kPanelXcds, -1);
+    for (int x = 0; x < kPanelXcds; x++)
+        for (size_t j = 0; j < per[x].size(); j++) map[j * kPanelXcds + x] = per[x][j];
+    return map;
 }
 
 // use_rows: the launch uses the handle's rows-per-lane schedule (single
@@ -582,19 +676,45 @@ int vec_is_f64(rgcsr_dtype vt) {
     fail(RGCSR_EUNSUPPORTED, "vectors must be F32 or F64");
 }
 
+// The panel copy serves launches whose per-piece sums fit the buffer
+// (K accumulators of kPanelRowBytes at most) and whose x slice per panel
+// (panel columns times the X row stride) fits kPanelSliceBytes.
+bool panel_slice_ok(const rgcsr_matrix_s *h, int64_t ldx, int f64) {
+    return h->PN && h->PN->panel_cols * ldx * (f64 ? 8 : 4) <= kPanelSliceBytes;
+}
+bool panel_launch_ok(const rgcsr_matrix_s *h, int K, int64_t ldx, int f64) {
+    return panel_slice_ok(h, ldx, f64) && K * (f64 ? 8 : 4) <= kPanelRowBytes;
+}
+
 void spmv_launch(const rgcsr_matrix_s *h, int K, const void *X, int64_t ldx, void *Y, int64_t ldy, int f64,
                  bool persistent, hipStream_t st) {
     if (h->n_rows == 0) return;
+    const bool panels = panel_launch_ok(h, K, ldx, f64);
+    const rgcsr_matrix_s *pn = h->PN;
     // the column-tiled rows take one FP32 vector with unit stride and the
     // default load policy; everything else runs them on the long-row path
-    const bool tiled = h->n_trows > 0 && K == 1 && !f64 && ldx == 1 && h->lp == 0;
-    SpmvParams P = params_of(h, K == 1, tiled);
+    const bool tiled = !panels && h->n_trows > 0 && K == 1 && !f64 && ldx == 1 && h->lp == 0;
+    // right-hand sides of up to kRunsRowBytes per row take the runs of rows
+    // per lane (R = 0) when the handle has them; otherwise one row per lane
+    const rgcsr_matrix_s *src = panels ? pn : h;
+    const bool rows = K == 1 || (K * (f64 ? 8 : 4) <= kRunsRowBytes && src->R == 0);
+    const int32_t R = K == 1 ? src->R : (rows ? 0 : 1);
+    SpmvParams P = params_of(src, rows, tiled);
     P.x = X; P.y = Y; P.ldx = ldx; P.ldy = ldy;
     int64_t nwg = P.total_units;
+    if (panels) {
+        // pieces of panel q on XCD q * 8 / P, their sums to the piece buffer
+        P.unit_map = rows ? pn->unit_map_rows : pn->unit_map_one;
+        P.n_map = rows ? pn->n_map_rows : pn->n_map_one;
+        P.y = pn->pan_y;
+        P.ldy = K;
+        nwg = P.n_map;
+    }
     // a persistent launch (several right-hand sides only) keeps two 256-thread
-    // workgroups per CU that stride over the units
+    // workgroups per CU that stride over the units (a multiple of 8, so a
+    // workgroup stays on the XCD of its table entries)
     if (persistent && K > 1) nwg = std::min<int64_t>(nwg, (int64_t)cu_count(h->device) * 2);
-    if (nwg == 0) return;
+    if (nwg == 0 && !panels) return;
     const int vd = h->vdt;
     if (f64 && !(vd == RGCSR_F64 || vd == RGCSR_F32))
         fail(RGCSR_EUNSUPPORTED, "F64 vectors need F64 or F32 stored values");
@@ -606,6 +726,20 @@ void spmv_launch(const rgcsr_matrix_s *h, int K, const void *X, int64_t ldx, voi
         fail(RGCSR_EUNSUPPORTED, "x (n_cols * ldx elements) of 4 GiB or more");
     if (K == 1 && h->lp != 0 && f64) fail(RGCSR_EUNSUPPORTED, "load policies 1 and 2 need F32 vectors");
     hipError_t e = hipSuccess;
+    if (panels) {
+        if (nwg > 0) {
+            e = launch_spmv(P, vd, f64, pn->prm.T, K, R, K == 1 ? pn->lp : 0, (int)nwg, st);
+            if (e != hipSuccess) fail(RGCSR_EHIP, std::string("spmv launch: ") + hipGetErrorString(e));
+        }
+        if (pn->n_combine) {
+            e = launch_combine(pn->combine, (int32_t)pn->n_combine, pn->long_row, pn->partial, pn->pan_y, K, f64, K,
+                               st);
+            if (e != hipSuccess) fail(RGCSR_EHIP, std::string("combine launch: ") + hipGetErrorString(e));
+        }
+        e = launch_panel_combine(pn->pan_vptr, pn->pan_vidx, h->n_rows, pn->pan_y, Y, ldy, f64, K, st);
+        if (e != hipSuccess) fail(RGCSR_EHIP, std::string("panel combine launch: ") + hipGetErrorString(e));
+        return;
+    }
     if (tiled) {
         TileParams TP{};
         TP.units = h->tile_units;
@@ -620,7 +754,7 @@ void spmv_launch(const rgcsr_matrix_s *h, int K, const void *X, int64_t ldx, voi
         e = launch_tile_spmv(TP, vd, (int)h->n_tunits, st);
         if (e != hipSuccess) fail(RGCSR_EHIP, std::string("tile launch: ") + hipGetErrorString(e));
     }
-    e = launch_spmv(P, vd, f64, h->prm.T, K, K == 1 ? h->R : 1, K == 1 ? h->lp : 0, (int)nwg, st);
+    e = launch_spmv(P, vd, f64, h->prm.T, K, R, K == 1 ? h->lp : 0, (int)nwg, st);
     if (e != hipSuccess) fail(RGCSR_EHIP, std::string("spmv launch: ") + hipGetErrorString(e));
     const int64_t n_comb = tiled ? h->n_rest_combine : h->n_combine;
     if (n_comb) {
@@ -673,6 +807,7 @@ rgcsr_status rgcsr_from_csr(int64_t n_rows, int64_t n_cols, int64_t nnz, const i
     check_dtype(o.value_dtype, "value_dtype");
     check_dtype(vals_dtype, "vals");
     if (n_rows < 0 || n_cols < 0 || nnz < 0) fail(RGCSR_EINVAL, "negative size");
+    check_panels(o.col_panels);
     hipStream_t st = (hipStream_t)stream;
     std::vector<int64_t> h_rp;
     std::vector<int32_t> h_col;
@@ -680,7 +815,7 @@ rgcsr_status rgcsr_from_csr(int64_t n_rows, int64_t n_cols, int64_t nnz, const i
     const int64_t *rp = row_ptr;
     const int32_t *col = col_idx;
     const void *val = vals;
-    if (inputs_on_device && !o.build_transpose) {
+    if (inputs_on_device && !o.build_transpose && !o.col_panels) {
         // conversion on the device; device inputs are always validated
         DevPlan P;
         P.scratch.st = st;
@@ -711,14 +846,24 @@ rgcsr_status rgcsr_from_csr(int64_t n_rows, int64_t n_cols, int64_t nnz, const i
     build_host(B, p, o.value_dtype, 1, &n_rows, &n_cols, &rp, &col, &val, vals_dtype, o.validate != 0, keep, tr);
     rgcsr_matrix_s *h = make_device(B.L, (keep || tr) ? &B.row_ptr : nullptr, nullptr, st, o.rows_per_lane,
                                     o.pad_loads, o.load_policy, o.tile_min_len);
-    if (tr) {
-        try {
+    try {
+        if (tr)
             h->AT = make_device(B.LT, nullptr, &B.LTmap, st, o.rows_per_lane, o.pad_loads, o.load_policy,
                                 o.tile_min_len);
-        } catch (...) {
-            free_handle(h);
-            throw;
+        if (o.col_panels) {
+            // the panel copy holds the values in the storage dtype; set_values
+            // refreshes it through its element -> CSR index map
+            const int64_t esz = dtype_size(o.value_dtype);
+            std::vector<uint8_t> conv((size_t)rp[n_rows] * esz);
+            if (rp[n_rows]) convert_values(val, vals_dtype, conv.data(), o.value_dtype, rp[n_rows]);
+            PanelBuilt pb;
+            build_panels(pb, p, o.value_dtype, o.col_panels, n_rows, n_cols, rp, col, conv.data());
+            h->n_panels = o.col_panels;
+            h->PN = make_device(pb.LP, nullptr, &pb.LPmap, st, o.rows_per_lane, o.pad_loads, o.load_policy, 0, &pb);
         }
+    } catch (...) {
+        free_handle(h);
+        throw;
     }
     *out = h;
     ABI_CATCH
@@ -739,6 +884,8 @@ rgcsr_status rgcsr_plan_from_csr(int64_t n_rows, int64_t n_cols, int64_t nnz, co
     if (n_rows < 0 || n_cols < 0 || nnz < 0) fail(RGCSR_EINVAL, "negative size");
     if (!row_ptr) fail(RGCSR_EINVAL, "row_ptr is null");
     if (!o.validate && row_ptr[n_rows] != nnz) fail(RGCSR_ECSR, "row_ptr[n_rows] != nnz");
+    check_panels(o.col_panels);
+    if (o.col_panels) fail(RGCSR_EUNSUPPORTED, "col_panels needs rgcsr_from_csr");
     std::unique_ptr<rgcsr_plan_s> P(new rgcsr_plan_s());
     P->with_row_ptr = o.keep_csr_map != 0 || o.build_transpose != 0;
     const bool tr = o.build_transpose != 0;
@@ -818,6 +965,8 @@ rgcsr_status rgcsr_from_csr_batch(int32_t count, const int64_t *n_rows, const in
     check_device_geometry(p);
     check_dtype(o.value_dtype, "value_dtype");
     check_dtype(vals_dtype, "vals");
+    check_panels(o.col_panels);
+    if (o.col_panels) fail(RGCSR_EUNSUPPORTED, "col_panels needs rgcsr_from_csr (one matrix)");
     hipStream_t st = (hipStream_t)stream;
     Built B;
     const bool keep = o.keep_csr_map != 0, tr = o.build_transpose != 0;
@@ -872,12 +1021,14 @@ rgcsr_status rgcsr_spmv_batched(rgcsr_handle A, int32_t k, const void *X, int64_
     // the multi-column kernels take one lane per row and F32/F64 values;
     // other handles run one single-column launch per column (strided x, y)
     const bool blocks = A->prm.T == 1 && (A->vdt == RGCSR_F32 || A->vdt == RGCSR_F64);
+    // a panel copy takes column blocks whose sums fit its piece buffer
+    const int32_t kmax = panel_slice_ok(A, ldx, f64) ? kPanelRowBytes / esz : 32;
     int32_t done = 0;
     while (done < k) {
         int32_t kb = 1;
         for (int32_t c : {32, 16, 8, 4, 2, 1}) {
             if (!blocks) break;
-            if (c > k - done) continue;
+            if (c > k - done || c > kmax) continue;
             if (c % vw == 0 && (!aligned || ((size_t)done * esz) % 16 != 0)) continue;
             kb = c;
             break;
@@ -951,6 +1102,12 @@ rgcsr_status rgcsr_set_values(rgcsr_handle A, const void *vals, rgcsr_dtype vals
             if (e == hipSuccess && A->AT->n_tent)
                 e = launch_tile_values(A->AT->long_nnz, A->AT->tile_dst, A->AT->long_val, A->AT->tile_val, A->esz, st);
             if (e != hipSuccess) fail(RGCSR_EHIP, std::string("set_values (transpose): ") + hipGetErrorString(e));
+        }
+        if (A->PN) {
+            hipError_t e = launch_gather_map(A->PN->slots, A->vdt, A->PN->t_map_slot, theta, theta_f64, A->PN->slot_val, st);
+            if (e == hipSuccess)
+                e = launch_gather_map(A->PN->long_nnz, A->vdt, A->PN->t_map_long, theta, theta_f64, A->PN->long_val, st);
+            if (e != hipSuccess) fail(RGCSR_EHIP, std::string("set_values (panels): ") + hipGetErrorString(e));
         }
         if (tmp) {
             HIPCHK(hipStreamSynchronize(st));
@@ -1055,6 +1212,11 @@ rgcsr_status rgcsr_info(rgcsr_handle A, rgcsr_info_t *out) {
     out->tiled_rows = A->n_trows;
     out->tile_entries = A->n_tent;
     out->n_tiles = A->n_tiles;
+    if (A->PN) {
+        out->col_panels = A->PN->n_panels;
+        out->panel_pieces = A->PN->n_rows;
+        out->device_bytes += (int64_t)A->PN->bytes;
+    }
     ABI_CATCH
 }
 
@@ -1079,6 +1241,7 @@ rgcsr_matrix_s *clone_handle(const rgcsr_matrix_s *A, hipStream_t st) {
     h->mem = nullptr;
     h->owns_mem = true;
     h->AT = nullptr;
+    h->PN = nullptr;
     h->tile_mem = nullptr;
     try {
         if (A->bytes) HIPCHK(hipMalloc(&h->mem, A->bytes));
@@ -1091,7 +1254,8 @@ rgcsr_matrix_s *clone_handle(const rgcsr_matrix_s *A, hipStream_t st) {
                &rgcsr_matrix_s::long_row, &rgcsr_matrix_s::long_col,
                &rgcsr_matrix_s::long_ptr, &rgcsr_matrix_s::long_val, &rgcsr_matrix_s::partial,
                &rgcsr_matrix_s::row_ptr, &rgcsr_matrix_s::t_map_slot,
-               &rgcsr_matrix_s::t_map_long);
+               &rgcsr_matrix_s::t_map_long, &rgcsr_matrix_s::unit_map_rows, &rgcsr_matrix_s::unit_map_one,
+               &rgcsr_matrix_s::pan_vptr, &rgcsr_matrix_s::pan_vidx, &rgcsr_matrix_s::pan_y);
         // tile arrays: in the same block, or in a block of their own
         auto tile_rebase = [&](void *rgcsr_matrix_s::*block) {
             rebase(h, A, block, &rgcsr_matrix_s::tile_units, &rgcsr_matrix_s::tile_ptr, &rgcsr_matrix_s::tile_dst,
@@ -1108,6 +1272,7 @@ rgcsr_matrix_s *clone_handle(const rgcsr_matrix_s *A, hipStream_t st) {
             tile_rebase(&rgcsr_matrix_s::mem);
         }
         if (A->AT) h->AT = clone_handle(A->AT, st);
+        if (A->PN) h->PN = clone_handle(A->PN, st);
         HIPCHK(hipStreamSynchronize(st));
     } catch (...) {
         free_handle(h);

@@ -47,6 +47,7 @@ void rgcsr_default_opts(rgcsr_opts *o) {
     o->pad_loads = -1;
     o->load_policy = 0;
     o->tile_min_len = -1;
+    o->col_panels = 0;
 }
 
 const char *rgcsr_status_string(rgcsr_status s) {

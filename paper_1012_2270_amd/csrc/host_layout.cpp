@@ -334,7 +334,10 @@ void build_host(Built &B, const LayoutParams &p, int vdt, int32_t count, const i
     }
     if (keep_map || transpose) B.row_ptr.assign(1, 0);
     int64_t nnz_base = 0;
+    // append_layout treats a null value pointer as "sizes only", so the value
+    // buffers stay allocated for matrices without nonzeros
     std::vector<uint8_t> conv;
+    conv.reserve((size_t)esz);
     for (int32_t m = 0; m < count; m++) {
         const int64_t nr = n_rows[m], nc = n_cols[m];
         if (nr < 0 || nc < 0) fail(RGCSR_EINVAL, "negative matrix size");
@@ -351,9 +354,9 @@ void build_host(Built &B, const LayoutParams &p, int vdt, int32_t count, const i
             std::vector<int64_t> rpT;
             std::vector<int32_t> colT, srcT;
             transpose_csr(nr, nc, rp[m], col[m], rpT, colT, srcT);
-            std::vector<uint8_t> valsT((size_t)nnz * esz);
+            std::vector<uint8_t> valsT((size_t)std::max<int64_t>(nnz, 1) * esz);
             for (int64_t k = 0; k < nnz; k++) memcpy(&valsT[(size_t)k * esz], &conv[(size_t)srcT[k] * esz], esz);
-            std::vector<int32_t> mapT(nnz);
+            std::vector<int32_t> mapT(std::max<int64_t>(nnz, 1));
             if (nnz_base + nnz > INT32_MAX) fail(RGCSR_EOVERFLOW, "transpose map needs total nnz < 2^31");
             for (int64_t k = 0; k < nnz; k++) mapT[k] = (int32_t)(srcT[k] + nnz_base);
             append_layout(B.LT, p, nc, nr, rpT.data(), colT.data(), valsT.data(), esz, 0);

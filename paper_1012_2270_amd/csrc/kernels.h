@@ -52,6 +52,10 @@ struct SpmvParams {
     // (-1 when its row is not tiled) and the tiled values; null without tiles
     const int32_t *tile_dst;     // [long_nnz]
     void *tile_vals;             // [tile entries] storage dtype
+    // column panels: workgroup (or, in a persistent launch, table entry) j
+    // runs unit unit_map[j], none when -1; null = the usual unit order
+    const int32_t *unit_map;     // [n_map]
+    int32_t n_map;
     // vectors
     const void *x;
     void *y;
@@ -71,8 +75,15 @@ struct HybParams {
 enum { kRR = 0, kRR0 = 1, kPQ = 2, kAlpha = 3, kBeta = 4, kOut = 5, kNumScal = 8 };
 enum { kScalPQ = 0, kScalRRNew = 1, kScalRRInit = 2, kScalOut = 3 };
 
+// Several right-hand sides take the runs of rows per lane (R = 0) up to this
+// many accumulator bytes per row (F32 K <= 4, F64 K <= 2); wider, one row per lane.
+constexpr int kRunsRowBytes = 16;
 hipError_t launch_spmv(const SpmvParams &P, int vdt, int vec_f64, int T, int K, int R, int load_policy, int nwg,
                        hipStream_t st);
+// Y[r] = sum of the piece sums yv[vidx[s]] (K values each) for s in
+// [vptr[r], vptr[r + 1]), in that order; 0 for a row without pieces.
+hipError_t launch_panel_combine(const int32_t *vptr, const int32_t *vidx, int64_t n_rows, const void *yv, void *Y,
+                                int64_t ldy, int vec_f64, int K, hipStream_t st);
 hipError_t launch_combine(const LongItem *items, int32_t n, const int32_t *long_row, const void *partial, void *Y,
                           int64_t ldy, int vec_f64, int K, hipStream_t st);
 hipError_t launch_setval(const SpmvParams &P, int vdt, int T, const void *theta, int theta_f64,

@@ -231,6 +231,9 @@ __device__ __forceinline__ LaneRow lane_row(const SpmvParams &P, int32_t w, int 
 // kernel), and each lane keeps the paper's serial order within its row.
 // ---------------------------------------------------------------------------
 template <int K> constexpr int unroll_for() { return K == 1 ? 8 : (K <= 4 ? 4 : (K <= 8 ? 2 : 1)); }
+// Steps in flight per lane of a several-rows-per-lane pass with K right-hand
+// sides: the gathered X rows take about 64 registers (16 steps up to K = 4).
+template <int K> constexpr int multi_steps() { return K <= 4 ? 16 : 64 / K; }
 
 // X[c * ldx] for one right-hand side with a 32-bit byte offset from the
 // uniform base (scalar base + vector offset addressing; the host checks
@@ -308,8 +311,8 @@ __device__ __forceinline__ void spmv_groups_uniform(const SpmvParams &P, int32_t
 #pragma unroll
         for (int k = 0; k < K; k++) acc[r][k] = A(0);
     // steps per pass: SB / R (the host's rows-per-lane choice uses the same
-    // step budget)
-    constexpr int U = K == 1 ? SB / R : unroll_for<K>();
+    // step budget); several right-hand sides: the X-row budget over R rows
+    constexpr int U = K == 1 ? SB / R : (R == 1 ? unroll_for<K>() : (multi_steps<K>() / R > 0 ? multi_steps<K>() / R : 1));
     // Inside the unrolled body every load is issued unconditionally (steps past
     // the bound read the group's first slot and x[0], in bounds whenever the
     // loop runs) and results are masked with selects, so the loads of a phase
@@ -520,7 +523,9 @@ __device__ __forceinline__ void spmv_wave_long(const SpmvParams &P, int32_t w, i
     A acc[K];
 #pragma unroll
     for (int k = 0; k < K; k++) acc[k] = A(0);
-    constexpr int U = K == 1 ? kWaveUnroll : unroll_for<K>();
+    // a lane's (at most kWaveUnroll) nonzeros in one pass while their X rows
+    // fit the multi-column register budget
+    constexpr int U = K == 1 ? kWaveUnroll : (multi_steps<K>() >= kWaveUnroll ? kWaveUnroll : unroll_for<K>());
     strided_dot32<VD, A, K, U, LP>(vb, cb, X, P.ldx, (uint32_t)(P.ldx * (int64_t)sizeof(A)), b + q, e, TL, acc);
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1)
@@ -609,7 +614,7 @@ __device__ __forceinline__ void spmv_block_item(const SpmvParams &P, int32_t u, 
     A acc[K];
 #pragma unroll
     for (int k = 0; k < K; k++) acc[k] = A(0);
-    constexpr int U = K == 1 ? 16 : unroll_for<K>();
+    constexpr int U = K == 1 || multi_steps<K>() >= 16 ? 16 : unroll_for<K>();
     // start the threads' walk at the 32-element boundary below the chunk, so
     // each wavefront's 64 consecutive loads cover the fewest cache lines; the
     // d elements before the chunk are loaded but not multiplied
@@ -708,13 +713,42 @@ __global__ __launch_bounds__(kBlockThreads) void rgcsr_spmv_k(SpmvParams P) {
     const int lane = threadIdx.x & 63;
     const int wv = threadIdx.x >> 6;
     const int nwg = gridDim.x;
+    // column panels: the host's table (unit_map) places each panel's units
+    // on one XCD; -1 entries run nothing.  With one right-hand side the grid
+    // is the table's length.
     if constexpr (K == 1) {
-        const int32_t u = first_unit(blockIdx.x, nwg, P.n_long_units);
-        if (u < P.total_units) spmv_unit<VD, A, K, T, R, LONG, LP>(P, u, lane, wv, red, lbuf[kLdsLong ? wv : 0]);
+        int32_t u = first_unit(blockIdx.x, nwg, P.n_long_units);
+        if (P.unit_map) u = ldc(P.unit_map, blockIdx.x);
+        if (u >= 0 && u < P.total_units)
+            spmv_unit<VD, A, K, T, R, LONG, LP>(P, u, lane, wv, red, lbuf[kLdsLong ? wv : 0]);
     } else {
-        for (int32_t u = first_unit(blockIdx.x, nwg, P.n_long_units); u < P.total_units; u += nwg)
-            spmv_unit<VD, A, K, T, R, LONG, LP>(P, u, lane, wv, red, lbuf[0]);
+        int32_t u = first_unit(blockIdx.x, nwg, P.n_long_units);
+        for (int32_t j = blockIdx.x; P.unit_map ? j < P.n_map : u < P.total_units; j += nwg, u += nwg) {
+            const int32_t v = P.unit_map ? ldc(P.unit_map, j) : u;
+            if (v >= 0) spmv_unit<VD, A, K, T, R, LONG, LP>(P, v, lane, wv, red, lbuf[0]);
+        }
     }
+}
+
+// Column panels: each output row adds its pieces' sums yv[vidx[s]] for s in
+// [vptr[r], vptr[r + 1]), in panel order.  The sums are stored by piece, in
+// panel order, so each XCD writes whole lines of its own.
+template <class A, int K>
+__global__ __launch_bounds__(256) void panel_combine_k(const int32_t *vptr, const int32_t *vidx, int64_t n_rows,
+                                                       const A *yv, A *Y, int64_t ldy) {
+    const int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (r >= n_rows) return;
+    const int32_t s0 = vptr[r], s1 = vptr[r + 1];
+    A acc[K];
+#pragma unroll
+    for (int k = 0; k < K; k++) acc[k] = A(0);
+    for (int32_t s = s0; s < s1; s++) {
+        A v[K];
+        load_row<A, K>(yv + (int64_t)vidx[s] * K, v);
+#pragma unroll
+        for (int k = 0; k < K; k++) acc[k] += v[k];
+    }
+    store_row<A, K>(Y + r * ldy, acc);
 }
 
 // Rows split over several block items: add the chunk partial sums in order.
@@ -1248,10 +1282,16 @@ static hipError_t launch_spmv_vk(const SpmvParams &P, int T, int K, int R, int n
         }
         return hipErrorInvalidValue;
     }
-    if (T != 1 || R != 1) return hipErrorInvalidValue;
+    // right-hand sides of at most 16 bytes per row: one row per lane, or the
+    // runs of rows per lane (R = 0); wider ones one row per lane
+    if (T != 1 || (R != 1 && (R != 0 || K * (int)sizeof(A) > kRunsRowBytes))) return hipErrorInvalidValue;
     switch (K) {
-    case 2: return launch_spmv_t<VD, A, 2, 1, 1>(P, nwg, st);
-    case 4: return launch_spmv_t<VD, A, 4, 1, 1>(P, nwg, st);
+    case 2: return R ? launch_spmv_t<VD, A, 2, 1, 1>(P, nwg, st) : launch_spmv_t<VD, A, 2, 1, 0>(P, nwg, st);
+    case 4:
+        if constexpr (sizeof(A) == 4) {
+            if (!R) return launch_spmv_t<VD, A, 4, 1, 0>(P, nwg, st);
+        }
+        return launch_spmv_t<VD, A, 4, 1, 1>(P, nwg, st);
     case 8: return launch_spmv_t<VD, A, 8, 1, 1>(P, nwg, st);
     case 16: return launch_spmv_t<VD, A, 16, 1, 1>(P, nwg, st);
     case 32: return launch_spmv_t<VD, A, 32, 1, 1>(P, nwg, st);
@@ -1279,6 +1319,27 @@ static hipError_t launch_combine_a(const LongItem *items, int32_t n, const int32
     case 32: return launch_combine_k<A, 32>(items, n, long_row, partial, Y, ldy, st);
     }
     return hipErrorInvalidValue;
+}
+
+template <class A>
+static hipError_t launch_panel_combine_a(const int32_t *vptr, const int32_t *vidx, int64_t n, const A *yv, A *Y,
+                                         int64_t ldy, int K, hipStream_t st) {
+    const dim3 g((unsigned)((n + 255) / 256)), b(256);
+    switch (K) {
+    case 1: hipLaunchKernelGGL((panel_combine_k<A, 1>), g, b, 0, st, vptr, vidx, n, yv, Y, ldy); break;
+    case 2: hipLaunchKernelGGL((panel_combine_k<A, 2>), g, b, 0, st, vptr, vidx, n, yv, Y, ldy); break;
+    case 4: hipLaunchKernelGGL((panel_combine_k<A, 4>), g, b, 0, st, vptr, vidx, n, yv, Y, ldy); break;
+    case 8: hipLaunchKernelGGL((panel_combine_k<A, 8>), g, b, 0, st, vptr, vidx, n, yv, Y, ldy); break;
+    default: return hipErrorInvalidValue;
+    }
+    return check_launch();
+}
+
+hipError_t launch_panel_combine(const int32_t *vptr, const int32_t *vidx, int64_t n_rows, const void *yv, void *Y,
+                                int64_t ldy, int vec_f64, int K, hipStream_t st) {
+    if (n_rows == 0) return hipSuccess;
+    if (vec_f64) return launch_panel_combine_a<double>(vptr, vidx, n_rows, (const double *)yv, (double *)Y, ldy, K, st);
+    return launch_panel_combine_a<float>(vptr, vidx, n_rows, (const float *)yv, (float *)Y, ldy, K, st);
 }
 
 hipError_t launch_combine(const LongItem *items, int32_t n, const int32_t *long_row, const void *partial, void *Y,

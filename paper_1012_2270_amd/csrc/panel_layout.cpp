@@ -1,0 +1,110 @@
+// Column panels of one CSR matrix (host).
+//
+// Every nonzero gathers x at its column; for a matrix whose columns are
+// spread over all of x (random or power-law sparsity), the gathers of one
+// XCD touch all of x and its L2 keeps only a part of it.  Split by column
+// into panels, each XCD multiplies one panel at a time and keeps that
+// panel's slice of x in its own L2 -- the reuse of x through a cache that
+// Section 4.3 studies with the texture cache, arranged for eight L2s.  The
+// panels are laid out with the same row groups, sort windows and long-row
+// split as the whole matrix (Sections 3.2 and 4.4.2).
+#include <algorithm>
+#include <cstring>
+
+#include "internal.h"
+
+namespace rg {
+
+void build_panels(PanelBuilt &B, const LayoutParams &p, int vdt, int32_t P, int64_t n_rows, int64_t n_cols,
+                  const int64_t *rp, const int32_t *col, const uint8_t *vals) {
+    if (P < 1 || P > kPanelMax) fail(RGCSR_EINVAL, "bad panel count");
+    const int esz = dtype_size(vdt);
+    const int64_t nnz = rp[n_rows];
+    if (nnz > INT32_MAX) fail(RGCSR_EOVERFLOW, "column panels need nnz < 2^31");
+    B = PanelBuilt{};
+    B.P = P;
+    // bounds: cb[q] is the first column at which the nonzeros of the columns
+    // before it reach q * nnz / P (nondecreasing; empty panels are allowed)
+    std::vector<int64_t> ccount((size_t)n_cols + 1, 0);
+    for (int64_t k = 0; k < nnz; k++) ccount[(size_t)col[k] + 1]++;
+    for (int64_t c = 0; c < n_cols; c++) ccount[c + 1] += ccount[c];
+    B.cb.assign((size_t)P + 1, 0);
+    for (int32_t q = 1; q < P; q++) {
+        const int64_t target = (nnz * q + P - 1) / P;
+        B.cb[q] = std::lower_bound(ccount.begin(), ccount.end(), target) - ccount.begin();
+        B.cb[q] = std::max(B.cb[q - 1], std::min(B.cb[q], n_cols));
+    }
+    B.cb[P] = n_cols;
+    auto panel_of = [&](int32_t c) {
+        return (int32_t)(std::upper_bound(B.cb.begin() + 1, B.cb.end(), (int64_t)c) - (B.cb.begin() + 1));
+    };
+    std::vector<int32_t> pan((size_t)nnz);
+    for (int64_t k = 0; k < nnz; k++) pan[k] = panel_of(col[k]);
+
+    // pieces per row (rank of a panel among the row's panels) and per panel
+    std::vector<int32_t> rows_in((size_t)P, 0);
+    B.vptr.assign((size_t)n_rows + 1, 0);
+    {
+        std::vector<int32_t> seen((size_t)P, -1);
+        for (int64_t r = 0; r < n_rows; r++) {
+            int32_t n = 0;
+            for (int64_t k = rp[r]; k < rp[r + 1]; k++)
+                if (seen[pan[k]] != (int32_t)r) {
+                    seen[pan[k]] = (int32_t)r;
+                    rows_in[pan[k]]++;
+                    n++;
+                }
+            if ((int64_t)B.vptr[r] + n > INT32_MAX) fail(RGCSR_EOVERFLOW, "column panels need < 2^31 pieces");
+            B.vptr[r + 1] = B.vptr[r] + n;
+        }
+    }
+    std::vector<int64_t> piece0((size_t)P + 1, 0);  // first piece of each panel
+    for (int32_t q = 0; q < P; q++) piece0[q + 1] = piece0[q] + rows_in[q];
+    B.vidx.assign((size_t)B.vptr[n_rows], 0);
+
+    B.LP = HostLayout{};
+    B.LP.G = p.G; B.LP.T = p.T; B.LP.sigma = p.sigma; B.LP.tau = p.tau; B.LP.vdt = vdt; B.LP.esz = esz;
+    B.LP.n_matrices = 0;
+    B.LPmap = B.LP;
+    B.LPmap.esz = 4;
+    B.grp_off.assign(1, 0);
+    B.long_off.assign(1, 0);
+    std::vector<int64_t> prp;
+    std::vector<int32_t> pcol, pmap;
+    std::vector<uint8_t> pval;
+    // append_layout treats a null value pointer as "sizes only": keep the
+    // value buffers allocated even for a panel without entries
+    pmap.reserve(1);
+    pval.reserve((size_t)esz);
+    std::vector<int32_t> next((size_t)n_rows);  // next piece slot of each row in vidx
+    for (int64_t r = 0; r < n_rows; r++) next[r] = B.vptr[r];
+    for (int32_t q = 0; q < P; q++) {
+        // panel q as a row-compressed CSR matrix with panel-local columns
+        prp.assign(1, 0);
+        pcol.clear();
+        pmap.clear();
+        pval.clear();
+        int64_t piece = piece0[q];
+        for (int64_t r = 0; r < n_rows; r++) {
+            const int64_t before = (int64_t)pcol.size();
+            for (int64_t k = rp[r]; k < rp[r + 1]; k++)
+                if (pan[k] == q) {
+                    pcol.push_back((int32_t)(col[k] - B.cb[q]));
+                    pmap.push_back((int32_t)k);
+                    pval.insert(pval.end(), vals + (size_t)k * esz, vals + (size_t)(k + 1) * esz);
+                }
+            if ((int64_t)pcol.size() > before) {
+                prp.push_back((int64_t)pcol.size());
+                B.vidx[next[r]++] = (int32_t)piece++;
+            }
+        }
+        const int64_t nr = (int64_t)prp.size() - 1, nc = B.cb[q + 1] - B.cb[q];
+        append_layout(B.LP, p, nr, nc, prp.data(), pcol.data(), pval.data(), esz, 0);
+        append_layout(B.LPmap, p, nr, nc, prp.data(), pcol.data(), (const uint8_t *)pmap.data(), 4, 0xff);
+        B.grp_off.push_back(B.LP.ng);
+        B.long_off.push_back(B.LP.nl);
+    }
+    build_long_work(B.LP.long_ptr, B.LP.work);
+}
+
+}  // namespace rg

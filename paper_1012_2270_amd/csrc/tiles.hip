@@ -61,12 +61,12 @@ __global__ __launch_bounds__(kTileThreads) void tile_spmv_k(TileParams P) {
     }
     const float *xt = P.x + c0;
     constexpr int X4 = kTileCols / 4 / kTileThreads;
+    // assigned on every path, so the array stays in registers
     float4 x4[X4];
     const bool vec = P.x_aligned && nc == kTileCols;
-    if (vec) {
 #pragma unroll
-        for (int k = 0; k < X4; k++) x4[k] = reinterpret_cast<const float4 *>(xt)[tid + k * kTileThreads];
-    }
+    for (int k = 0; k < X4; k++)
+        x4[k] = vec ? reinterpret_cast<const float4 *>(xt)[tid + k * kTileThreads] : make_float4(0.f, 0.f, 0.f, 0.f);
     const int L = u.lanes;
     const int sh = 31 - __builtin_clz(L);
     const int q = tid & (L - 1);
