@@ -57,14 +57,24 @@ void build_tiles(const HostLayout &L, int64_t min_len, HostTiles &T) {
     const bool automatic = min_len < 0;
     const int64_t n_tiles = (L.n_cols + kTileCols - 1) / kTileCols;
     const int64_t thr = std::max<int64_t>(automatic ? 256 : min_len, (n_tiles + 1) / 2);
-    // a tile segment holds at most kTileCols entries (distinct columns), so
-    // it always fits one unit
-    static_assert(kTileCols <= kTileUnitMax, "a segment fits a unit");
+    // a row's segment in one tile must fit a unit: a row with more than
+    // kTileUnitMax entries in some tile stays on the long-row path (columns
+    // ascend within a row, so a segment is a run of consecutive entries)
+    auto longest_segment = [&](int64_t i) {
+        int64_t best = 0, run = 0, prev = -1;
+        for (int64_t q = L.long_ptr[i]; q < L.long_ptr[i + 1]; q++) {
+            const int64_t t = L.long_col[q] / kTileCols;
+            run = t == prev ? run + 1 : 1;
+            prev = t;
+            best = std::max(best, run);
+        }
+        return best;
+    };
     T.tiled.assign(L.nl, 0);
     int64_t n_ent = 0;
     for (int64_t i = 0; i < L.nl; i++) {
         const int64_t len = L.long_ptr[i + 1] - L.long_ptr[i];
-        if (len < thr) continue;
+        if (len < thr || (len > kTileUnitMax && longest_segment(i) > kTileUnitMax)) continue;
         T.tiled[i] = 1;
         T.trow.push_back((int32_t)i);
         n_ent += len;

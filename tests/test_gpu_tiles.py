@@ -130,8 +130,9 @@ def test_tiles_built_on_device_and_into_torch_memory(torch_cuda, oracle, zipf):
 
 def test_tiles_with_a_dense_tile_segment(torch_cuda, oracle):
     """A row holding 4,096 consecutive columns of one tile (one segment of
-    4,096 entries: 64 lanes per row, 64 products per lane) next to sparse long
-    rows."""
+    4,096 entries, a whole unit: 64 lanes per row, 64 products per lane) next
+    to sparse long rows, and a row with 5,000 entries in one tile, more than a
+    unit holds, which stays on the long-row path."""
     A = W.random_csr(3000, 70_000, seed=46, max_len=8, long_rows=6, long_len=9000)
     L = np.diff(A.row_ptr).copy()
     cols, vals = [], []
@@ -143,6 +144,10 @@ def test_tiles_with_a_dense_tile_segment(torch_cuda, oracle):
             c = np.concatenate([np.arange(4096), 8192 + np.sort(rng.choice(60_000, 3000, replace=False))])
             c = c.astype(np.int32)
             v = rng.standard_normal(len(c))
+        if r == 1:
+            c = np.concatenate([np.sort(rng.choice(16_384, 1500, replace=False)), 16_384 + np.arange(5000)])
+            c = c.astype(np.int32)
+            v = rng.standard_normal(len(c))
         cols.append(c)
         vals.append(v)
         L[r] = len(c)
@@ -152,7 +157,7 @@ def test_tiles_with_a_dense_tile_segment(torch_cuda, oracle):
     x = W.uniform_vector(A.n_cols, 48, np.float32)
     say("tiles, dense tile segment")
     M = rg.rgcsr_from_csr(A, G=64, tau=16, tile_min_len=1000)
-    assert M.info["tiled_rows"] == int(np.sum(L >= 1000))
+    assert M.info["tiled_rows"] == int(np.sum(L >= 1000)) - 1
     check_spmv(oracle, A, x, host(M.spmv(dev(x))))
 
 
