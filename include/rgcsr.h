@@ -125,24 +125,30 @@ typedef struct {
                                tiled rows hold at least 262,144 nonzeros.  F64 storage
                                never tiles. */
     int32_t col_panels;     /* 0 (default) = off.  P = 8, 16, ..., 64: the handle also
-                               keeps a copy of the matrix split by column into P panels
-                               of about equal nonzero count, the panels stacked as P
-                               row-compressed matrices (a row's entries in one panel's
-                               columns form one piece; rows without such entries have
-                               none) in the layout above, with each element's CSR index
-                               so rgcsr_set_values refreshes it.  A launch whose x rows
-                               (ldx elements) give at most 3 MiB of x per panel and whose
-                               column block has at most 32 bytes of accumulators per row
-                               (K <= 8 with F32 vectors, K <= 4 with F64) runs on the
-                               copy: panel q's workgroups run on XCD (q * 8 / P) of the
-                               eight, so each XCD's L2 keeps that panel's slice of x (the
-                               x reuse through a cache that Section 4.3 studies), write
-                               one sum per piece to a device buffer of the handle, and a
-                               second kernel adds each row's piece sums in panel order
-                               (deterministic).  Other launches use the layout itself.
-                               The copy doubles the stored matrix and adds 32 bytes per
-                               piece.  Host conversion only (device inputs are copied
-                               to the host); rgcsr_plan_from_csr and batches return
+                               keeps a copy of the matrix for launches of several
+                               right-hand sides.  The columns are split into P panels
+                               of about equal nonzero count; a row longer than
+                               long_row_threshold (every row when that is negative) is
+                               split into pieces, its entries in one panel's columns,
+                               and the other rows stay whole.  The pieces of each panel
+                               and then the whole rows are laid out as above, with
+                               each element's CSR index so rgcsr_set_values refreshes
+                               the copy.  A launch of 2 or more right-hand sides whose
+                               X rows (ldx elements) give at most 3 MiB of X per panel
+                               and whose column block has at most 32 bytes of
+                               accumulators per row (K <= 8 with F32 vectors, K <= 4
+                               with F64) runs on the copy: panel q's workgroups run on
+                               XCD (q * 8 / P) of the eight, so each XCD's L2 keeps
+                               that panel's slice of X (the x reuse through a cache
+                               that Section 4.3 studies); whole rows, dealt to every
+                               XCD, write their rows of Y, pieces write one sum each
+                               to a device buffer of the handle, and a second kernel
+                               adds each split row's piece sums in panel order
+                               (deterministic).  One vector, and other launches, use
+                               the layout itself.  The copy doubles the stored matrix
+                               and adds 32 bytes per piece.  Host conversion only
+                               (device inputs are copied to the host);
+                               rgcsr_plan_from_csr and batches return
                                RGCSR_EUNSUPPORTED. */
 } rgcsr_opts;
 

@@ -131,13 +131,13 @@ struct rgcsr_matrix_s {
     rgcsr_matrix_s *PN = nullptr;
     int32_t n_panels = 0;
     int64_t panel_cols = 0;                    // widest panel, in columns
-    int64_t n_out_rows = 0;                    // rows of the matrix the pieces add up to
+    int64_t n_split = 0;                       // rows split into pieces (the others are written whole)
     int32_t *unit_map_rows = nullptr;          // [n_map_rows] workgroup -> unit, rows-per-lane schedule
     int32_t *unit_map_one = nullptr;           // [n_map_one] workgroup -> unit, one row per lane
     int32_t n_map_rows = 0, n_map_one = 0;
-    int32_t *pan_vptr = nullptr, *pan_vidx = nullptr;  // pieces of each output row, in panel order
-    void *pan_y = nullptr;                     // [pieces * kPanelRowBytes] per-piece sums
-    std::shared_ptr<std::vector<int32_t>> pending_maps[4];  // host copies until they are uploaded
+    int32_t *pan_crow = nullptr, *pan_cptr = nullptr, *pan_vidx = nullptr;  // split rows and their pieces
+    void *pan_y = nullptr;                     // [split pieces * kPanelRowBytes] per-piece sums
+    std::shared_ptr<std::vector<int32_t>> pending_maps[5];  // host copies until they are uploaded
 };
 
 struct hyb_matrix_s {
@@ -380,20 +380,22 @@ rgcsr_matrix_s *prepare_handle(const HostLayout &L, bool with_row_ptr, const Hos
             // each output row, and the per-piece sums
             h->n_panels = pb->P;
             for (int32_t q = 0; q < pb->P; q++) h->panel_cols = std::max(h->panel_cols, pb->cb[q + 1] - pb->cb[q]);
-            h->n_out_rows = (int64_t)pb->vptr.size() - 1;
+            h->n_split = (int64_t)pb->crow.size();
             auto rows = std::make_shared<std::vector<int32_t>>(panel_unit_map(h, L, *pb, true));
             auto one = std::make_shared<std::vector<int32_t>>(panel_unit_map(h, L, *pb, false));
             h->n_map_rows = (int32_t)rows->size();
             h->n_map_one = (int32_t)one->size();
             a.add(&h->unit_map_rows, rows->size());
             a.add(&h->unit_map_one, one->size());
-            a.add(&h->pan_vptr, pb->vptr.size());
+            a.add(&h->pan_crow, pb->crow.size());
+            a.add(&h->pan_cptr, pb->cptr.size());
             a.add(&h->pan_vidx, pb->vidx.size());
-            a.add((uint8_t **)&h->pan_y, (size_t)L.n_rows * kPanelRowBytes);
+            a.add((uint8_t **)&h->pan_y, (size_t)pb->split_pieces * kPanelRowBytes);
             h->pending_maps[0] = rows;
             h->pending_maps[1] = one;
-            h->pending_maps[2] = std::make_shared<std::vector<int32_t>>(pb->vptr);
-            h->pending_maps[3] = std::make_shared<std::vector<int32_t>>(pb->vidx);
+            h->pending_maps[2] = std::make_shared<std::vector<int32_t>>(pb->crow);
+            h->pending_maps[3] = std::make_shared<std::vector<int32_t>>(pb->cptr);
+            h->pending_maps[4] = std::make_shared<std::vector<int32_t>>(pb->vidx);
         }
         h->bytes = a.total;
     } catch (...) {
@@ -432,8 +434,8 @@ void place_and_upload(rgcsr_matrix_s *h, Arena &a, const HostLayout &L, const st
         if (map->long_nnz) HIPCHK(hipMemcpyAsync(h->t_map_long, map->long_val.data(), (size_t)map->long_nnz * 4, hipMemcpyHostToDevice, st));
     }
     if (h->pending_tiles) upload_tiles(h, *h->pending_tiles, L.long_row, st);
-    int32_t *const map_dst[4] = {h->unit_map_rows, h->unit_map_one, h->pan_vptr, h->pan_vidx};
-    for (int i = 0; i < 4; i++)
+    int32_t *const map_dst[5] = {h->unit_map_rows, h->unit_map_one, h->pan_crow, h->pan_cptr, h->pan_vidx};
+    for (int i = 0; i < 5; i++)
         if (h->pending_maps[i]) upload(map_dst[i], *h->pending_maps[i], st);
     HIPCHK(hipStreamSynchronize(st));
     h->pending_tiles.reset();
@@ -583,8 +585,9 @@ int32_t short_waves(const rgcsr_matrix_s *h, bool scheduled) {
 // forms them (block items, then wavefront items four to a unit); each unit
 // belongs to the panel of its first item.  The hardware deals workgroup b to
 // XCD b % 8, so panel q's units go to the workgroups b with b % 8 == q * 8 / P
-// in unit order (long-row units first, as in every launch), and -1 fills the
-// tail of XCDs with fewer units than the busiest one.
+// in unit order (long-row units first, as in every launch); the units of the
+// whole rows (index P) are dealt to the XCDs in turn, after the panels' own;
+// -1 fills the tail of XCDs with fewer units than the busiest one.
 std::vector<int32_t> panel_unit_map(const rgcsr_matrix_s *h, const HostLayout &L, const PanelBuilt &pb,
                                     bool use_rows) {
     const int64_t n_block = h->n_block, n_wave_long = h->n_wave_long;
@@ -594,7 +597,8 @@ std::vector<int32_t> panel_unit_map(const rgcsr_matrix_s *h, const HostLayout &L
         return (int32_t)(std::upper_bound(off.begin() + 1, off.end(), i) - (off.begin() + 1));
     };
     const int32_t R = use_rows ? h->R : 1;
-    std::vector<std::vector<int32_t>> per(kPanelXcds);
+    std::vector<std::vector<int32_t>> per(kPanelXcds), whole(kPanelXcds);
+    int64_t n_whole = 0;
     for (int64_t u = 0; u < units; u++) {
         int32_t q;
         if (u < n_block) {
@@ -614,8 +618,12 @@ std::vector<int32_t> panel_unit_map(const rgcsr_matrix_s *h, const HostLayout &L
                 q = panel_in(pb.grp_off, g);
             }
         }
-        per[(size_t)q * kPanelXcds / pb.P].push_back((int32_t)u);
+        if (q < pb.P)
+            per[(size_t)q * kPanelXcds / pb.P].push_back((int32_t)u);
+        else
+            whole[n_whole++ % kPanelXcds].push_back((int32_t)u);
     }
+    for (int x = 0; x < kPanelXcds; x++) per[x].insert(per[x].end(), whole[x].begin(), whole[x].end());
     size_t longest = 0;
     for (auto &v : per) longest = std::max(longest, v.size());
     if (longest * kPanelXcds > (size_t)INT32_MAX / 2) fail(RGCSR_EOVERFLOW, "too many workgroups");
@@ -676,14 +684,17 @@ int vec_is_f64(rgcsr_dtype vt) {
     fail(RGCSR_EUNSUPPORTED, "vectors must be F32 or F64");
 }
 
-// The panel copy serves launches whose per-piece sums fit the buffer
-// (K accumulators of kPanelRowBytes at most) and whose x slice per panel
-// (panel columns times the X row stride) fits kPanelSliceBytes.
+// The panel copy serves launches of several right-hand sides whose
+// per-piece sums fit the buffer (K accumulators of kPanelRowBytes at most)
+// and whose X slice per panel (panel columns times the X row stride) fits
+// kPanelSliceBytes.  One vector stays on the layout, whose column tiles
+// keep the long rows' x in LDS (and whose kernels store without the
+// per-piece output codes).
 bool panel_slice_ok(const rgcsr_matrix_s *h, int64_t ldx, int f64) {
     return h->PN && h->PN->panel_cols * ldx * (f64 ? 8 : 4) <= kPanelSliceBytes;
 }
 bool panel_launch_ok(const rgcsr_matrix_s *h, int K, int64_t ldx, int f64) {
-    return panel_slice_ok(h, ldx, f64) && K * (f64 ? 8 : 4) <= kPanelRowBytes;
+    return K > 1 && panel_slice_ok(h, ldx, f64) && K * (f64 ? 8 : 4) <= kPanelRowBytes;
 }
 
 void spmv_launch(const rgcsr_matrix_s *h, int K, const void *X, int64_t ldx, void *Y, int64_t ldy, int f64,
@@ -706,8 +717,8 @@ void spmv_launch(const rgcsr_matrix_s *h, int K, const void *X, int64_t ldx, voi
         // pieces of panel q on XCD q * 8 / P, their sums to the piece buffer
         P.unit_map = rows ? pn->unit_map_rows : pn->unit_map_one;
         P.n_map = rows ? pn->n_map_rows : pn->n_map_one;
-        P.y = pn->pan_y;
-        P.ldy = K;
+        P.pan_y = pn->pan_y;
+        P.pan_ld = K;
         nwg = P.n_map;
     }
     // a persistent launch (several right-hand sides only) keeps two 256-thread
@@ -732,11 +743,11 @@ void spmv_launch(const rgcsr_matrix_s *h, int K, const void *X, int64_t ldx, voi
             if (e != hipSuccess) fail(RGCSR_EHIP, std::string("spmv launch: ") + hipGetErrorString(e));
         }
         if (pn->n_combine) {
-            e = launch_combine(pn->combine, (int32_t)pn->n_combine, pn->long_row, pn->partial, pn->pan_y, K, f64, K,
-                               st);
+            e = launch_combine(pn->combine, (int32_t)pn->n_combine, pn->long_row, pn->partial, Y, ldy, pn->pan_y, K,
+                               f64, K, st);
             if (e != hipSuccess) fail(RGCSR_EHIP, std::string("combine launch: ") + hipGetErrorString(e));
         }
-        e = launch_panel_combine(pn->pan_vptr, pn->pan_vidx, h->n_rows, pn->pan_y, Y, ldy, f64, K, st);
+        e = launch_panel_combine(pn->pan_crow, pn->pan_cptr, pn->n_split, pn->pan_vidx, pn->pan_y, Y, ldy, f64, K, st);
         if (e != hipSuccess) fail(RGCSR_EHIP, std::string("panel combine launch: ") + hipGetErrorString(e));
         return;
     }
@@ -759,7 +770,7 @@ void spmv_launch(const rgcsr_matrix_s *h, int K, const void *X, int64_t ldx, voi
     const int64_t n_comb = tiled ? h->n_rest_combine : h->n_combine;
     if (n_comb) {
         e = launch_combine(tiled ? h->rest_combine : h->combine, (int32_t)n_comb, h->long_row, h->partial, Y, ldy,
-                           f64, K, st);
+                           nullptr, 0, f64, K, st);
         if (e != hipSuccess) fail(RGCSR_EHIP, std::string("combine launch: ") + hipGetErrorString(e));
     }
 }
@@ -808,6 +819,8 @@ rgcsr_status rgcsr_from_csr(int64_t n_rows, int64_t n_cols, int64_t nnz, const i
     check_dtype(vals_dtype, "vals");
     if (n_rows < 0 || n_cols < 0 || nnz < 0) fail(RGCSR_EINVAL, "negative size");
     check_panels(o.col_panels);
+    if (o.col_panels && o.value_dtype != RGCSR_F32 && o.value_dtype != RGCSR_F64)
+        fail(RGCSR_EUNSUPPORTED, "col_panels serves several right-hand sides, which need F32 or F64 stored values");
     hipStream_t st = (hipStream_t)stream;
     std::vector<int64_t> h_rp;
     std::vector<int32_t> h_col;
@@ -857,7 +870,9 @@ rgcsr_status rgcsr_from_csr(int64_t n_rows, int64_t n_cols, int64_t nnz, const i
             std::vector<uint8_t> conv((size_t)rp[n_rows] * esz);
             if (rp[n_rows]) convert_values(val, vals_dtype, conv.data(), o.value_dtype, rp[n_rows]);
             PanelBuilt pb;
-            build_panels(pb, p, o.value_dtype, o.col_panels, n_rows, n_cols, rp, col, conv.data());
+            // rows up to the long-row threshold stay whole (all rows are
+            // split when there is none)
+            build_panels(pb, p, o.value_dtype, o.col_panels, p.tau, n_rows, n_cols, rp, col, conv.data());
             h->n_panels = o.col_panels;
             h->PN = make_device(pb.LP, nullptr, &pb.LPmap, st, o.rows_per_lane, o.pad_loads, o.load_policy, 0, &pb);
         }
@@ -1255,7 +1270,8 @@ rgcsr_matrix_s *clone_handle(const rgcsr_matrix_s *A, hipStream_t st) {
                &rgcsr_matrix_s::long_ptr, &rgcsr_matrix_s::long_val, &rgcsr_matrix_s::partial,
                &rgcsr_matrix_s::row_ptr, &rgcsr_matrix_s::t_map_slot,
                &rgcsr_matrix_s::t_map_long, &rgcsr_matrix_s::unit_map_rows, &rgcsr_matrix_s::unit_map_one,
-               &rgcsr_matrix_s::pan_vptr, &rgcsr_matrix_s::pan_vidx, &rgcsr_matrix_s::pan_y);
+               &rgcsr_matrix_s::pan_crow, &rgcsr_matrix_s::pan_cptr, &rgcsr_matrix_s::pan_vidx,
+               &rgcsr_matrix_s::pan_y);
         // tile arrays: in the same block, or in a block of their own
         auto tile_rebase = [&](void *rgcsr_matrix_s::*block) {
             rebase(h, A, block, &rgcsr_matrix_s::tile_units, &rgcsr_matrix_s::tile_ptr, &rgcsr_matrix_s::tile_dst,

@@ -215,21 +215,27 @@ struct Built {
 // of about equal nonzero count, panel q holding columns [cb[q], cb[q+1]).
 // The panels are stacked as P row-compressed matrices: piece v of panel q is
 // the entries of one row in the panel's columns (in CSR order), pieces of a
-// panel in ascending row order, panel after panel.  LP lays the stack out
-// like any matrix (each panel appended as one matrix of a batch, so groups
-// and the long-row list never mix panels and columns stay global); LPmap is
-// the same layout whose "values" are the CSR index of each element (-1 for
-// padding).  Output row r is the sum of its pieces vidx[vptr[r] ..
-// vptr[r + 1]) in panel order; rows without entries have none.
+// panel in ascending row order, panel after panel; rows of at most whole_max
+// nonzeros (empty rows included) are not split but form a last matrix
+// (index P) of whole rows, one piece each, with all columns.  LP lays the
+// stack out like any matrix (each panel appended as one matrix of a batch,
+// so groups and the long-row list never mix panels and columns stay
+// global); its output row codes are the row itself for a whole row and
+// -1 - v for piece v of a split row (a slot of the per-piece sums, pieces in
+// panel order).  LPmap is the same layout whose "values" are the CSR index
+// of each element (-1 for padding).  Split row crow[i] is the sum of its
+// pieces vidx[cptr[i] .. cptr[i + 1]) in panel order.
 // ---------------------------------------------------------------------------
 struct PanelBuilt {
     int32_t P = 0;
     std::vector<int64_t> cb;        // [P+1] panel column bounds
     HostLayout LP, LPmap;
-    std::vector<int64_t> grp_off;   // [P+1] first row group of each panel in LP
-    std::vector<int64_t> long_off;  // [P+1] first long row of each panel in LP
-    std::vector<int32_t> vptr;      // [n_rows+1]
-    std::vector<int32_t> vidx;      // [pieces] piece index (row of LP)
+    std::vector<int64_t> grp_off;   // [P+2] first row group of each panel (then of the whole rows) in LP
+    std::vector<int64_t> long_off;  // [P+2] first long row of each panel (then of the whole rows) in LP
+    std::vector<int32_t> crow;      // [split rows] row of each split row
+    std::vector<int32_t> cptr;      // [split rows + 1] its pieces in vidx
+    std::vector<int32_t> vidx;      // [pieces of split rows] piece index (row of LP)
+    int64_t split_pieces = 0;       // pieces of split rows: LP rows [0, split_pieces)
 };
 
 constexpr int kPanelMax = 64;            // panels per handle
@@ -240,8 +246,8 @@ constexpr int64_t kPanelSliceBytes = 3 << 20;  // x slice of one panel that one 
 // Builds the panel layouts of one CSR matrix whose values are already in the
 // storage dtype (esz bytes each); throws RGCSR_EOVERFLOW when the pieces or
 // the nonzeros do not fit 32-bit indices.
-void build_panels(PanelBuilt &B, const LayoutParams &p, int vdt, int32_t P, int64_t n_rows, int64_t n_cols,
-                  const int64_t *rp, const int32_t *col, const uint8_t *vals);
+void build_panels(PanelBuilt &B, const LayoutParams &p, int vdt, int32_t P, int64_t whole_max, int64_t n_rows,
+                  int64_t n_cols, const int64_t *rp, const int32_t *col, const uint8_t *vals);
 
 // Host layout of `count` CSR matrices (a block-diagonal batch when count > 1)
 // with values converted to vdt; the CSR row pointers when keep_map or

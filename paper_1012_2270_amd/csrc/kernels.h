@@ -53,9 +53,13 @@ struct SpmvParams {
     const int32_t *tile_dst;     // [long_nnz]
     void *tile_vals;             // [tile entries] storage dtype
     // column panels: workgroup (or, in a persistent launch, table entry) j
-    // runs unit unit_map[j], none when -1; null = the usual unit order
+    // runs unit unit_map[j], none when -1; null = the usual unit order.  A
+    // negative output row code -1 - s (short_row, long_row) names slot s of
+    // pan_y (pan_ld elements per slot) instead of a row of y.
     const int32_t *unit_map;     // [n_map]
     int32_t n_map;
+    void *pan_y;
+    int64_t pan_ld;
     // vectors
     const void *x;
     void *y;
@@ -80,12 +84,13 @@ enum { kScalPQ = 0, kScalRRNew = 1, kScalRRInit = 2, kScalOut = 3 };
 constexpr int kRunsRowBytes = 16;
 hipError_t launch_spmv(const SpmvParams &P, int vdt, int vec_f64, int T, int K, int R, int load_policy, int nwg,
                        hipStream_t st);
-// Y[r] = sum of the piece sums yv[vidx[s]] (K values each) for s in
-// [vptr[r], vptr[r + 1]), in that order; 0 for a row without pieces.
-hipError_t launch_panel_combine(const int32_t *vptr, const int32_t *vidx, int64_t n_rows, const void *yv, void *Y,
-                                int64_t ldy, int vec_f64, int K, hipStream_t st);
+// Split rows of a column-panel copy: Y[crow[i]] = sum of the piece sums
+// yv[vidx[s]] (K values each) for s in [cptr[i], cptr[i + 1]), in that order
+// (0 for a row without pieces).
+hipError_t launch_panel_combine(const int32_t *crow, const int32_t *cptr, int64_t n, const int32_t *vidx,
+                                const void *yv, void *Y, int64_t ldy, int vec_f64, int K, hipStream_t st);
 hipError_t launch_combine(const LongItem *items, int32_t n, const int32_t *long_row, const void *partial, void *Y,
-                          int64_t ldy, int vec_f64, int K, hipStream_t st);
+                          int64_t ldy, void *pan_y, int64_t pan_ld, int vec_f64, int K, hipStream_t st);
 hipError_t launch_setval(const SpmvParams &P, int vdt, int T, const void *theta, int theta_f64,
                          const int64_t *row_ptr, hipStream_t st);
 hipError_t launch_gather_map(int64_t n, int vdt, const int32_t *map, const void *theta, int theta_f64,

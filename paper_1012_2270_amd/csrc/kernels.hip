@@ -138,6 +138,16 @@ template <class A, int K> __device__ __forceinline__ void store_row(A *p, const 
     }
 }
 
+// Output of a row code: a row of Y when the code is >= 0; a negative code
+// -1 - s names slot s of the per-piece sums of a column-panel copy, which
+// only launches with several right-hand sides use (single-vector kernels
+// store to Y without the select).
+template <int K, class A>
+__device__ __forceinline__ A *out_row(A *Y, int64_t ldy, void *pan, int64_t pan_ld, int32_t code) {
+    if constexpr (K == 1) return Y + (int64_t)code * ldy;
+    else return code >= 0 ? Y + (int64_t)code * ldy : (A *)pan + (int64_t)(-1 - code) * pan_ld;
+}
+
 __device__ __forceinline__ float fmaA(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
 __device__ __forceinline__ double fmaA(double a, double b, double c) { return __builtin_fma(a, b, c); }
 
@@ -375,7 +385,7 @@ __device__ __forceinline__ void spmv_groups_uniform(const SpmvParams &P, int32_t
 #pragma unroll
                 for (int k = 0; k < K; k++) acc[r][k] += __shfl_xor(acc[r][k], off);
         }
-        if (ok[r] && q == 0) store_row<A, K>(Y + (int64_t)orow[r] * P.ldy, acc[r]);
+        if (ok[r] && q == 0) store_row<A, K>(out_row<K>(Y, P.ldy, P.pan_y, P.pan_ld, orow[r]), acc[r]);
     }
 }
 
@@ -424,8 +434,8 @@ __device__ __forceinline__ void spmv_groups_lane(const SpmvParams &P, int32_t w,
             for (int k = 0; k < K; k++) acc[k] += __shfl_xor(acc[k], off);
     }
     if (L.ok && L.q == 0) {
-        const int64_t row = P.perm ? (int64_t)P.short_row[L.i] : L.i;
-        store_row<A, K>(Y + row * P.ldy, acc);
+        const int32_t row = P.perm ? P.short_row[L.i] : (int32_t)L.i;
+        store_row<A, K>(out_row<K>(Y, P.ldy, P.pan_y, P.pan_ld, row), acc);
     }
 }
 
@@ -532,7 +542,7 @@ __device__ __forceinline__ void spmv_wave_long(const SpmvParams &P, int32_t w, i
         if (off < TL)
 #pragma unroll
             for (int k = 0; k < K; k++) acc[k] += __shfl_xor(acc[k], off);
-    if (ok && q == 0) store_row<A, K>(Y + (int64_t)orow * P.ldy, acc);
+    if (ok && q == 0) store_row<A, K>(out_row<K>(Y, P.ldy, P.pan_y, P.pan_ld, orow), acc);
 }
 
 // Same work item, single right-hand side: the item's nonzeros (at most
@@ -636,7 +646,7 @@ __device__ __forceinline__ void spmv_block_item(const SpmvParams &P, int32_t u, 
         A tot = A(0);
         for (int i = 0; i < kBlockWaves; i++) tot += red[i][k];
         if (it.c == 1)
-            Y[(int64_t)ldc(P.long_row, li) * P.ldy + k] = tot;
+            out_row<K>(Y, P.ldy, P.pan_y, P.pan_ld, ldc(P.long_row, li))[k] = tot;
         else
             ((A *)P.partial)[((int64_t)it.d + it.b) * K + k] = tot;
     }
@@ -730,23 +740,35 @@ __global__ __launch_bounds__(kBlockThreads) void rgcsr_spmv_k(SpmvParams P) {
     }
 }
 
-// Column panels: each output row adds its pieces' sums yv[vidx[s]] for s in
-// [vptr[r], vptr[r + 1]), in panel order.  The sums are stored by piece, in
-// panel order, so each XCD writes whole lines of its own.
+// Column panels: each split row crow[i] adds its pieces' sums yv[vidx[s]]
+// for s in [cptr[i], cptr[i + 1]), in panel order.  The sums are stored by
+// piece, in panel order, so each XCD writes whole lines of its own.
 template <class A, int K>
-__global__ __launch_bounds__(256) void panel_combine_k(const int32_t *vptr, const int32_t *vidx, int64_t n_rows,
-                                                       const A *yv, A *Y, int64_t ldy) {
-    const int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (r >= n_rows) return;
-    const int32_t s0 = vptr[r], s1 = vptr[r + 1];
+__global__ __launch_bounds__(256) void panel_combine_k(const int32_t *crow, const int32_t *cptr, int64_t n,
+                                                       const int32_t *vidx, const A *yv, A *Y, int64_t ldy) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    const int64_t r = crow[i];
+    const int32_t s0 = cptr[i], m = cptr[i + 1] - s0;  // pieces of this row
     A acc[K];
 #pragma unroll
     for (int k = 0; k < K; k++) acc[k] = A(0);
-    for (int32_t s = s0; s < s1; s++) {
-        A v[K];
-        load_row<A, K>(yv + (int64_t)vidx[s] * K, v);
+    // a split row has about one piece per panel: eight pieces per pass, their
+    // indices and then their sums loaded together (steps past the row's
+    // pieces re-read its first piece, which exists whenever the loop runs),
+    // added in panel order
+    constexpr int U = 8;
+    for (int32_t b = 0; b < m; b += U) {
+        int32_t id[U];
 #pragma unroll
-        for (int k = 0; k < K; k++) acc[k] += v[k];
+        for (int u = 0; u < U; u++) id[u] = vidx[s0 + (b + u < m ? b + u : 0)];
+        A v[U][K];
+#pragma unroll
+        for (int u = 0; u < U; u++) load_row<A, K>(yv + (int64_t)id[u] * K, v[u]);
+#pragma unroll
+        for (int u = 0; u < U; u++)
+#pragma unroll
+            for (int k = 0; k < K; k++) acc[k] = b + u < m ? acc[k] + v[u][k] : acc[k];
     }
     store_row<A, K>(Y + r * ldy, acc);
 }
@@ -754,7 +776,7 @@ __global__ __launch_bounds__(256) void panel_combine_k(const int32_t *vptr, cons
 // Rows split over several block items: add the chunk partial sums in order.
 template <class A, int K>
 __global__ __launch_bounds__(256) void combine_k(const LongItem *items, int32_t n, const int32_t *long_row,
-                                                 const A *partial, A *Y, int64_t ldy) {
+                                                 const A *partial, A *Y, int64_t ldy, void *pan_y, int64_t pan_ld) {
     const int32_t i = blockIdx.x * 256 + threadIdx.x;
     if (i >= n) return;
     const LongItem it = items[i];
@@ -764,7 +786,7 @@ __global__ __launch_bounds__(256) void combine_k(const LongItem *items, int32_t 
     for (int c = 0; c < it.c; c++)
 #pragma unroll
         for (int k = 0; k < K; k++) tot[k] += partial[((int64_t)it.d + c) * K + k];
-    store_row<A, K>(Y + (int64_t)long_row[it.a] * ldy, tot);
+    store_row<A, K>(out_row<K>(Y, ldy, pan_y, pan_ld, long_row[it.a]), tot);
 }
 
 // ---------------------------------------------------------------------------
@@ -1301,52 +1323,53 @@ static hipError_t launch_spmv_vk(const SpmvParams &P, int T, int K, int R, int n
 
 template <class A, int K>
 static hipError_t launch_combine_k(const LongItem *items, int32_t n, const int32_t *long_row, const void *partial,
-                                   void *Y, int64_t ldy, hipStream_t st) {
+                                   void *Y, int64_t ldy, void *pan_y, int64_t pan_ld, hipStream_t st) {
     hipLaunchKernelGGL((combine_k<A, K>), dim3((n + 255) / 256), dim3(256), 0, st, items, n, long_row,
-                       (const A *)partial, (A *)Y, ldy);
+                       (const A *)partial, (A *)Y, ldy, pan_y, pan_ld);
     return check_launch();
 }
 
 template <class A>
 static hipError_t launch_combine_a(const LongItem *items, int32_t n, const int32_t *long_row, const void *partial,
-                                   void *Y, int64_t ldy, int K, hipStream_t st) {
+                                   void *Y, int64_t ldy, void *pan_y, int64_t pan_ld, int K, hipStream_t st) {
     switch (K) {
-    case 1: return launch_combine_k<A, 1>(items, n, long_row, partial, Y, ldy, st);
-    case 2: return launch_combine_k<A, 2>(items, n, long_row, partial, Y, ldy, st);
-    case 4: return launch_combine_k<A, 4>(items, n, long_row, partial, Y, ldy, st);
-    case 8: return launch_combine_k<A, 8>(items, n, long_row, partial, Y, ldy, st);
-    case 16: return launch_combine_k<A, 16>(items, n, long_row, partial, Y, ldy, st);
-    case 32: return launch_combine_k<A, 32>(items, n, long_row, partial, Y, ldy, st);
+    case 1: return launch_combine_k<A, 1>(items, n, long_row, partial, Y, ldy, pan_y, pan_ld, st);
+    case 2: return launch_combine_k<A, 2>(items, n, long_row, partial, Y, ldy, pan_y, pan_ld, st);
+    case 4: return launch_combine_k<A, 4>(items, n, long_row, partial, Y, ldy, pan_y, pan_ld, st);
+    case 8: return launch_combine_k<A, 8>(items, n, long_row, partial, Y, ldy, pan_y, pan_ld, st);
+    case 16: return launch_combine_k<A, 16>(items, n, long_row, partial, Y, ldy, pan_y, pan_ld, st);
+    case 32: return launch_combine_k<A, 32>(items, n, long_row, partial, Y, ldy, pan_y, pan_ld, st);
     }
     return hipErrorInvalidValue;
 }
 
 template <class A>
-static hipError_t launch_panel_combine_a(const int32_t *vptr, const int32_t *vidx, int64_t n, const A *yv, A *Y,
-                                         int64_t ldy, int K, hipStream_t st) {
+static hipError_t launch_panel_combine_a(const int32_t *crow, const int32_t *cptr, int64_t n, const int32_t *vidx,
+                                         const A *yv, A *Y, int64_t ldy, int K, hipStream_t st) {
     const dim3 g((unsigned)((n + 255) / 256)), b(256);
     switch (K) {
-    case 1: hipLaunchKernelGGL((panel_combine_k<A, 1>), g, b, 0, st, vptr, vidx, n, yv, Y, ldy); break;
-    case 2: hipLaunchKernelGGL((panel_combine_k<A, 2>), g, b, 0, st, vptr, vidx, n, yv, Y, ldy); break;
-    case 4: hipLaunchKernelGGL((panel_combine_k<A, 4>), g, b, 0, st, vptr, vidx, n, yv, Y, ldy); break;
-    case 8: hipLaunchKernelGGL((panel_combine_k<A, 8>), g, b, 0, st, vptr, vidx, n, yv, Y, ldy); break;
+    case 1: hipLaunchKernelGGL((panel_combine_k<A, 1>), g, b, 0, st, crow, cptr, n, vidx, yv, Y, ldy); break;
+    case 2: hipLaunchKernelGGL((panel_combine_k<A, 2>), g, b, 0, st, crow, cptr, n, vidx, yv, Y, ldy); break;
+    case 4: hipLaunchKernelGGL((panel_combine_k<A, 4>), g, b, 0, st, crow, cptr, n, vidx, yv, Y, ldy); break;
+    case 8: hipLaunchKernelGGL((panel_combine_k<A, 8>), g, b, 0, st, crow, cptr, n, vidx, yv, Y, ldy); break;
     default: return hipErrorInvalidValue;
     }
     return check_launch();
 }
 
-hipError_t launch_panel_combine(const int32_t *vptr, const int32_t *vidx, int64_t n_rows, const void *yv, void *Y,
-                                int64_t ldy, int vec_f64, int K, hipStream_t st) {
-    if (n_rows == 0) return hipSuccess;
-    if (vec_f64) return launch_panel_combine_a<double>(vptr, vidx, n_rows, (const double *)yv, (double *)Y, ldy, K, st);
-    return launch_panel_combine_a<float>(vptr, vidx, n_rows, (const float *)yv, (float *)Y, ldy, K, st);
+hipError_t launch_panel_combine(const int32_t *crow, const int32_t *cptr, int64_t n, const int32_t *vidx,
+                                const void *yv, void *Y, int64_t ldy, int vec_f64, int K, hipStream_t st) {
+    if (n == 0) return hipSuccess;
+    if (vec_f64)
+        return launch_panel_combine_a<double>(crow, cptr, n, vidx, (const double *)yv, (double *)Y, ldy, K, st);
+    return launch_panel_combine_a<float>(crow, cptr, n, vidx, (const float *)yv, (float *)Y, ldy, K, st);
 }
 
 hipError_t launch_combine(const LongItem *items, int32_t n, const int32_t *long_row, const void *partial, void *Y,
-                          int64_t ldy, int vec_f64, int K, hipStream_t st) {
+                          int64_t ldy, void *pan_y, int64_t pan_ld, int vec_f64, int K, hipStream_t st) {
     if (n == 0) return hipSuccess;
-    if (vec_f64) return launch_combine_a<double>(items, n, long_row, partial, Y, ldy, K, st);
-    return launch_combine_a<float>(items, n, long_row, partial, Y, ldy, K, st);
+    if (vec_f64) return launch_combine_a<double>(items, n, long_row, partial, Y, ldy, pan_y, pan_ld, K, st);
+    return launch_combine_a<float>(items, n, long_row, partial, Y, ldy, pan_y, pan_ld, K, st);
 }
 
 hipError_t launch_spmv(const SpmvParams &P, int vdt, int vec_f64, int T, int K, int R, int load_policy, int nwg,

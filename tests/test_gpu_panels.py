@@ -32,9 +32,11 @@ def zipf():
     return A, x
 
 
-def pieces(A, P):
+def pieces(A, P, whole_max=LAY["tau"]):
     """Pieces of the panel split, counted on the host from the same rule
-    (bounds at the columns where the running nonzero count reaches q*nnz/P)."""
+    (bounds at the columns where the running nonzero count reaches q*nnz/P;
+    rows of at most whole_max nonzeros, empty ones included, stay whole, one
+    piece each)."""
     # cnt[i]: nonzeros in the columns before column i
     cnt = np.concatenate([[0], np.bincount(A.col, minlength=A.n_cols).cumsum()])
     cb = [0]
@@ -42,9 +44,11 @@ def pieces(A, P):
         t = (A.nnz * q + P - 1) // P
         cb.append(max(cb[-1], min(int(np.searchsorted(cnt, t)), A.n_cols)))
     cb.append(A.n_cols)
+    L = np.diff(A.row_ptr)
+    rows = np.repeat(np.arange(A.n_rows), L)
     pan = np.searchsorted(np.asarray(cb[1:]), A.col, side="right")
-    rows = np.repeat(np.arange(A.n_rows), np.diff(A.row_ptr))
-    return int(np.unique(rows.astype(np.int64) * P + pan).size)
+    split = np.repeat(L > whole_max, L)
+    return int(np.unique(rows[split].astype(np.int64) * P + pan[split]).size) + int(np.sum(L <= whole_max))
 
 
 def nan_out(torch, n, k=None, dtype=None):
@@ -54,20 +58,63 @@ def nan_out(torch, n, k=None, dtype=None):
 
 
 @pytest.mark.parametrize("P", [8, 16, 64])
-@pytest.mark.parametrize("dt", ["f32", "bf16", "f16"])
-def test_panel_spmv_parity(torch_cuda, oracle, zipf, P, dt):
+@pytest.mark.parametrize("vdt", ["f32", "f64"])
+def test_panel_spmm_parity_panels(torch_cuda, oracle, zipf, P, vdt):
+    """Two right-hand sides on the copy, deterministic; one vector runs on the
+    layout itself and gives the same bits as a handle without the copy."""
+    torch = torch_cuda
     A, x = zipf
-    say("panels spmv", P, dt)
-    M = rg.rgcsr_from_csr(A, col_panels=P, value_dtype=dt, **LAY)
+    say("panels", P, vdt)
+    B = A if vdt == "f32" else W.CSR(A.n_rows, A.n_cols, A.row_ptr, A.col, A.val.astype(np.float64))
+    M = rg.rgcsr_from_csr(B, col_panels=P, value_dtype=vdt, **LAY)
     assert M.info["col_panels"] == P and M.info["panel_pieces"] == pieces(A, P)
-    y = nan_out(torch_cuda, A.n_rows)
+    dt = torch.float32 if vdt == "f32" else torch.float64
+    X = W.uniform_matrix(A.n_cols, 2, 62).astype(np.float32 if vdt == "f32" else np.float64)
+    Y = nan_out(torch, A.n_rows, 2, dtype=dt)
+    rg.rgcsr_spmv_batched(M, dev(X), Y)
+    Yh = host(Y)
+    B64 = W.CSR(A.n_rows, A.n_cols, A.row_ptr, A.col, B.val.astype(np.float64))
+    ref = oracle.csr_spmm(B64, X.astype(np.float64))
+    tol = TOL_F32 if vdt == "f32" else TOL_F64
+    for c in range(2):
+        assert oracle.scaled_error(Yh[:, c], ref[:, c], oracle.csr_absmv(B64, X[:, c].astype(np.float64))) <= tol
+    Y2 = nan_out(torch, A.n_rows, 2, dtype=dt)
+    rg.rgcsr_spmv_batched(M, dev(X), Y2)
+    np.testing.assert_array_equal(host(Y2), Yh)
+    # one vector: the layout's own kernels
+    M0 = rg.rgcsr_from_csr(B, value_dtype=vdt, **LAY)
+    xv = x if vdt == "f32" else x.astype(np.float64)
+    np.testing.assert_array_equal(host(M.spmv(dev(xv))), host(M0.spmv(dev(xv))))
+
+
+@pytest.mark.parametrize("dt", ["bf16", "f16"])
+def test_panel_needs_f32_or_f64_values(torch_cuda, zipf, dt):
+    A, _ = zipf
+    say("panels refuse", dt)
+    with pytest.raises(rg.RgcsrError) as e:
+        rg.rgcsr_from_csr(A, col_panels=8, value_dtype=dt, **LAY)
+    assert e.value.status == 6
+
+
+@pytest.mark.parametrize("tau", [-1, 0, 64])
+def test_panel_whole_row_threshold(torch_cuda, oracle, zipf, tau):
+    """Rows up to the long-row threshold stay whole (tau = -1: every row is
+    split; tau = 0: every row with entries is split too)."""
+    torch = torch_cuda
+    A, x = zipf
+    say("panels tau", tau)
+    M = rg.rgcsr_from_csr(A, col_panels=8, G=64, sigma=512, tau=tau)
+    assert M.info["panel_pieces"] == pieces(A, 8, whole_max=tau)
+    y = nan_out(torch, A.n_rows)
     M.spmv(dev(x), y)
-    y = host(y)
-    check_spmv(oracle, A, x, y, vals64=None if dt == "f32" else storage_values(oracle, A, dt))
-    # deterministic: the same bits again
-    y2 = nan_out(torch_cuda, A.n_rows)
-    M.spmv(dev(x), y2)
-    np.testing.assert_array_equal(host(y2).view(np.uint32), y.view(np.uint32))
+    check_spmv(oracle, A, x, host(y))
+    X = W.uniform_matrix(A.n_cols, 4, 61)
+    Y = nan_out(torch, A.n_rows, 4)
+    rg.rgcsr_spmv_batched(M, dev(X), Y)
+    Yh = host(Y)
+    ref = oracle.csr_spmm(A, X)
+    for c in range(4):
+        assert oracle.scaled_error(Yh[:, c], ref[:, c], oracle.csr_absmv(A, X[:, c])) <= TOL_F32
 
 
 @pytest.mark.parametrize("k", [2, 4, 8, 16, 5])
@@ -107,15 +154,26 @@ def test_panel_f64_vectors(torch_cuda, oracle, zipf, vdt, k):
 
 
 def test_panel_same_as_layout_within_rounding(torch_cuda, oracle, zipf):
-    """The copy and the layout itself sum in different orders; both are
-    within the FP32 bound of the oracle and of each other."""
-    A, x = zipf
+    """The copy and the layout itself sum the split rows in different orders
+    (the whole rows in the same one); both are within the FP32 bound of the
+    oracle and of each other."""
+    torch = torch_cuda
+    A, _ = zipf
     say("panels vs layout")
+    X = W.uniform_matrix(A.n_cols, 4, 63)
     M0 = rg.rgcsr_from_csr(A, **LAY)
     M1 = rg.rgcsr_from_csr(A, col_panels=8, **LAY)
-    y0, y1 = host(M0.spmv(dev(x))), host(M1.spmv(dev(x)))
-    s = oracle.csr_absmv(A, x)
-    assert oracle.scaled_error(y1, y0.astype(np.float64), s) <= 2 * TOL_F32
+    Y0, Y1 = nan_out(torch, A.n_rows, 4), nan_out(torch, A.n_rows, 4)
+    rg.rgcsr_spmv_batched(M0, dev(X), Y0)
+    rg.rgcsr_spmv_batched(M1, dev(X), Y1)
+    Y0h, Y1h = host(Y0), host(Y1)
+    L = np.diff(A.row_ptr)
+    for c in range(4):
+        s = oracle.csr_absmv(A, X[:, c])
+        assert oracle.scaled_error(Y1h[:, c], Y0h[:, c].astype(np.float64), s) <= 2 * TOL_F32
+    # a whole row is one piece summed by the same kernel path: same bits
+    whole = L <= LAY["tau"]
+    np.testing.assert_array_equal(Y1h[whole], Y0h[whole])
 
 
 def test_panel_set_values_and_clone(torch_cuda, oracle, zipf):
