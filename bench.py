@@ -34,7 +34,7 @@ ROTATE_BYTES = 1 << 30
 
 # layouts timed by the benchmark (also used by the full-size parity test)
 LAYOUT_STENCIL = dict(G=64, T=1, sigma=1, tau=-1)          # the paper's layout
-LAYOUT_ZIPF = dict(G=64, T=1, sigma=512, tau=16)  # descending order in windows + long-row path
+LAYOUT_ZIPF = dict(G=64, T=1, sigma=512, tau=6)   # descending order in windows + long-row path (rows > 6)
 
 METRIC = "SpMV GFLOP/s and achieved HBM GB/s (% of peak), RgCSR vs Hybrid, 1 MI355X"
 
@@ -259,12 +259,15 @@ def gather_floor_us(torch, rg, c, reps):
 def bench_spmm(args, torch, rg, W):
     """Multi-RHS SpMM on the Zipf matrix, k in {1, 4, 16, 32}, one launch per k,
     against k sequential single-vector SpMVs; the same with a handle that also
-    keeps the eight-panel column split (col_panels = 8), which the launches
-    use where a panel's slice of X fits one XCD's L2 (k <= 4 here)."""
+    keeps the eight-panel column split (col_panels = 8, rows longer than 12
+    split), which the launches use where a panel's slice of X fits one XCD's
+    L2 (k = 4 here)."""
     import oracle
     A, _ = W.workload_zipf(1_000_000)
     base = rg.rgcsr_from_csr(A, **LAYOUT_ZIPF)
-    pbase = rg.rgcsr_from_csr(A, col_panels=8, **LAYOUT_ZIPF)
+    # the copy splits the rows longer than tau; 12 is the best of a sweep
+    # (4-16) for four right-hand sides, 6 for one vector
+    pbase = rg.rgcsr_from_csr(A, col_panels=8, **dict(LAYOUT_ZIPF, tau=12))
     out = {"metric": "SpMM GFLOP/s and GB/s, Zipf n=1e6, FP32", "results": [],
            "panel_pieces": pbase.info["panel_pieces"]}
 
@@ -471,8 +474,12 @@ def bench_grad(args, torch, rg, W):
     st = float(np.max(s + np.abs(bvec))) * float(np.max(np.abs(x)))
     AT = W.CSR(A.n_cols, A.n_rows, *oracle.csr_transpose(A.astype(np.float64)))
     sx = float(np.max(oracle.csr_absmv(AT, s + np.abs(bvec))))
+    # the step's value updates and dtheta walk every long row by wavefront:
+    # rows over 16 nonzeros on the long-row path keep it fastest (261 us,
+    # 289 us with the single-vector layout's tau = 6)
+    lay = dict(LAYOUT_ZIPF, tau=16)
     for transpose in (True, False):
-        M = rg.rgcsr_from_csr(A, keep_csr_map=True, build_transpose=transpose, **LAYOUT_ZIPF)
+        M = rg.rgcsr_from_csr(A, keep_csr_map=True, build_transpose=transpose, **lay)
         y = torch.empty(A.n_rows, device="cuda:0")
         dx = torch.empty(A.n_cols, device="cuda:0")
         dv = torch.empty(A.nnz, device="cuda:0")
