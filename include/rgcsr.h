@@ -205,6 +205,22 @@ rgcsr_status rgcsr_layout_host(int64_t n_rows, int64_t n_cols, int64_t nnz,
                                int32_t *long_row, int64_t *long_ptr, void *long_val,
                                int32_t *long_col);
 
+/* Sizes of the column-panel copy (rgcsr_opts.col_panels) of a host CSR
+ * matrix under *opts, without a GPU: col_bounds[col_panels + 1] receives the
+ * panel column bounds (panel q holds columns [col_bounds[q],
+ * col_bounds[q + 1]); NULL skips it), *pieces the rows of the copy (one per
+ * whole row, empty rows included, and one per split row and panel holding
+ * some of its entries), *split_rows the rows longer than long_row_threshold
+ * (split), *split_pieces their pieces, *slots and *long_nnz the grouped slots
+ * and long-row nonzeros of the copy's layout (any output may be NULL).
+ * RGCSR_EINVAL when opts is NULL or col_panels is not a multiple of 8 from 8
+ * to 64; RGCSR_ECSR for malformed CSR when opts->validate != 0. */
+rgcsr_status rgcsr_panel_sizes(int64_t n_rows, int64_t n_cols, int64_t nnz,
+                               const int64_t *row_ptr, const int32_t *col_idx,
+                               const rgcsr_opts *opts, int64_t *col_bounds, int64_t *pieces,
+                               int64_t *split_rows, int64_t *split_pieces, int64_t *slots,
+                               int64_t *long_nnz);
+
 /* ---- Device handles ------------------------------------------------------ */
 
 /* rgcsr_from_csr: convert a CSR matrix (Section 3.1) to RgCSR on the current

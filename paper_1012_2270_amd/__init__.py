@@ -117,6 +117,17 @@ def rgcsr_layout_sizes(A, opts: _lib.Opts) -> dict:
     return info.as_dict()
 
 
+def rgcsr_panel_sizes(A, opts: _lib.Opts) -> dict:
+    """Column bounds and piece counts of the column-panel copy (no GPU)."""
+    rp, col, _ = _csr_arrays(A)
+    cb = np.zeros(max(opts.col_panels, 0) + 1, np.int64)  # the library refuses a bad count
+    outs = [ctypes.c_int64() for _ in range(5)]
+    _lib.call("rgcsr_panel_sizes", A.n_rows, A.n_cols, int(rp[-1]) if rp.size else 0, _ptr(rp), _ptr(col),
+              ctypes.byref(opts), _ptr(cb), *[ctypes.byref(o) for o in outs])
+    keys = ("pieces", "split_rows", "split_pieces", "slots", "long_nnz")
+    return dict(col_bounds=cb, **{k: o.value for k, o in zip(keys, outs)})
+
+
 def rgcsr_layout_host(A, opts: _lib.Opts, bf16_bits: bool = False) -> dict:
     rp, col, val = _csr_arrays(A)
     s = rgcsr_layout_sizes(A, opts)

@@ -65,6 +65,8 @@ class CGStats(ctypes.Structure):
 SIGNATURES = {
     "rgcsr_default_opts": (None, [ctypes.POINTER(Opts)]),
     "rgcsr_layout_sizes": (c_int, [c_i64, c_i64, c_i64, c_vp, c_vp, ctypes.POINTER(Opts), ctypes.POINTER(Info)]),
+    "rgcsr_panel_sizes": (c_int, [c_i64, c_i64, c_i64, c_vp, c_vp, ctypes.POINTER(Opts), c_vp, P_I64, P_I64, P_I64,
+                                  P_I64, P_I64]),
     "rgcsr_layout_host": (c_int, [c_i64, c_i64, c_i64, c_vp, c_vp, c_vp, c_int, ctypes.POINTER(Opts),
                                   c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp]),
     "rgcsr_from_csr": (c_int, [c_i64, c_i64, c_i64, c_vp, c_vp, c_vp, c_int, ctypes.POINTER(Opts), c_int,

@@ -152,11 +152,6 @@ struct hyb_matrix_s {
 
 namespace {
 
-void check_panels(int32_t P) {
-    if (P != 0 && (P < kPanelXcds || P > kPanelMax || P % kPanelXcds != 0))
-        fail(RGCSR_EINVAL, "col_panels must be 0 or a multiple of 8 from 8 to 64");
-}
-
 void check_device_geometry(const LayoutParams &p) {
     const int64_t GT = (int64_t)p.G * p.T;
     if (!(GT % 64 == 0 || 64 % GT == 0))

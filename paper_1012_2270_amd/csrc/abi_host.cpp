@@ -7,6 +7,8 @@
 #include <string>
 #include <vector>
 
+#include <algorithm>
+
 #include "internal.h"
 
 namespace rg {
@@ -99,6 +101,28 @@ rgcsr_status rgcsr_layout_sizes(int64_t n_rows, int64_t n_cols, int64_t nnz, con
     out->group_size = p.G; out->lanes_per_row = p.T;
     out->value_dtype = opts ? opts->value_dtype : RGCSR_F32;
     out->sort_window = p.sigma; out->long_row_threshold = p.tau;
+    ABI_CATCH
+}
+
+rgcsr_status rgcsr_panel_sizes(int64_t n_rows, int64_t n_cols, int64_t nnz, const int64_t *row_ptr,
+                               const int32_t *col_idx, const rgcsr_opts *opts, int64_t *col_bounds, int64_t *pieces,
+                               int64_t *split_rows, int64_t *split_pieces, int64_t *slots, int64_t *long_nnz) {
+    ABI_TRY
+    if (!opts) fail(RGCSR_EINVAL, "opts is null");
+    check_panels(opts->col_panels);
+    if (opts->col_panels == 0) fail(RGCSR_EINVAL, "col_panels is 0");
+    const LayoutParams p = resolve_opts(opts);
+    if (opts->validate) validate_csr(n_rows, n_cols, nnz, row_ptr, col_idx);
+    else if (!row_ptr) fail(RGCSR_EINVAL, "row_ptr is null");
+    else if (row_ptr[n_rows] != nnz) fail(RGCSR_ECSR, "row_ptr[n_rows] != nnz");
+    PanelBuilt B;
+    build_panels(B, p, RGCSR_F32, opts->col_panels, p.tau, n_rows, n_cols, row_ptr, col_idx, nullptr);
+    if (col_bounds) std::copy(B.cb.begin(), B.cb.end(), col_bounds);
+    if (pieces) *pieces = B.LP.n_rows;
+    if (split_rows) *split_rows = (int64_t)B.crow.size();
+    if (split_pieces) *split_pieces = B.split_pieces;
+    if (slots) *slots = B.LP.slots;
+    if (long_nnz) *long_nnz = B.LP.long_nnz;
     ABI_CATCH
 }
 

@@ -243,9 +243,12 @@ constexpr int kPanelXcds = 8;            // XCDs the panels are dealt to (P a mu
 constexpr int kPanelRowBytes = 32;       // per-piece sums buffer: K * accumulator bytes per piece
 constexpr int64_t kPanelSliceBytes = 3 << 20;  // x slice of one panel that one L2 is asked to hold
 
+// Throws RGCSR_EINVAL unless P is 0 or a multiple of kPanelXcds up to kPanelMax.
+void check_panels(int32_t P);
+
 // Builds the panel layouts of one CSR matrix whose values are already in the
-// storage dtype (esz bytes each); throws RGCSR_EOVERFLOW when the pieces or
-// the nonzeros do not fit 32-bit indices.
+// storage dtype (esz bytes each; vals null: sizes and indices only); throws
+// RGCSR_EOVERFLOW when the pieces or the nonzeros do not fit 32-bit indices.
 void build_panels(PanelBuilt &B, const LayoutParams &p, int vdt, int32_t P, int64_t whole_max, int64_t n_rows,
                   int64_t n_cols, const int64_t *rp, const int32_t *col, const uint8_t *vals);
 

@@ -18,13 +18,21 @@
 
 namespace rg {
 
+void check_panels(int32_t P) {
+    if (P != 0 && (P < kPanelXcds || P > kPanelMax || P % kPanelXcds != 0))
+        fail(RGCSR_EINVAL, "col_panels must be 0 or a multiple of 8 from 8 to 64");
+}
+
 void build_panels(PanelBuilt &B, const LayoutParams &p, int vdt, int32_t P, int64_t whole_max, int64_t n_rows,
                   int64_t n_cols, const int64_t *rp, const int32_t *col, const uint8_t *vals) {
     if (P < 1 || P > kPanelMax) fail(RGCSR_EINVAL, "bad panel count");
     const int esz = dtype_size(vdt);
     const int64_t nnz = rp[n_rows];
     if (nnz > INT32_MAX || n_rows + nnz > INT32_MAX) fail(RGCSR_EOVERFLOW, "column panels need nnz + rows < 2^31");
-    B = PanelBuilt{};
+    // value-initialized with (): a braced temporary of an aggregate whose
+    // members allocate is not cleaned up by GCC before 13 when one of them
+    // throws (the members built before it leak)
+    B = PanelBuilt();
     B.P = P;
     // bounds: cb[q] is the first column at which the nonzeros of the columns
     // before it reach q * nnz / P (nondecreasing; empty panels are allowed)
@@ -74,7 +82,7 @@ void build_panels(PanelBuilt &B, const LayoutParams &p, int vdt, int32_t P, int6
     B.split_pieces = piece0[P];
     B.vidx.assign((size_t)B.cptr.back(), 0);
 
-    B.LP = HostLayout{};
+    B.LP = HostLayout();
     B.LP.G = p.G; B.LP.T = p.T; B.LP.sigma = p.sigma; B.LP.tau = p.tau; B.LP.vdt = vdt; B.LP.esz = esz;
     B.LP.n_matrices = 0;
     B.LPmap = B.LP;
@@ -110,7 +118,7 @@ void build_panels(PanelBuilt &B, const LayoutParams &p, int vdt, int32_t P, int6
                 if (pan[k] == q) {
                     pcol.push_back((int32_t)(col[k] - c0));
                     pmap.push_back((int32_t)k);
-                    pval.insert(pval.end(), vals + (size_t)k * esz, vals + (size_t)(k + 1) * esz);
+                    if (vals) pval.insert(pval.end(), vals + (size_t)k * esz, vals + (size_t)(k + 1) * esz);
                 }
             if (w) {
                 prp.push_back((int64_t)pcol.size());
@@ -125,7 +133,7 @@ void build_panels(PanelBuilt &B, const LayoutParams &p, int vdt, int32_t P, int6
             }
         }
         const int64_t nr = (int64_t)prp.size() - 1, nc = q < P ? B.cb[q + 1] - B.cb[q] : 0;
-        append_layout(B.LP, p, nr, nc, prp.data(), pcol.data(), pval.data(), esz, 0);
+        append_layout(B.LP, p, nr, nc, prp.data(), pcol.data(), vals ? pval.data() : nullptr, esz, 0);
         append_layout(B.LPmap, p, nr, nc, prp.data(), pcol.data(), (const uint8_t *)pmap.data(), 4, 0xff);
         B.grp_off.push_back(B.LP.ng);
         B.long_off.push_back(B.LP.nl);

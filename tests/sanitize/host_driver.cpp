@@ -1,6 +1,6 @@
 // Sanitizer driver for the host part of librgcsr (built with
-// -fsanitize=address,undefined from host_layout.cpp, ordering.cpp and
-// abi_host.cpp; no device code).  It runs the host-only C entry points on
+// -fsanitize=address,undefined from host_layout.cpp, ordering.cpp,
+// tile_layout.cpp, panel_layout.cpp and abi_host.cpp; no device code).  It runs the host-only C entry points on
 // seeded random and malformed CSR inputs, then repeats a conversion with the
 // n-th host allocation failing for every n until one succeeds: each failing
 // call must return RGCSR_ENOMEM, and LeakSanitizer (at exit) must find no
@@ -124,6 +124,32 @@ static rgcsr_status layout_all(const Csr &A, const rgcsr_opts &o) {
     return s;
 }
 
+// Column-panel sizes: bounds nondecreasing from 0 to n_cols, every split
+// row with at least one piece, every whole row one piece.
+static rgcsr_status panels_all(const Csr &A, rgcsr_opts o, int32_t P) {
+    o.col_panels = P;
+    std::vector<int64_t> cb((size_t)P + 1, -1);
+    int64_t pieces = -1, split_rows = -1, split_pieces = -1, slots = -1, long_nnz = -1;
+    g_armed = true;
+    const rgcsr_status s = rgcsr_panel_sizes(A.n_rows, A.n_cols, A.rp.back(), A.rp.data(), A.col.data(), &o,
+                                             cb.data(), &pieces, &split_rows, &split_pieces, &slots, &long_nnz);
+    g_armed = false;
+    if (s != RGCSR_OK) return s;
+    CHECK(cb[0] == 0 && cb[P] == A.n_cols, "panel bounds end points");
+    for (int32_t q = 0; q < P; q++) CHECK(cb[q] <= cb[q + 1], "panel bounds decrease");
+    int64_t whole = 0, split = 0;
+    for (int64_t r = 0; r < A.n_rows; r++) (A.rp[r + 1] - A.rp[r] > o.long_row_threshold ? split : whole)++;
+    CHECK(split_rows == split, "split rows %lld, expected %lld", (long long)split_rows, (long long)split);
+    CHECK(pieces == whole + split_pieces, "pieces %lld", (long long)pieces);
+    CHECK(split_pieces >= split - [&] {
+        int64_t empty = 0;
+        for (int64_t r = 0; r < A.n_rows; r++) empty += A.rp[r + 1] == A.rp[r] && o.long_row_threshold < 0;
+        return empty;
+    }(), "a split row without pieces");
+    CHECK(slots >= 0 && long_nnz >= 0 && long_nnz <= A.rp.back(), "copy sizes");
+    return s;
+}
+
 int main() {
     std::mt19937_64 rng(20101012);
     const int shapes[][5] = {{0, 0, 0, 0, 0},     {1, 1, 1, 0, 0},       {7, 5, 4, 0, 0},
@@ -148,6 +174,16 @@ int main() {
                             CHECK(s == RGCSR_OK, "layout status %d: %s", (int)s, rgcsr_last_error());
                             cases++;
                         }
+        for (int32_t P : {8, 16, 64})
+            for (int64_t tau : {(int64_t)-1, (int64_t)0, (int64_t)16}) {
+                rgcsr_opts o;
+                rgcsr_default_opts(&o);
+                o.sort_window = 5;
+                o.long_row_threshold = tau;
+                const rgcsr_status s = panels_all(A, o, P);
+                CHECK(s == RGCSR_OK, "panel sizes status %d: %s", (int)s, rgcsr_last_error());
+                cases++;
+            }
         int64_t k1 = -1;
         CHECK(hyb_choose_width(A.n_rows, A.rp.data(), RGCSR_F32, &k1) == RGCSR_OK && k1 >= 0, "hyb width");
         if (A.n_rows == A.n_cols) {
@@ -212,6 +248,22 @@ int main() {
             }
         }
         CHECK(enomem > 10, "only %d allocations were failed", enomem);
+        int enomem_panels = 0;
+        for (long n = 0;; n++) {
+            g_fail_countdown = n;
+            const rgcsr_status s = panels_all(A, o, 8);
+            g_fail_countdown = -1;
+            if (s == RGCSR_OK) break;
+            CHECK(s == RGCSR_ENOMEM, "panel sizes: allocation %ld failing gave status %d: %s", n, (int)s,
+                  rgcsr_last_error());
+            enomem_panels++;
+            if (n > 100000) {
+                CHECK(false, "panel sizes never got through");
+                break;
+            }
+        }
+        CHECK(enomem_panels > 10, "only %d panel allocations were failed", enomem_panels);
+        enomem += enomem_panels;
         std::printf("allocation failures injected: %d, each returned RGCSR_ENOMEM\n", enomem);
     }
     std::printf("layout cases: %d, failures: %d\n", cases, g_failures);

@@ -27,7 +27,8 @@ def _run(cmd, **kw):
 @pytest.mark.skipif(shutil.which("g++") is None, reason="needs g++")
 def test_host_library_under_asan_ubsan(tmp_path):
     exe = str(tmp_path / "host_asan")
-    srcs = [os.path.join(CSRC, f) for f in ("host_layout.cpp", "ordering.cpp", "abi_host.cpp", "tile_layout.cpp")]
+    srcs = [os.path.join(CSRC, f) for f in ("host_layout.cpp", "ordering.cpp", "abi_host.cpp", "tile_layout.cpp",
+                                             "panel_layout.cpp")]
     _run(["g++", "-std=c++17", *SAN, "-I", os.path.join(ROOT, "include"), *srcs,
           os.path.join(ROOT, "tests", "sanitize", "host_driver.cpp"), "-o", exe])
     r = _run([exe], env=ENV, timeout=600)
