@@ -217,8 +217,9 @@ class RgCSRMatrix:
 
 
 def rgcsr_from_csr(A, opts: _lib.Opts | None = None, stream=None, bf16_bits: bool = False,
-                   on_device: bool = False, **kw) -> RgCSRMatrix:
-    """Convert a host CSR matrix (workloads.CSR) to a device RgCSR handle."""
+                   **kw) -> RgCSRMatrix:
+    """Convert a host CSR matrix (workloads.CSR) to a device RgCSR handle
+    (device CSR arrays: rgcsr_from_csr_device)."""
     opts = opts if opts is not None else make_opts(**kw)
     rp, col, val = _csr_arrays(A)
     h = ctypes.c_void_p()

@@ -302,3 +302,23 @@ def test_panel_full_size_zipf_spmm(torch_cuda, oracle):
     ref = oracle.csr_spmm(A, X)
     for c in range(4):
         assert oracle.scaled_error(Yh[:, c], ref[:, c], oracle.csr_absmv(A, X[:, c])) <= TOL_F32
+
+
+def test_panel_device_inputs_and_host_sizes(torch_cuda, oracle, zipf):
+    """Device CSR inputs with col_panels go through the host conversion and
+    give the same bits as host inputs; the host-only rgcsr_panel_sizes counts
+    the pieces the handle holds."""
+    torch = torch_cuda
+    A, _ = zipf
+    say("panels device inputs")
+    X = W.uniform_matrix(A.n_cols, 4, 64)
+    Mh = rg.rgcsr_from_csr(A, col_panels=8, **LAY)
+    Md = rg.rgcsr_from_csr_device(A.n_rows, A.n_cols, dev(np.ascontiguousarray(A.row_ptr, np.int64)),
+                                  dev(np.ascontiguousarray(A.col, np.int32)), dev(A.val),
+                                  rg.make_opts(col_panels=8, **LAY))
+    s = rg.rgcsr_panel_sizes(A, rg.make_opts(col_panels=8, **LAY))
+    assert Mh.info["panel_pieces"] == Md.info["panel_pieces"] == s["pieces"]
+    Yh, Yd = nan_out(torch, A.n_rows, 4), nan_out(torch, A.n_rows, 4)
+    rg.rgcsr_spmv_batched(Mh, dev(X), Yh)
+    rg.rgcsr_spmv_batched(Md, dev(X), Yd)
+    np.testing.assert_array_equal(host(Yd), host(Yh))
