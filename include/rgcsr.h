@@ -254,8 +254,9 @@ rgcsr_status rgcsr_from_csr(int64_t n_rows, int64_t n_cols, int64_t nnz,
  * buf_bytes) -- a device pointer, 256-byte aligned, at least the plan's
  * device bytes, else RGCSR_EINVAL before any device work -- uploads the
  * layout on `stream` and synchronises it.  The handle borrows the buffer:
- * it must stay allocated and untouched until rgcsr_destroy, which does not
- * free it.  device_buf = NULL: the handle allocates and owns the block as
+ * it must stay allocated and untouched while the handle is in use and until
+ * the work queued on it has run; rgcsr_destroy neither frees it nor waits
+ * for that work.  device_buf = NULL: the handle allocates and owns the block as
  * rgcsr_from_csr does.  A plan builds one handle: once a build has passed its
  * argument checks (whether it then succeeds or not), rgcsr_build and
  * rgcsr_plan_device_bytes on that plan return RGCSR_EINVAL; argument errors
@@ -350,9 +351,13 @@ rgcsr_status rgcsr_info(rgcsr_handle A, rgcsr_info_t *out);
  * to rotate several copies of one matrix through the caches when timing. */
 rgcsr_status rgcsr_clone(rgcsr_handle A, void *stream, rgcsr_handle *out);
 
-/* Synchronises the device, then frees the handle and the device block it
- * owns; a block given to rgcsr_build stays allocated and may be released by
- * its owner once this returns.  NULL is accepted. */
+/* A handle that owns device memory (every handle except one that
+ * rgcsr_build placed in caller memory): synchronises the device, then frees
+ * the handle and its device memory.  A handle in caller memory: frees the
+ * host struct only and makes no device call, so it stalls no stream; the
+ * block stays allocated, and its owner releases it once the work already
+ * queued on the handle has run (in stream order, or after synchronising
+ * the streams that used it).  NULL is accepted. */
 rgcsr_status rgcsr_destroy(rgcsr_handle A);
 
 /* rgcsr_autotune: choose the layout for one host CSR matrix by a cost-model

@@ -54,6 +54,17 @@ def _stream(stream=None) -> int:
     return s.cuda_stream
 
 
+def _astream(A, stream=None) -> int:
+    """_stream for a call on matrix A; a matrix in torch memory (built from a
+    plan) notes the stream, so that close() can hold the block until the work
+    queued there has run."""
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    if getattr(A, "_memory", None) is not None:
+        A._streams[s.cuda_stream] = s
+    return s.cuda_stream
+
+
 def _ptr(a) -> int:
     if a is None:
         return 0
@@ -161,6 +172,7 @@ class RgCSRMatrix:
     def __init__(self, handle: int, memory=None):
         self._h = ctypes.c_void_p(handle)
         self._memory = memory  # caller-owned device buffer the handle borrows (rgcsr_build)
+        self._streams = {}     # streams that queued work on a borrowing handle
         info = _lib.Info()
         _lib.call("rgcsr_info", self._h, ctypes.byref(info))
         self.info = info.as_dict()
@@ -180,7 +192,14 @@ class RgCSRMatrix:
         if self._h is not None and self._h.value:
             _lib.call("rgcsr_destroy", self._h)
         self._h = None
+        if self._memory is not None:
+            # destroying a handle in torch memory does not wait for its work:
+            # the caching allocator reuses the block only once the work queued
+            # so far on each stream that used the handle has run
+            for st in self._streams.values():
+                self._memory.record_stream(st)
         self._memory = None  # released only after the handle is gone
+        self._streams = {}
 
     def __del__(self):
         try:
@@ -321,7 +340,7 @@ def rgcsr_spmv(A: RgCSRMatrix, x, y, stream=None) -> None:
     _dev_check(y, "y")
     if x.dtype != y.dtype or x.numel() != A.n_cols or y.numel() != A.n_rows:
         raise ValueError("x/y shape or dtype mismatch")
-    _lib.call("rgcsr_spmv", A.handle, _ptr(x), _ptr(y), _code_of_tensor(x), _stream(stream))
+    _lib.call("rgcsr_spmv", A.handle, _ptr(x), _ptr(y), _code_of_tensor(x), _astream(A, stream))
 
 
 def rgcsr_spmv_batched(A: RgCSRMatrix, X, Y, persistent: bool = False, stream=None) -> None:
@@ -334,7 +353,7 @@ def rgcsr_spmv_batched(A: RgCSRMatrix, X, Y, persistent: bool = False, stream=No
         raise ValueError("X/Y shape or dtype mismatch")
     k = X.shape[1]
     _lib.call("rgcsr_spmv_batched", A.handle, k, _ptr(X), X.stride(0), _ptr(Y), Y.stride(0),
-              _code_of_tensor(X), int(persistent), _stream(stream))
+              _code_of_tensor(X), int(persistent), _astream(A, stream))
 
 
 def rgcsr_spmv_transpose_grad(A: RgCSRMatrix, x, dy, dx=None, dvals=None, stream=None) -> None:
@@ -354,7 +373,7 @@ def rgcsr_spmv_transpose_grad(A: RgCSRMatrix, x, dy, dx=None, dvals=None, stream
         if t is not None:
             _on_device_of(A, t, nm)
     _lib.call("rgcsr_spmv_transpose_grad", A.handle, _ptr(x), _ptr(dy), _ptr(dx), _ptr(dvals),
-              _code_of_tensor(dy), _stream(stream))
+              _code_of_tensor(dy), _astream(A, stream))
 
 
 def rgcsr_set_values(A: RgCSRMatrix, vals, stream=None) -> None:
@@ -367,13 +386,13 @@ def rgcsr_set_values(A: RgCSRMatrix, vals, stream=None) -> None:
             raise ValueError(f"vals has {v.size} elements, expected {A.nnz}")
         if v.dtype not in (np.float64, np.float32, np.float16):
             raise ValueError(f"vals has dtype {v.dtype}, expected float64, float32 or float16")
-        _lib.call("rgcsr_set_values", A.handle, _ptr(v), _code_of_numpy(v), 0, _stream(stream))
+        _lib.call("rgcsr_set_values", A.handle, _ptr(v), _code_of_numpy(v), 0, _astream(A, stream))
     else:
         if vals.dtype not in (_torch().float32, _torch().float64):
             raise ValueError(f"vals has dtype {vals.dtype}, expected float32 or float64")
         _size_check(vals, "vals", A.nnz)
         _on_device_of(A, vals, "vals")
-        _lib.call("rgcsr_set_values", A.handle, _ptr(vals), _code_of_tensor(vals), 1, _stream(stream))
+        _lib.call("rgcsr_set_values", A.handle, _ptr(vals), _code_of_tensor(vals), 1, _astream(A, stream))
     A.value_version = getattr(A, "value_version", 0) + 1
 
 

@@ -564,6 +564,12 @@ void free_handle(rgcsr_matrix_s *h) {
     delete h;
 }
 
+// Device memory that freeing the handle releases (none for a handle built
+// into caller memory: its transpose sits in the same block).
+bool owns_device_memory(const rgcsr_matrix_s *h) {
+    return h && ((h->mem && h->owns_mem) || h->tile_mem || owns_device_memory(h->AT) || owns_device_memory(h->PN));
+}
+
 void check_handle(const rgcsr_matrix_s *h) {
     if (!h) fail(RGCSR_EINVAL, "null handle");
     if (current_device() != h->device) fail(RGCSR_EINVAL, "handle belongs to another device");
@@ -1307,7 +1313,9 @@ rgcsr_status rgcsr_clone(rgcsr_handle A, void *stream, rgcsr_handle *out) {
 rgcsr_status rgcsr_destroy(rgcsr_handle A) {
     ABI_TRY
     if (!A) return RGCSR_OK;
-    (void)hipDeviceSynchronize();
+    // hipFree waits for the device in any case; a handle in caller memory
+    // frees host memory only, so destroying it stalls no stream
+    if (owns_device_memory(A)) (void)hipDeviceSynchronize();
     free_handle(A);
     ABI_CATCH
 }

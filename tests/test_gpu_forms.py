@@ -408,6 +408,48 @@ def test_build_into_torch_memory(torch_cuda, oracle, lay):
     M2.close()
 
 
+def test_destroy_of_a_handle_in_torch_memory_does_not_wait(torch_cuda, oracle):
+    """Destroying a handle built into torch memory makes no device call: the
+    work queued before it is still running when close() returns, and the
+    block, held for that work (on the stream it ran on, also a side stream),
+    still gives the right product although the same-sized allocation that
+    follows is filled at once.  A handle that owns its memory synchronises
+    the device when destroyed."""
+    torch = torch_cuda
+    A = W.random_csr(4000, 3000, seed=35, max_len=40, empty_frac=0.1, dtype=np.float32)
+    x = W.uniform_vector(A.n_cols, 36, np.float32)
+    xd = dev(x)
+    a = torch.randn(8192, 8192, device="cuda:0")
+    side = torch.cuda.Stream()
+    for own, on_side in ((True, False), (False, False), (False, True)):
+        say("destroy while busy", "owns its memory" if own else "torch memory", "side stream" if on_side else "")
+        if own:
+            M = rg.rgcsr_from_csr(A, G=64)
+            nbytes = 0
+        else:
+            plan = rg.rgcsr_plan_from_csr(A, G=64)
+            nbytes = plan.device_bytes
+            M = plan.build()
+            plan.close()
+        y = torch.empty(A.n_rows, device="cuda:0")
+        torch.cuda.synchronize()
+        st = side if on_side else torch.cuda.current_stream()
+        with torch.cuda.stream(st):
+            for _ in range(3):
+                c = a @ a  # milliseconds of queued work ahead of the product
+            M.spmv(xd, y)
+        M.close()
+        pending = not st.query()
+        if nbytes:
+            junk = torch.full((nbytes,), 255, dtype=torch.uint8, device="cuda:0")
+        torch.cuda.synchronize()
+        assert pending != own
+        check_spmv(oracle, A, x, host(y))
+        del c
+        if nbytes:
+            del junk
+
+
 @pytest.mark.parametrize("transpose", [True, False])
 def test_grad_rows_split_into_chunks(torch_cuda, oracle, transpose):
     """Rows longer than one workgroup chunk (16,384 nonzeros) and rows of
