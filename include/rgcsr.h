@@ -112,9 +112,11 @@ typedef struct {
                                lanes_per_row = 1 and F32 vectors, and apply to single
                                right-hand-side launches */
     int32_t tile_min_len;   /* kernel schedule: long rows of at least this many nonzeros
-                               (and at least 4 per column tile) are also stored split
-                               by column tile of 8,192 columns; a launch with one F32
-                               vector of unit stride and load policy 0 first runs one
+                               (and at least half as many as there are column tiles)
+                               are also stored split by column tile of 8,192 columns
+                               (4,096 for F64 storage); a launch with one vector of
+                               unit stride (F64 for F64 storage, F32 otherwise) and
+                               load policy 0 first runs one
                                workgroup per (tile, run of those rows) that stages the
                                tile of x in LDS and writes one partial sum per (row,
                                tile), then the SpMV kernel adds each row's partials in
@@ -122,8 +124,9 @@ typedef struct {
                                the texture-cache study of Section 4.3).  Rows with more
                                than 4,096 nonzeros in one tile stay on the long-row
                                path.  0 = off; -1 (default) = 256, used only when the
-                               tiled rows hold at least 262,144 nonzeros.  F64 storage
-                               never tiles. */
+                               tiled rows hold at least 262,144 nonzeros.  F32 storage
+                               with F64 vectors runs the tiled rows on the long-row
+                               path. */
     int32_t col_panels;     /* 0 (default) = off.  P = 8, 16, ..., 64: the handle also
                                keeps a copy of the matrix for launches of several
                                right-hand sides.  The columns are split into P panels

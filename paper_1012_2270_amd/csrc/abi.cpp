@@ -120,7 +120,7 @@ struct rgcsr_matrix_s {
     int32_t *tile_ptr = nullptr, *tile_dst = nullptr, *tile_orow = nullptr;
     uint16_t *tile_lcol = nullptr;
     void *tile_val = nullptr;
-    float *tile_partial = nullptr;
+    void *tile_partial = nullptr;         // FP64 for F64 storage, else FP32
     LongItem *rest_wave = nullptr, *rest_block = nullptr, *rest_combine = nullptr;
     void *tile_mem = nullptr;
     size_t tile_bytes = 0;
@@ -281,7 +281,7 @@ void add_tile_arrays(rgcsr_matrix_s *h, const HostTiles &T, Arena &a) {
     a.add((uint8_t **)&h->tile_val, (size_t)T.n_ent * h->esz);
     a.add(&h->tile_dst, T.dst.size());
     a.add(&h->tile_orow, (size_t)T.n_trows);
-    a.add(&h->tile_partial, (size_t)(T.n_tiles * T.n_trows));
+    a.add((uint8_t **)&h->tile_partial, (size_t)(T.n_tiles * T.n_trows) * (h->vdt == RGCSR_F64 ? 8 : 4));
     a.add(&h->rest_wave, T.rest.wave.size());
     a.add(&h->rest_block, T.rest.block.size());
     a.add(&h->rest_combine, T.rest.combine.size());
@@ -365,9 +365,9 @@ rgcsr_matrix_s *prepare_handle(const HostLayout &L, bool with_row_ptr, const Hos
             a.add(&h->t_map_slot, (size_t)map->slots);
             a.add(&h->t_map_long, (size_t)map->long_nnz);
         }
-        // the column-tiled path takes FP32 vectors, so F64 storage has none
+        // column tiles: FP64 x for F64 storage, FP32 x otherwise
         auto tiles = std::make_shared<HostTiles>();
-        if (L.vdt != RGCSR_F64) build_tiles(L, tile_min_len, *tiles);
+        build_tiles(L, tile_min_len, *tiles);
         add_tile_arrays(h, *tiles, a);
         if (tiles->active()) h->pending_tiles = tiles;
         if (pb) {
@@ -526,7 +526,7 @@ rgcsr_matrix_s *make_device_on_device(DevPlan &P, const LayoutParams &p, int vdt
         HIPCHK(hipStreamSynchronize(st));
         // column tiles from the converted long-row segment: its columns come
         // back to the host, the tile arrays go to a block of their own
-        if (tile_min_len != 0 && vdt != RGCSR_F64 && L.nl > 0) {
+        if (tile_min_len != 0 && L.nl > 0) {
             L.nl = P.nl;
             L.long_ptr = P.long_ptr_host;
             L.long_col.resize((size_t)L.long_nnz);
@@ -703,9 +703,11 @@ void spmv_launch(const rgcsr_matrix_s *h, int K, const void *X, int64_t ldx, voi
     if (h->n_rows == 0) return;
     const bool panels = panel_launch_ok(h, K, ldx, f64);
     const rgcsr_matrix_s *pn = h->PN;
-    // the column-tiled rows take one FP32 vector with unit stride and the
-    // default load policy; everything else runs them on the long-row path
-    const bool tiled = !panels && h->n_trows > 0 && K == 1 && !f64 && ldx == 1 && h->lp == 0;
+    // the column-tiled rows take one vector with unit stride (FP64 for F64
+    // storage, FP32 otherwise) and the default load policy; everything else
+    // runs them on the long-row path
+    const bool tiled = !panels && h->n_trows > 0 && K == 1 && (f64 != 0) == (h->vdt == RGCSR_F64) && ldx == 1 &&
+                       h->lp == 0;
     // right-hand sides of up to kRunsRowBytes per row take the runs of rows
     // per lane (R = 0) when the handle has them; otherwise one row per lane
     const rgcsr_matrix_s *src = panels ? pn : h;
@@ -758,7 +760,7 @@ void spmv_launch(const rgcsr_matrix_s *h, int K, const void *X, int64_t ldx, voi
         TP.ptr = h->tile_ptr;
         TP.lcol = h->tile_lcol;
         TP.val = h->tile_val;
-        TP.x = (const float *)X;
+        TP.x = X;
         TP.partial = h->tile_partial;
         TP.n_cols = h->n_cols;
         TP.n_trows = (int32_t)h->n_trows;

@@ -42,10 +42,11 @@ struct SpmvParams {
     // total_waves - n_long_waves (n_long_waves = long rows)
     int32_t n_long_waves;
     int32_t total_waves;
-    // column-tiled long rows (FP32 vectors, one right-hand side): the tile
-    // kernel has written one partial sum per (tile, tiled row); units
-    // [0, n_comb_units) of the launch add them, 64 rows each
-    const float *tile_partial;   // [n_tiles * n_trows]
+    // column-tiled long rows (one right-hand side, FP64 vectors for F64
+    // storage, else FP32): the tile kernel has written one partial sum per
+    // (tile, tiled row) in the vector type; units [0, n_comb_units) of the
+    // launch add them, 64 rows each
+    const void *tile_partial;    // [n_tiles * n_trows]
     const int32_t *tile_orow;    // [n_trows] output row of each tiled row
     int32_t n_comb_units, n_tiles, n_trows;
     // value updates: position of each long-row element in the tiled copy
@@ -121,8 +122,8 @@ struct TileParams {
     const int32_t *ptr;      // [n_tiles * (n_trows + 1)]
     const uint16_t *lcol;    // [n_ent] column within the tile
     const void *val;         // [n_ent] storage dtype
-    const float *x;
-    float *partial;          // [n_tiles * n_trows]
+    const void *x;           // FP64 for F64 storage, else FP32
+    void *partial;           // [n_tiles * n_trows], the type of x
     int64_t n_cols;
     int32_t n_trows;
     int32_t x_aligned;       // x is 16-byte aligned (vector loads of a tile)

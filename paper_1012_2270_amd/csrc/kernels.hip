@@ -657,17 +657,19 @@ __device__ __forceinline__ void spmv_block_item(const SpmvParams &P, int32_t u, 
 // one per lane, so each load reads 64 consecutive partial sums; wavefront w
 // adds tiles [w * q, (w + 1) * q) in tile order, then one wavefront adds the
 // four sums in wavefront order (a fixed order; chains of q + 4 additions).
-__device__ __forceinline__ void tile_combine_unit(const SpmvParams &P, int32_t ui, int lane, int wv, float *lds) {
+// A is the vector type (FP64 partial sums for F64 storage, else FP32).
+template <class A>
+__device__ __forceinline__ void tile_combine_unit(const SpmvParams &P, int32_t ui, int lane, int wv, A *lds) {
     const int32_t k = ui * 64 + lane;
     const int q = (P.n_tiles + kBlockWaves - 1) / kBlockWaves;
     const int t0 = min(wv * q, P.n_tiles), t1 = min(t0 + q, P.n_tiles);
     const int64_t nt = P.n_trows;
-    float run = 0.f;
+    A run = A(0);
     if (k < P.n_trows) {
-        const float *p = P.tile_partial + k;
+        const A *p = (const A *)P.tile_partial + k;
         int t = t0;
         for (; t + 16 <= t1; t += 16) {
-            float v[16];
+            A v[16];
 #pragma unroll
             for (int j = 0; j < 16; j++) v[j] = p[(int64_t)(t + j) * nt];
 #pragma unroll
@@ -678,22 +680,23 @@ __device__ __forceinline__ void tile_combine_unit(const SpmvParams &P, int32_t u
     lds[wv * 64 + lane] = run;
     __syncthreads();
     if (wv == 0 && k < P.n_trows) {
-        float acc = 0.f;
+        A acc = A(0);
 #pragma unroll
         for (int w = 0; w < kBlockWaves; w++) acc += lds[w * 64 + lane];
-        ((float *)P.y)[(int64_t)P.tile_orow[k] * P.ldy] = acc;
+        ((A *)P.y)[(int64_t)P.tile_orow[k] * P.ldy] = acc;
     }
 }
 
 template <int VD, class A, int K, int T, int R, bool LONG, int LP>
 __device__ __forceinline__ void spmv_unit(const SpmvParams &P, int32_t u, int lane, int wv, A (*red)[K], A *lbuf) {
     constexpr bool kLdsLong = LONG && K == 1;
-    // combine units of the column-tiled rows: FP32 accumulation, one
-    // right-hand side, the default load policy; they use the workgroup's
-    // LDS buffer (lbuf of wavefront 0 starts it)
-    if constexpr (kLdsLong && sizeof(A) == 4 && LP == 0) {
+    // combine units of the column-tiled rows: one right-hand side, the
+    // default load policy, partial sums in the vector type (FP64 vectors
+    // only with F64 storage); they use the workgroup's LDS buffer (lbuf of
+    // wavefront 0 starts it)
+    if constexpr (kLdsLong && LP == 0 && (sizeof(A) == 4 || VD == RGCSR_F64)) {
         if (u < P.n_comb_units) {
-            tile_combine_unit(P, u, lane, wv, (float *)lbuf - wv * (kWaveRowMax + 1));
+            tile_combine_unit<A>(P, u, lane, wv, lbuf - wv * (kWaveRowMax + 1));
             return;
         }
         u -= P.n_comb_units;

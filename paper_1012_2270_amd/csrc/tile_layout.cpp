@@ -55,7 +55,8 @@ void build_tiles(const HostLayout &L, int64_t min_len, HostTiles &T) {
     T = HostTiles{};
     if (min_len == 0 || L.nl == 0 || L.n_cols == 0) return;
     const bool automatic = min_len < 0;
-    const int64_t n_tiles = (L.n_cols + kTileCols - 1) / kTileCols;
+    const int64_t C = tile_cols(L.vdt);
+    const int64_t n_tiles = (L.n_cols + C - 1) / C;
     const int64_t thr = std::max<int64_t>(automatic ? 256 : min_len, (n_tiles + 1) / 2);
     // a row's segment in one tile must fit a unit: a row with more than
     // kTileUnitMax entries in some tile stays on the long-row path (columns
@@ -63,7 +64,7 @@ void build_tiles(const HostLayout &L, int64_t min_len, HostTiles &T) {
     auto longest_segment = [&](int64_t i) {
         int64_t best = 0, run = 0, prev = -1;
         for (int64_t q = L.long_ptr[i]; q < L.long_ptr[i + 1]; q++) {
-            const int64_t t = L.long_col[q] / kTileCols;
+            const int64_t t = L.long_col[q] / C;
             run = t == prev ? run + 1 : 1;
             prev = t;
             best = std::max(best, run);
@@ -93,7 +94,7 @@ void build_tiles(const HostLayout &L, int64_t min_len, HostTiles &T) {
     T.ptr.assign(n_tiles * (nt + 1), 0);
     for (int64_t k = 0; k < nt; k++) {
         const int64_t i = T.trow[k];
-        for (int64_t q = L.long_ptr[i]; q < L.long_ptr[i + 1]; q++) T.ptr[(L.long_col[q] / kTileCols) * (nt + 1) + k]++;
+        for (int64_t q = L.long_ptr[i]; q < L.long_ptr[i + 1]; q++) T.ptr[(L.long_col[q] / C) * (nt + 1) + k]++;
     }
     int64_t run = 0;
     for (int64_t t = 0; t < n_tiles; t++) {
@@ -111,9 +112,9 @@ void build_tiles(const HostLayout &L, int64_t min_len, HostTiles &T) {
     for (int64_t k = 0; k < nt; k++) {
         const int64_t i = T.trow[k];
         for (int64_t q = L.long_ptr[i]; q < L.long_ptr[i + 1]; q++) {
-            const int64_t t = L.long_col[q] / kTileCols;
+            const int64_t t = L.long_col[q] / C;
             const int32_t d = fill[t * (nt + 1) + k]++;
-            T.lcol[d] = (uint16_t)(L.long_col[q] - t * kTileCols);
+            T.lcol[d] = (uint16_t)(L.long_col[q] - t * C);
             T.src[d] = (int32_t)q;
             T.dst[q] = d;
         }
@@ -140,9 +141,10 @@ void build_tiles(const HostLayout &L, int64_t min_len, HostTiles &T) {
                 r1++;
             }
             per_tile[t].push_back(TileUnit{(int32_t)t, (int32_t)r0, (int32_t)r1, lanes_for_seg(seg)});
-            // a unit streams its entries and stages a tile of x (32 KB, about
-            // as much as 4,096 entries of value and column)
-            tile_cost[t] += (p[r1] - p[r0]) + kTileCols / 2;
+            // a unit streams its entries and stages a tile of x (32 KB in
+            // either precision, about as much as 4,096 entries of value and
+            // column)
+            tile_cost[t] += (p[r1] - p[r0]) + 4096;
             r0 = r1;
         }
     }

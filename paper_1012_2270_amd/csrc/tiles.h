@@ -1,7 +1,7 @@
 // Column tiles of the longest rows: x staged in LDS.  Internal.
 //
 // Rows of the long-row segment with at least `min_len` nonzeros are also
-// stored split by column tile (kTileCols columns per tile).  A tile kernel
+// stored split by column tile (tile_cols(vdt) columns per tile).  A tile kernel
 // runs first: each workgroup stages a tile of x in LDS with coalesced loads,
 // streams the tile's entries of a range of those rows, multiplies them
 // against x read from LDS and writes one partial sum per (row, tile).  The
@@ -20,8 +20,11 @@
 namespace rg {
 
 constexpr int kTileCols = 8192;      // x columns per tile: 32 KB of FP32 in LDS
-constexpr int kTileUnitMax = 4096;   // entries per unit: 16 KB of FP32 products in LDS
-constexpr int kTileThreads = 512;    // one workgroup per unit, three per CU (48 KB of LDS each)
+constexpr int kTileCols64 = 4096;    // F64 storage (FP64 x): 32 KB of FP64 in LDS
+constexpr int kTileUnitMax = 4096;   // entries per unit: 16 KB of FP32 (32 KB of FP64) products in LDS
+constexpr int kTileThreads = 512;    // one workgroup per unit, three per CU (48 KB of LDS each; FP64: two, 64 KB)
+// Columns per tile of a layout with stored value type vdt.
+constexpr int tile_cols(int vdt) { return vdt == RGCSR_F64 ? kTileCols64 : kTileCols; }
 constexpr int kTilePasses = 4;       // passes over a unit's rows (512 / lanes rows per pass)
 constexpr int kTileLaneSteps = 16;   // products a lane adds per row segment, at most
 constexpr int64_t kTileMinEntries = int64_t(1) << 18;  // automatic choice: tile only this many entries or more

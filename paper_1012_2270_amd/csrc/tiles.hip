@@ -7,17 +7,27 @@
 
 namespace rg {
 
+// Stored value type S and the type A of x, the products and the partial
+// sums (FP64 for F64 storage, else FP32).
 template <int VD> struct TileVal;
+template <> struct TileVal<RGCSR_F64> {
+    using S = double;
+    using A = double;
+    __device__ static double cvt(S v) { return v; }
+};
 template <> struct TileVal<RGCSR_F32> {
     using S = float;
+    using A = float;
     __device__ static float cvt(S v) { return v; }
 };
 template <> struct TileVal<RGCSR_F16> {
     using S = uint16_t;
+    using A = float;
     __device__ static float cvt(S v) { return (float)__builtin_bit_cast(_Float16, v); }
 };
 template <> struct TileVal<RGCSR_BF16> {
     using S = uint16_t;
+    using A = float;
     __device__ static float cvt(S v) { return bf16_to_f32(v); }
 };
 
@@ -32,14 +42,16 @@ template <int VD>
 __global__ __launch_bounds__(kTileThreads) void tile_spmv_k(TileParams P) {
     using V = TileVal<VD>;
     using S = typename V::S;
+    using A = typename V::A;
+    constexpr int C = tile_cols(VD);
     constexpr int EU = kTileUnitMax / kTileThreads;
-    __shared__ float xs[kTileCols];
-    __shared__ float prod[kTileUnitMax];
+    __shared__ A xs[C];
+    __shared__ A prod[kTileUnitMax];
     const TileUnit u = P.units[blockIdx.x];
     if (u.t < 0) return;
     const int tid = threadIdx.x;
-    const int64_t c0 = (int64_t)u.t * kTileCols;
-    const int nc = (int)min((int64_t)kTileCols, P.n_cols - c0);
+    const int64_t c0 = (int64_t)u.t * C;
+    const int nc = (int)min((int64_t)C, P.n_cols - c0);
     const int32_t *ptr = P.ptr + (int64_t)u.t * (P.n_trows + 1);
     const int32_t e0 = ptr[u.r0];
     const int32_t n = ptr[u.r1] - e0;
@@ -59,11 +71,12 @@ __global__ __launch_bounds__(kTileThreads) void tile_spmv_k(TileParams P) {
             c[k] = 0;
         }
     }
-    const float *xt = P.x + c0;
-    constexpr int X4 = kTileCols / 4 / kTileThreads;
+    const A *xt = (const A *)P.x + c0;
+    // the tile (32 KB in either precision) as 16-byte vectors
+    constexpr int X4 = C * (int)sizeof(A) / 16 / kTileThreads;
     // assigned on every path, so the array stays in registers
     float4 x4[X4];
-    const bool vec = P.x_aligned && nc == kTileCols;
+    const bool vec = P.x_aligned && nc == C;
 #pragma unroll
     for (int k = 0; k < X4; k++)
         x4[k] = vec ? reinterpret_cast<const float4 *>(xt)[tid + k * kTileThreads] : make_float4(0.f, 0.f, 0.f, 0.f);
@@ -94,16 +107,17 @@ __global__ __launch_bounds__(kTileThreads) void tile_spmv_k(TileParams P) {
 #pragma unroll
     for (int j = 0; j < kTilePasses; j++) {
         const int r = j * per + (tid >> sh);
-        float acc = 0.f;
+        A acc = A(0);
         for (int32_t p = b0[j] + q; p < b1[j]; p += L) acc += prod[p];
         for (int off = L >> 1; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
-        if (u.r0 + r < u.r1 && q == 0) P.partial[(int64_t)u.t * P.n_trows + u.r0 + r] = acc;
+        if (u.r0 + r < u.r1 && q == 0) ((A *)P.partial)[(int64_t)u.t * P.n_trows + u.r0 + r] = acc;
     }
 }
 
 hipError_t launch_tile_spmv(const TileParams &P, int vdt, int n_units, hipStream_t st) {
     if (n_units == 0) return hipSuccess;
     switch (vdt) {
+    case RGCSR_F64: hipLaunchKernelGGL(tile_spmv_k<RGCSR_F64>, dim3(n_units), dim3(kTileThreads), 0, st, P); break;
     case RGCSR_F32: hipLaunchKernelGGL(tile_spmv_k<RGCSR_F32>, dim3(n_units), dim3(kTileThreads), 0, st, P); break;
     case RGCSR_F16: hipLaunchKernelGGL(tile_spmv_k<RGCSR_F16>, dim3(n_units), dim3(kTileThreads), 0, st, P); break;
     case RGCSR_BF16: hipLaunchKernelGGL(tile_spmv_k<RGCSR_BF16>, dim3(n_units), dim3(kTileThreads), 0, st, P); break;
@@ -124,7 +138,10 @@ hipError_t launch_tile_values(int64_t n, const int32_t *dst, const void *long_va
                               hipStream_t st) {
     if (n == 0) return hipSuccess;
     const int nb = (int)((n + 255) / 256);
-    if (esz == 4)
+    if (esz == 8)
+        hipLaunchKernelGGL(tile_values_k<uint64_t>, dim3(nb), dim3(256), 0, st, n, dst, (const uint64_t *)long_val,
+                           (uint64_t *)tile_val);
+    else if (esz == 4)
         hipLaunchKernelGGL(tile_values_k<uint32_t>, dim3(nb), dim3(256), 0, st, n, dst, (const uint32_t *)long_val,
                            (uint32_t *)tile_val);
     else if (esz == 2)

@@ -1,5 +1,6 @@
 """GPU parity of the column-tiled long rows (x staged in LDS per tile of
-8,192 columns, partial sums added in a fixed order) against the FP64 oracle,
+8,192 columns, 4,096 for F64 storage, partial sums added in a fixed order)
+against the FP64 oracle,
 through the C ABI, and the paths that must fall back to the long-row kernel
 (FP64 vectors, several right-hand sides, strided x, other load policies)."""
 import numpy as np
@@ -184,3 +185,104 @@ def test_full_size_zipf_tiles_auto(torch_cuda, oracle):
     say("full-size Zipf, automatic tiles", M.info["tiled_rows"], M.info["tile_entries"])
     assert M.info["tiled_rows"] > 0
     check_spmv(oracle, A, x, host(M.spmv(dev(x))))
+
+
+# F64 storage: tiles of 4,096 columns with x, the products and the partial
+# sums in FP64.  200,000 columns make 49 tiles, the last one partial (3,392
+# columns); rows need at least max(min_len, 25) nonzeros.
+@pytest.mark.parametrize("min_len", [16, 300, 2000])
+def test_tiled_parity_f64(torch_cuda, oracle, zipf, min_len):
+    A, _ = zipf
+    x = W.uniform_vector(A.n_cols, 52, np.float64)
+    say("tiles, F64 storage", min_len)
+    M = tiled(A, tile_min_len=min_len, value_dtype="f64")
+    assert M.info["n_tiles"] == 49
+    L = np.diff(A.row_ptr)
+    assert M.info["tiled_rows"] == int(np.sum(L >= max(min_len, 25)))
+    y = host(M.spmv(dev(x)))
+    check_spmv(oracle, A, x, y, tol=TOL_F64)
+    np.testing.assert_array_equal(host(M.spmv(dev(x))).view(np.uint64), y.view(np.uint64))
+    M0 = tiled(A, tile_min_len=0, value_dtype="f64")
+    assert M0.info["tiled_rows"] == 0
+    check_spmv(oracle, A, x, host(M0.spmv(dev(x))), tol=TOL_F64)
+
+
+def test_tiles_f64_updates_clone_device_and_torch_memory(torch_cuda, oracle, zipf):
+    """F64 tiles follow value updates (both value paths), clones, device
+    conversion and plan/build, bit for bit; x at an 8-byte offset (not
+    16-byte aligned) stages the tile element by element; two right-hand
+    sides take the long-row kernel."""
+    torch = torch_cuda
+    A, _ = zipf
+    x = W.uniform_vector(A.n_cols, 53, np.float64)
+    lay = dict(LAY, tile_min_len=64, value_dtype="f64")
+    say("tiles, F64 set_values and clone")
+    M = tiled(A, keep_csr_map=True, build_transpose=True, **lay)
+    assert M.info["tiled_rows"] > 0
+    theta = W.normal_vector(A.nnz, 54, np.float64)
+    rg.rgcsr_set_values(M, dev(theta))
+    A2 = W.CSR(A.n_rows, A.n_cols, A.row_ptr, A.col, theta)
+    y = host(M.spmv(dev(x)))
+    check_spmv(oracle, A2, x, y, tol=TOL_F64)
+    np.testing.assert_array_equal(host(M.clone().spmv(dev(x))).view(np.uint64), y.view(np.uint64))
+    rg.rgcsr_set_values(M, theta)  # host values: the other update path
+    np.testing.assert_array_equal(host(M.spmv(dev(x))).view(np.uint64), y.view(np.uint64))
+    say("tiles, F64 x at an 8-byte offset")
+    buf = torch.empty(A.n_cols + 1, dtype=torch.float64, device="cuda:0")
+    buf[1:] = dev(x)
+    assert buf[1:].data_ptr() % 16 != 0
+    np.testing.assert_array_equal(host(M.spmv(buf[1:])).view(np.uint64), y.view(np.uint64))
+    say("tiles, F64 k = 2 and strided x")
+    X = W.uniform_matrix(A.n_cols, 2, 55).astype(np.float64)
+    Y = host(M.spmm(dev(X)))
+    ref = oracle.csr_spmm(A2, X)
+    for c in range(2):
+        assert oracle.scaled_error(Y[:, c], ref[:, c], oracle.csr_absmv(A2, X[:, c])) <= TOL_F64
+    say("tiles, F64 device conversion")
+    y1 = host(tiled(A, **lay).spmv(dev(x)))
+    D = rg.rgcsr_from_csr_device(A.n_rows, A.n_cols, dev(np.ascontiguousarray(A.row_ptr, np.int64)),
+                                 dev(A.col), dev(A.val), rg.make_opts(**lay))
+    assert D.info["tiled_rows"] == M.info["tiled_rows"]
+    np.testing.assert_array_equal(host(D.spmv(dev(x))).view(np.uint64), y1.view(np.uint64))
+    say("tiles, F64 plan and build into torch memory")
+    B = rg.rgcsr_plan_from_csr(A, **lay).build()
+    np.testing.assert_array_equal(host(B.spmv(dev(x))).view(np.uint64), y1.view(np.uint64))
+    check_spmv(oracle, A, x, y1, tol=TOL_F64)
+
+
+def test_tiles_f64_with_a_whole_tile_row(torch_cuda, oracle):
+    """F64 tiles of 4,096 columns: a row holding every column of tile 1 (one
+    segment of 4,096 entries, a whole unit) next to sparse long rows."""
+    A = W.random_csr(2000, 40_000, seed=56, max_len=8, long_rows=5, long_len=6000)
+    L = np.diff(A.row_ptr).copy()
+    cols, vals = [], []
+    rng = np.random.default_rng(57)
+    for r in range(A.n_rows):
+        c = A.col[A.row_ptr[r]:A.row_ptr[r + 1]]
+        v = A.val[A.row_ptr[r]:A.row_ptr[r + 1]]
+        if r == 3:
+            c = np.concatenate([np.sort(rng.choice(4096, 700, replace=False)), 4096 + np.arange(4096),
+                                8192 + np.sort(rng.choice(30_000, 900, replace=False))]).astype(np.int32)
+            v = rng.standard_normal(len(c))
+        cols.append(c)
+        vals.append(v)
+        L[r] = len(c)
+    rp = np.concatenate([[0], np.cumsum(L)]).astype(np.int64)
+    A = W.CSR(A.n_rows, A.n_cols, rp, np.concatenate(cols).astype(np.int32), np.concatenate(vals))
+    x = W.uniform_vector(A.n_cols, 58, np.float64)
+    say("tiles, F64 whole-tile row")
+    M = rg.rgcsr_from_csr(A, G=64, tau=16, tile_min_len=1000, value_dtype="f64")
+    assert M.info["tiled_rows"] == int(np.sum(L >= 1000))
+    check_spmv(oracle, A, x, host(M.spmv(dev(x))), tol=TOL_F64)
+
+
+def test_full_size_zipf_tiles_auto_f64(torch_cuda, oracle):
+    """The benchmark's Zipf layout in F64 storage picks the column tiles by
+    itself (4,096 columns each)."""
+    from bench import LAYOUT_ZIPF
+    A, x = W.workload_zipf()
+    x = x.astype(np.float64)
+    M = rg.rgcsr_from_csr(A, value_dtype="f64", **LAYOUT_ZIPF)
+    say("full-size Zipf F64, automatic tiles", M.info["tiled_rows"], M.info["tile_entries"])
+    assert M.info["tiled_rows"] > 0 and M.info["n_tiles"] == -(-A.n_cols // 4096)
+    check_spmv(oracle, A, x, host(M.spmv(dev(x))), tol=TOL_F64)
