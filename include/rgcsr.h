@@ -122,8 +122,8 @@ typedef struct {
                                tile), then the SpMV kernel adds each row's partials in
                                tile order (x is kept in LDS instead of the caches, after
                                the texture-cache study of Section 4.3).  Rows with more
-                               than 4,096 nonzeros in one tile stay on the long-row
-                               path.  0 = off; -1 (default) = 256, used only when the
+                               than 4,096 nonzeros in one tile (2,048 for F64 storage)
+                               stay on the long-row path.  0 = off; -1 (default) = 256, used only when the
                                tiled rows hold at least 262,144 nonzeros.  F32 storage
                                with F64 vectors runs the tiled rows on the long-row
                                path. */

@@ -56,10 +56,11 @@ void build_tiles(const HostLayout &L, int64_t min_len, HostTiles &T) {
     if (min_len == 0 || L.nl == 0 || L.n_cols == 0) return;
     const bool automatic = min_len < 0;
     const int64_t C = tile_cols(L.vdt);
+    const int64_t UM = tile_unit_max(L.vdt);
     const int64_t n_tiles = (L.n_cols + C - 1) / C;
     const int64_t thr = std::max<int64_t>(automatic ? 256 : min_len, (n_tiles + 1) / 2);
-    // a row's segment in one tile must fit a unit: a row with more than
-    // kTileUnitMax entries in some tile stays on the long-row path (columns
+    // a row's segment in one tile must fit a unit: a row with more than UM
+    // entries in some tile stays on the long-row path (columns
     // ascend within a row, so a segment is a run of consecutive entries)
     auto longest_segment = [&](int64_t i) {
         int64_t best = 0, run = 0, prev = -1;
@@ -75,7 +76,7 @@ void build_tiles(const HostLayout &L, int64_t min_len, HostTiles &T) {
     int64_t n_ent = 0;
     for (int64_t i = 0; i < L.nl; i++) {
         const int64_t len = L.long_ptr[i + 1] - L.long_ptr[i];
-        if (len < thr || (len > kTileUnitMax && longest_segment(i) > kTileUnitMax)) continue;
+        if (len < thr || (len > UM && longest_segment(i) > UM)) continue;
         T.tiled[i] = 1;
         T.trow.push_back((int32_t)i);
         n_ent += len;
@@ -119,7 +120,7 @@ void build_tiles(const HostLayout &L, int64_t min_len, HostTiles &T) {
             T.dst[q] = d;
         }
     }
-    // units: consecutive rows of one tile, at most kTileUnitMax entries; the
+    // units: consecutive rows of one tile, at most UM entries; the
     // longest segment sets the lanes per row, and the rows must fit
     // kTilePasses passes of kTileThreads / lanes rows
     auto lanes_for_seg = [](int64_t seg) {
@@ -134,7 +135,7 @@ void build_tiles(const HostLayout &L, int64_t min_len, HostTiles &T) {
         int64_t r0 = 0;
         while (r0 < nt) {
             int64_t r1 = r0 + 1, seg = p[r0 + 1] - p[r0];
-            while (r1 < nt && p[r1 + 1] - p[r0] <= kTileUnitMax) {
+            while (r1 < nt && p[r1 + 1] - p[r0] <= UM) {
                 const int64_t s2 = std::max<int64_t>(seg, p[r1 + 1] - p[r1]);
                 if (r1 + 1 - r0 > (int64_t)kTilePasses * (kTileThreads / lanes_for_seg(s2))) break;
                 seg = s2;

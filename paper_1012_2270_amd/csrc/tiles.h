@@ -21,10 +21,12 @@ namespace rg {
 
 constexpr int kTileCols = 8192;      // x columns per tile: 32 KB of FP32 in LDS
 constexpr int kTileCols64 = 4096;    // F64 storage (FP64 x): 32 KB of FP64 in LDS
-constexpr int kTileUnitMax = 4096;   // entries per unit: 16 KB of FP32 (32 KB of FP64) products in LDS
-constexpr int kTileThreads = 512;    // one workgroup per unit, three per CU (48 KB of LDS each; FP64: two, 64 KB)
-// Columns per tile of a layout with stored value type vdt.
+constexpr int kTileUnitMax = 4096;   // entries per unit: 16 KB of FP32 products in LDS
+constexpr int kTileUnitMax64 = 2048; // F64 storage: 16 KB of FP64 products in LDS
+constexpr int kTileThreads = 512;    // one workgroup per unit, three per CU (48 KB of LDS each)
+// Columns per tile and entries per unit of a layout with stored value type vdt.
 constexpr int tile_cols(int vdt) { return vdt == RGCSR_F64 ? kTileCols64 : kTileCols; }
+constexpr int tile_unit_max(int vdt) { return vdt == RGCSR_F64 ? kTileUnitMax64 : kTileUnitMax; }
 constexpr int kTilePasses = 4;       // passes over a unit's rows (512 / lanes rows per pass)
 constexpr int kTileLaneSteps = 16;   // products a lane adds per row segment, at most
 constexpr int64_t kTileMinEntries = int64_t(1) << 18;  // automatic choice: tile only this many entries or more
@@ -53,8 +55,8 @@ struct HostTiles {
 
 // Selects the tiled rows of layout L (long rows of at least
 // max(min_len, tiles / 2) nonzeros, so the partial sums never outnumber the
-// entries twice over, and at most kTileUnitMax nonzeros in any one tile, so
-// a row's segment fits a unit;
+// entries twice over, and at most tile_unit_max(vdt) nonzeros in any one
+// tile, so a row's segment fits a unit;
 // min_len < 0 picks 256 and keeps the tiles only when they hold at least
 // kTileMinEntries entries; 0 disables) and builds their index arrays and
 // units (values are copied on the device through src).  Needs L.long_ptr and

@@ -44,9 +44,10 @@ __global__ __launch_bounds__(kTileThreads) void tile_spmv_k(TileParams P) {
     using S = typename V::S;
     using A = typename V::A;
     constexpr int C = tile_cols(VD);
-    constexpr int EU = kTileUnitMax / kTileThreads;
+    constexpr int UM = tile_unit_max(VD);
+    constexpr int EU = UM / kTileThreads;
     __shared__ A xs[C];
-    __shared__ A prod[kTileUnitMax];
+    __shared__ A prod[UM];
     const TileUnit u = P.units[blockIdx.x];
     if (u.t < 0) return;
     const int tid = threadIdx.x;

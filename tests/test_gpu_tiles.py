@@ -187,8 +187,8 @@ def test_full_size_zipf_tiles_auto(torch_cuda, oracle):
     check_spmv(oracle, A, x, host(M.spmv(dev(x))))
 
 
-# F64 storage: tiles of 4,096 columns with x, the products and the partial
-# sums in FP64.  200,000 columns make 49 tiles, the last one partial (3,392
+# F64 storage: tiles of 4,096 columns and units of 2,048 entries with x, the
+# products and the partial sums in FP64.  200,000 columns make 49 tiles, the last one partial (3,392
 # columns); rows need at least max(min_len, 25) nonzeros.
 @pytest.mark.parametrize("min_len", [16, 300, 2000])
 def test_tiled_parity_f64(torch_cuda, oracle, zipf, min_len):
@@ -250,9 +250,11 @@ def test_tiles_f64_updates_clone_device_and_torch_memory(torch_cuda, oracle, zip
     check_spmv(oracle, A, x, y1, tol=TOL_F64)
 
 
-def test_tiles_f64_with_a_whole_tile_row(torch_cuda, oracle):
-    """F64 tiles of 4,096 columns: a row holding every column of tile 1 (one
-    segment of 4,096 entries, a whole unit) next to sparse long rows."""
+def test_tiles_f64_with_a_whole_unit_segment(torch_cuda, oracle):
+    """F64 tiles of 4,096 columns and units of 2,048 entries: a row holding
+    2,048 consecutive columns of tile 1 (one segment that fills a unit) next
+    to sparse long rows, and a row with 3,000 entries in tile 3, more than a
+    unit holds, which stays on the long-row path."""
     A = W.random_csr(2000, 40_000, seed=56, max_len=8, long_rows=5, long_len=6000)
     L = np.diff(A.row_ptr).copy()
     cols, vals = [], []
@@ -261,8 +263,12 @@ def test_tiles_f64_with_a_whole_tile_row(torch_cuda, oracle):
         c = A.col[A.row_ptr[r]:A.row_ptr[r + 1]]
         v = A.val[A.row_ptr[r]:A.row_ptr[r + 1]]
         if r == 3:
-            c = np.concatenate([np.sort(rng.choice(4096, 700, replace=False)), 4096 + np.arange(4096),
+            c = np.concatenate([np.sort(rng.choice(4096, 700, replace=False)), 4096 + np.arange(2048),
                                 8192 + np.sort(rng.choice(30_000, 900, replace=False))]).astype(np.int32)
+            v = rng.standard_normal(len(c))
+        if r == 4:
+            c = np.concatenate([np.sort(rng.choice(4096, 500, replace=False)),
+                                12_288 + np.arange(3000)]).astype(np.int32)
             v = rng.standard_normal(len(c))
         cols.append(c)
         vals.append(v)
@@ -270,9 +276,9 @@ def test_tiles_f64_with_a_whole_tile_row(torch_cuda, oracle):
     rp = np.concatenate([[0], np.cumsum(L)]).astype(np.int64)
     A = W.CSR(A.n_rows, A.n_cols, rp, np.concatenate(cols).astype(np.int32), np.concatenate(vals))
     x = W.uniform_vector(A.n_cols, 58, np.float64)
-    say("tiles, F64 whole-tile row")
+    say("tiles, F64 whole-unit segment")
     M = rg.rgcsr_from_csr(A, G=64, tau=16, tile_min_len=1000, value_dtype="f64")
-    assert M.info["tiled_rows"] == int(np.sum(L >= 1000))
+    assert M.info["tiled_rows"] == int(np.sum(L >= 1000)) - 1
     check_spmv(oracle, A, x, host(M.spmv(dev(x))), tol=TOL_F64)
 
 
