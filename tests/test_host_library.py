@@ -204,6 +204,32 @@ def test_plan_needs_no_gpu_and_sizes_the_device_block(lib):
         PT.close()
 
 
+def test_plan_sizes_the_column_tiles(lib):
+    """The plan's device block holds the column-tiled copy of the long rows:
+    8,192-column tiles with FP32 partial sums for F32 storage, 4,096-column
+    tiles with FP64 partial sums for F64 storage.  Rows of at least
+    max(min_len, tiles / 2) nonzeros are tiled; the extra bytes cover their
+    16-bit columns and values, one partial sum per (tile, row), the
+    tile-major row pointers and the source map (sizes from an independent
+    count)."""
+    A = W.random_csr(2000, 1_000_000, seed=12, max_len=8, long_rows=400, long_len=1200)
+    L = np.diff(A.row_ptr)
+    for vt, cols, esz in (("f32", 8192, 4), ("f64", 4096, 8)):
+        n_tiles = -(-A.n_cols // cols)
+        rows = L >= max(300, (n_tiles + 1) // 2)
+        n_trows, n_ent = int(rows.sum()), int(L[rows].sum())
+        long_nnz = int(L[L > 16].sum())
+        assert n_trows == 400 and long_nnz == n_ent
+        base = rg.rgcsr_plan_from_csr(A, G=64, tau=16, tile_min_len=0, value_dtype=vt)
+        tiled = rg.rgcsr_plan_from_csr(A, G=64, tau=16, tile_min_len=300, value_dtype=vt)
+        d = tiled.device_bytes - base.device_bytes
+        low = (n_ent * (2 + esz) + n_tiles * n_trows * esz + long_nnz * 4 + n_tiles * (n_trows + 1) * 4
+               + n_trows * 4)
+        assert low <= d <= low + 64 * 1024, (vt, d, low)
+        base.close()
+        tiled.close()
+
+
 def test_plan_build_argument_errors(lib):
     """A buffer below the plan's size or off 256-byte alignment is refused
     before any device work, and the plan stays buildable; bad CSR is refused
