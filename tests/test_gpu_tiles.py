@@ -162,19 +162,21 @@ def test_tiles_with_a_dense_tile_segment(torch_cuda, oracle):
     check_spmv(oracle, A, x, host(M.spmv(dev(x))))
 
 
-def test_tiles_in_a_batch(torch_cuda, oracle):
+@pytest.mark.parametrize("vdt", ["f32", "f64"])
+def test_tiles_in_a_batch(torch_cuda, oracle, vdt):
     torch = torch_cuda
     mats = [W.zipf_matrix(60_000, seed=50 + i) for i in range(3)]
-    say("tiles, batch")
-    B = rg.rgcsr_from_csr_batch(mats, G=64, sigma=512, tau=16, tile_min_len=64)
+    say("tiles, batch", vdt)
+    B = rg.rgcsr_from_csr_batch(mats, G=64, sigma=512, tau=16, tile_min_len=64, value_dtype=vdt)
     assert B.info["tiled_rows"] > 0
     ro, co = B.batch_offsets()
-    xh = W.uniform_vector(int(co[-1]), 51, np.float32)
-    y = torch.empty(int(ro[-1]), device="cuda:0")
+    ft = np.float64 if vdt == "f64" else np.float32
+    xh = W.uniform_vector(int(co[-1]), 51, ft)
+    y = torch.empty(int(ro[-1]), dtype=torch.float64 if vdt == "f64" else torch.float32, device="cuda:0")
     rg.rgcsr_spmv(B, dev(xh), y)
     yh = host(y)
     for i, Mi in enumerate(mats):
-        check_spmv(oracle, Mi, xh[co[i]:co[i + 1]], yh[ro[i]:ro[i + 1]])
+        check_spmv(oracle, Mi, xh[co[i]:co[i + 1]], yh[ro[i]:ro[i + 1]], tol=TOL_F64 if vdt == "f64" else TOL_F32)
 
 
 def test_full_size_zipf_tiles_auto(torch_cuda, oracle):
