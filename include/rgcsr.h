@@ -208,6 +208,20 @@ rgcsr_status rgcsr_layout_host(int64_t n_rows, int64_t n_cols, int64_t nnz,
                                int32_t *long_row, int64_t *long_ptr, void *long_val,
                                int32_t *long_col);
 
+/* Sizes of the column-tiled copy (rgcsr_opts.tile_min_len) of a host CSR
+ * matrix under *opts, without a GPU: the rows that a handle built with the
+ * same options stores split by column tile as well.  *n_tiles receives the
+ * tiles (n_cols / 8,192 rounded up, or / 4,096 for F64 value_dtype; 0 when no
+ * row is tiled), *tiled_rows and *tile_entries the rows and nonzeros tiled,
+ * *units the workgroups of the tile kernel (empty ones that even out the XCD
+ * queues included) and *min_len the row length threshold applied (any output
+ * may be NULL).  Values are not needed.  RGCSR_EINVAL when opts is NULL;
+ * RGCSR_ECSR for malformed CSR when opts->validate != 0. */
+rgcsr_status rgcsr_tile_sizes(int64_t n_rows, int64_t n_cols, int64_t nnz,
+                              const int64_t *row_ptr, const int32_t *col_idx,
+                              const rgcsr_opts *opts, int64_t *n_tiles, int64_t *tiled_rows,
+                              int64_t *tile_entries, int64_t *units, int64_t *min_len);
+
 /* Sizes of the column-panel copy (rgcsr_opts.col_panels) of a host CSR
  * matrix under *opts, without a GPU: col_bounds[col_panels + 1] receives the
  * panel column bounds (panel q holds columns [col_bounds[q],

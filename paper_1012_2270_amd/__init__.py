@@ -139,6 +139,17 @@ def rgcsr_panel_sizes(A, opts: _lib.Opts) -> dict:
     return dict(col_bounds=cb, **{k: o.value for k, o in zip(keys, outs)})
 
 
+def rgcsr_tile_sizes(A, opts: _lib.Opts) -> dict:
+    """Tiles, tiled rows and entries, tile-kernel workgroups and the row
+    length threshold of the column-tiled copy (no GPU)."""
+    rp, col, _ = _csr_arrays(A)
+    outs = [ctypes.c_int64() for _ in range(5)]
+    _lib.call("rgcsr_tile_sizes", A.n_rows, A.n_cols, int(rp[-1]) if rp.size else 0, _ptr(rp), _ptr(col),
+              ctypes.byref(opts), *[ctypes.byref(o) for o in outs])
+    keys = ("n_tiles", "tiled_rows", "tile_entries", "units", "min_len")
+    return {k: o.value for k, o in zip(keys, outs)}
+
+
 def rgcsr_layout_host(A, opts: _lib.Opts, bf16_bits: bool = False) -> dict:
     rp, col, val = _csr_arrays(A)
     s = rgcsr_layout_sizes(A, opts)

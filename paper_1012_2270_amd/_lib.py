@@ -67,6 +67,8 @@ SIGNATURES = {
     "rgcsr_layout_sizes": (c_int, [c_i64, c_i64, c_i64, c_vp, c_vp, ctypes.POINTER(Opts), ctypes.POINTER(Info)]),
     "rgcsr_panel_sizes": (c_int, [c_i64, c_i64, c_i64, c_vp, c_vp, ctypes.POINTER(Opts), c_vp, P_I64, P_I64, P_I64,
                                   P_I64, P_I64]),
+    "rgcsr_tile_sizes": (c_int, [c_i64, c_i64, c_i64, c_vp, c_vp, ctypes.POINTER(Opts), P_I64, P_I64, P_I64, P_I64,
+                                 P_I64]),
     "rgcsr_layout_host": (c_int, [c_i64, c_i64, c_i64, c_vp, c_vp, c_vp, c_int, ctypes.POINTER(Opts),
                                   c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp]),
     "rgcsr_from_csr": (c_int, [c_i64, c_i64, c_i64, c_vp, c_vp, c_vp, c_int, ctypes.POINTER(Opts), c_int,

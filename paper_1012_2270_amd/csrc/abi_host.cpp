@@ -10,6 +10,7 @@
 #include <algorithm>
 
 #include "internal.h"
+#include "tiles.h"
 
 namespace rg {
 
@@ -123,6 +124,32 @@ rgcsr_status rgcsr_panel_sizes(int64_t n_rows, int64_t n_cols, int64_t nnz, cons
     if (split_pieces) *split_pieces = B.split_pieces;
     if (slots) *slots = B.LP.slots;
     if (long_nnz) *long_nnz = B.LP.long_nnz;
+    ABI_CATCH
+}
+
+rgcsr_status rgcsr_tile_sizes(int64_t n_rows, int64_t n_cols, int64_t nnz, const int64_t *row_ptr,
+                              const int32_t *col_idx, const rgcsr_opts *opts, int64_t *n_tiles, int64_t *tiled_rows,
+                              int64_t *tile_entries, int64_t *units, int64_t *min_len) {
+    ABI_TRY
+    if (!opts) fail(RGCSR_EINVAL, "opts is null");
+    const LayoutParams p = resolve_opts(opts);
+    check_dtype(opts->value_dtype, "value_dtype");
+    if (opts->validate) validate_csr(n_rows, n_cols, nnz, row_ptr, col_idx);
+    else if (!row_ptr) fail(RGCSR_EINVAL, "row_ptr is null");
+    else if (row_ptr[n_rows] != nnz) fail(RGCSR_ECSR, "row_ptr[n_rows] != nnz");
+    // the layout's long-row segment (columns only), then the tile selection
+    // that a device handle makes from it
+    HostLayout L;
+    L.G = p.G; L.T = p.T; L.sigma = p.sigma; L.tau = p.tau;
+    L.vdt = opts->value_dtype; L.esz = dtype_size(L.vdt);
+    append_layout(L, p, n_rows, n_cols, row_ptr, col_idx, nullptr, L.esz, 0);
+    HostTiles T;
+    build_tiles(L, opts->tile_min_len, T);
+    if (n_tiles) *n_tiles = T.n_tiles;
+    if (tiled_rows) *tiled_rows = T.n_trows;
+    if (tile_entries) *tile_entries = T.n_ent;
+    if (units) *units = (int64_t)T.units.size();
+    if (min_len) *min_len = T.min_len;
     ABI_CATCH
 }
 

@@ -150,6 +150,24 @@ static rgcsr_status panels_all(const Csr &A, rgcsr_opts o, int32_t P) {
     return s;
 }
 
+// Column-tile sizes: no more tiled entries than long-row entries, a tile
+// count that covers the columns, units only when rows are tiled.
+static rgcsr_status tiles_all(const Csr &A, rgcsr_opts o, int32_t min_len) {
+    o.tile_min_len = min_len;
+    int64_t n_tiles = -1, rows = -1, entries = -1, units = -1, thr = -1;
+    g_armed = true;
+    const rgcsr_status s = rgcsr_tile_sizes(A.n_rows, A.n_cols, A.rp.back(), A.rp.data(), A.col.data(), &o,
+                                            &n_tiles, &rows, &entries, &units, &thr);
+    g_armed = false;
+    if (s != RGCSR_OK) return s;
+    const int64_t cols = o.value_dtype == RGCSR_F64 ? 4096 : 8192;
+    CHECK(entries >= 0 && entries <= A.rp.back(), "tile entries %lld", (long long)entries);
+    CHECK(rows == 0 ? (n_tiles == 0 && units == 0 && entries == 0)
+                    : (n_tiles == (A.n_cols + cols - 1) / cols && units > 0 && thr >= 1),
+          "tile sizes: %lld rows, %lld tiles, %lld units", (long long)rows, (long long)n_tiles, (long long)units);
+    return s;
+}
+
 int main() {
     std::mt19937_64 rng(20101012);
     const int shapes[][5] = {{0, 0, 0, 0, 0},     {1, 1, 1, 0, 0},       {7, 5, 4, 0, 0},
@@ -174,6 +192,18 @@ int main() {
                             CHECK(s == RGCSR_OK, "layout status %d: %s", (int)s, rgcsr_last_error());
                             cases++;
                         }
+        for (int dt : {RGCSR_F32, RGCSR_F64})
+            for (int32_t min_len : {-1, 0, 1, 64})
+                for (int64_t tau : {(int64_t)-1, (int64_t)0, (int64_t)16}) {
+                    rgcsr_opts o;
+                    rgcsr_default_opts(&o);
+                    o.sort_window = 5;
+                    o.long_row_threshold = tau;
+                    o.value_dtype = dt;
+                    const rgcsr_status s = tiles_all(A, o, min_len);
+                    CHECK(s == RGCSR_OK, "tile sizes status %d: %s", (int)s, rgcsr_last_error());
+                    cases++;
+                }
         for (int32_t P : {8, 16, 64})
             for (int64_t tau : {(int64_t)-1, (int64_t)0, (int64_t)16}) {
                 rgcsr_opts o;
@@ -264,6 +294,23 @@ int main() {
         }
         CHECK(enomem_panels > 10, "only %d panel allocations were failed", enomem_panels);
         enomem += enomem_panels;
+        int enomem_tiles = 0;
+        o.value_dtype = RGCSR_F64;
+        for (long n = 0;; n++) {
+            g_fail_countdown = n;
+            const rgcsr_status s = tiles_all(A, o, 64);
+            g_fail_countdown = -1;
+            if (s == RGCSR_OK) break;
+            CHECK(s == RGCSR_ENOMEM, "tile sizes: allocation %ld failing gave status %d: %s", n, (int)s,
+                  rgcsr_last_error());
+            enomem_tiles++;
+            if (n > 100000) {
+                CHECK(false, "tile sizes never got through");
+                break;
+            }
+        }
+        CHECK(enomem_tiles > 10, "only %d tile allocations were failed", enomem_tiles);
+        enomem += enomem_tiles;
         std::printf("allocation failures injected: %d, each returned RGCSR_ENOMEM\n", enomem);
     }
     std::printf("layout cases: %d, failures: %d\n", cases, g_failures);
