@@ -294,3 +294,20 @@ def test_full_size_zipf_tiles_auto_f64(torch_cuda, oracle):
     say("full-size Zipf F64, automatic tiles", M.info["tiled_rows"], M.info["tile_entries"])
     assert M.info["tiled_rows"] > 0 and M.info["n_tiles"] == -(-A.n_cols // 4096)
     check_spmv(oracle, A, x, host(M.spmv(dev(x))), tol=TOL_F64)
+
+
+@pytest.mark.parametrize("vdt", ["f32", "f64"])
+def test_handle_tiles_match_host_tile_sizes(torch_cuda, zipf, vdt):
+    """A handle built on the host or on the device tiles the rows that
+    rgcsr_tile_sizes selects without a GPU."""
+    A, _ = zipf
+    o = dict(LAY, tile_min_len=64, value_dtype=vdt)
+    s = rg.rgcsr_tile_sizes(A, rg.make_opts(**o))
+    assert s["tiled_rows"] > 0
+    say("tiles, host sizes against handles", vdt)
+    M = rg.rgcsr_from_csr(A, **o)
+    D = rg.rgcsr_from_csr_device(A.n_rows, A.n_cols, dev(np.ascontiguousarray(A.row_ptr, np.int64)),
+                                 dev(A.col), dev(A.val), rg.make_opts(**o))
+    for H in (M, D):
+        assert (H.info["n_tiles"], H.info["tiled_rows"], H.info["tile_entries"]) == \
+            (s["n_tiles"], s["tiled_rows"], s["tile_entries"])
