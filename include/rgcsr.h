@@ -264,7 +264,9 @@ rgcsr_status rgcsr_from_csr(int64_t n_rows, int64_t n_cols, int64_t nnz,
  * rgcsr_plan_from_csr: validates (per opts->validate) and converts the host
  * CSR input on the host, exactly as rgcsr_from_csr does, and keeps the
  * layout in a host-side plan.  Arguments as rgcsr_from_csr with
- * inputs_on_device = 0; needs no GPU.
+ * inputs_on_device = 0; needs no GPU.  rgcsr_plan_from_csr_batch: the same
+ * for a block-diagonal batch (arguments as rgcsr_from_csr_batch, without
+ * the stream); its handle answers rgcsr_batch_offsets.
  * rgcsr_plan_device_bytes: bytes of device memory the handle needs (its
  * arrays and, with build_transpose, those of A^T), one contiguous block.
  * rgcsr_build: places the handle's arrays in [device_buf, device_buf +
@@ -285,6 +287,10 @@ rgcsr_status rgcsr_plan_from_csr(int64_t n_rows, int64_t n_cols, int64_t nnz,
                                  const int64_t *row_ptr, const int32_t *col_idx,
                                  const void *vals, rgcsr_dtype vals_dtype,
                                  const rgcsr_opts *opts, rgcsr_plan *out);
+rgcsr_status rgcsr_plan_from_csr_batch(int32_t count, const int64_t *n_rows, const int64_t *n_cols,
+                                       const int64_t *const *row_ptr, const int32_t *const *col_idx,
+                                       const void *const *vals, rgcsr_dtype vals_dtype,
+                                       const rgcsr_opts *opts, rgcsr_plan *out);
 rgcsr_status rgcsr_plan_device_bytes(rgcsr_plan plan, int64_t *bytes);
 rgcsr_status rgcsr_build(rgcsr_plan plan, void *device_buf, int64_t buf_bytes, void *stream,
                          rgcsr_handle *out);

@@ -312,9 +312,9 @@ def rgcsr_from_csr_device(n_rows: int, n_cols: int, row_ptr, col, vals, opts: _l
     return RgCSRMatrix(h.value)
 
 
-def rgcsr_from_csr_batch(mats, opts: _lib.Opts | None = None, stream=None, **kw) -> RgCSRMatrix:
-    """One handle for a list of host CSR matrices (block-diagonal batch)."""
-    opts = opts if opts is not None else make_opts(**kw)
+def _batch_arrays(mats):
+    """Per-matrix sizes and pointer arrays of a batch (the arrays they point
+    into are returned too, to stay alive across the call)."""
     n = len(mats)
     arrs = [_csr_arrays(A) for A in mats]
     nr = np.array([A.n_rows for A in mats], np.int64)
@@ -325,10 +325,27 @@ def rgcsr_from_csr_batch(mats, opts: _lib.Opts | None = None, stream=None, **kw)
     codes = {_code_of_numpy(a[2]) for a in arrs}
     if len(codes) != 1:
         raise ValueError("all matrices of a batch must share one value dtype")
+    return arrs, nr, nc, rps, cols, vals, codes.pop()
+
+
+def rgcsr_from_csr_batch(mats, opts: _lib.Opts | None = None, stream=None, **kw) -> RgCSRMatrix:
+    """One handle for a list of host CSR matrices (block-diagonal batch)."""
+    opts = opts if opts is not None else make_opts(**kw)
+    arrs, nr, nc, rps, cols, vals, code = _batch_arrays(mats)
     h = ctypes.c_void_p()
-    _lib.call("rgcsr_from_csr_batch", n, _ptr(nr), _ptr(nc), ctypes.addressof(rps), ctypes.addressof(cols),
-              ctypes.addressof(vals), codes.pop(), ctypes.byref(opts), _stream(stream), ctypes.byref(h))
+    _lib.call("rgcsr_from_csr_batch", len(mats), _ptr(nr), _ptr(nc), ctypes.addressof(rps), ctypes.addressof(cols),
+              ctypes.addressof(vals), code, ctypes.byref(opts), _stream(stream), ctypes.byref(h))
     return RgCSRMatrix(h.value)
+
+
+def rgcsr_plan_from_csr_batch(mats, opts: _lib.Opts | None = None, **kw) -> RgCSRPlan:
+    """Host conversion of a block-diagonal batch, device memory left to the caller."""
+    opts = opts if opts is not None else make_opts(**kw)
+    arrs, nr, nc, rps, cols, vals, code = _batch_arrays(mats)
+    p = ctypes.c_void_p()
+    _lib.call("rgcsr_plan_from_csr_batch", len(mats), _ptr(nr), _ptr(nc), ctypes.addressof(rps),
+              ctypes.addressof(cols), ctypes.addressof(vals), code, ctypes.byref(opts), ctypes.byref(p))
+    return RgCSRPlan(p.value)
 
 
 def rgcsr_clone(A: RgCSRMatrix, stream=None) -> RgCSRMatrix:

@@ -78,6 +78,7 @@ SIGNATURES = {
     "rgcsr_plan_device_bytes": (c_int, [c_vp, P_I64]),
     "rgcsr_build": (c_int, [c_vp, c_vp, c_i64, c_vp, ctypes.POINTER(c_vp)]),
     "rgcsr_plan_destroy": (c_int, [c_vp]),
+    "rgcsr_plan_from_csr_batch": (c_int, [c_i32, c_vp, c_vp, c_vp, c_vp, c_vp, c_int, ctypes.POINTER(Opts), c_vp]),
     "rgcsr_from_csr_batch": (c_int, [c_i32, c_vp, c_vp, c_vp, c_vp, c_vp, c_int, ctypes.POINTER(Opts), c_vp,
                                      ctypes.POINTER(c_vp)]),
     "rgcsr_batch_offsets": (c_int, [c_vp, c_vp, c_vp]),

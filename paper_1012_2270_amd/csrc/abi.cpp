@@ -887,34 +887,61 @@ rgcsr_status rgcsr_from_csr(int64_t n_rows, int64_t n_cols, int64_t nnz, const i
     ABI_CATCH
 }
 
-rgcsr_status rgcsr_plan_from_csr(int64_t n_rows, int64_t n_cols, int64_t nnz, const int64_t *row_ptr,
-                                 const int32_t *col_idx, const void *vals, rgcsr_dtype vals_dtype,
-                                 const rgcsr_opts *opts, rgcsr_plan *out) {
-    ABI_TRY
-    if (!out) fail(RGCSR_EINVAL, "out is null");
-    *out = nullptr;
+}  // extern "C"
+
+namespace {
+
+// Host conversion of one matrix or a block-diagonal batch into a plan.
+rgcsr_plan plan_of(int32_t count, const int64_t *n_rows, const int64_t *n_cols, const int64_t *const *row_ptr,
+                   const int32_t *const *col_idx, const void *const *vals, rgcsr_dtype vals_dtype,
+                   const rgcsr_opts *opts) {
     rgcsr_opts o;
     if (opts) o = *opts; else rgcsr_default_opts(&o);
     const LayoutParams p = resolve_opts(&o);
     check_device_geometry(p);
     check_dtype(o.value_dtype, "value_dtype");
     check_dtype(vals_dtype, "vals");
-    if (n_rows < 0 || n_cols < 0 || nnz < 0) fail(RGCSR_EINVAL, "negative size");
-    if (!row_ptr) fail(RGCSR_EINVAL, "row_ptr is null");
-    if (!o.validate && row_ptr[n_rows] != nnz) fail(RGCSR_ECSR, "row_ptr[n_rows] != nnz");
     check_panels(o.col_panels);
     if (o.col_panels) fail(RGCSR_EUNSUPPORTED, "col_panels needs rgcsr_from_csr");
     std::unique_ptr<rgcsr_plan_s> P(new rgcsr_plan_s());
     P->with_row_ptr = o.keep_csr_map != 0 || o.build_transpose != 0;
     const bool tr = o.build_transpose != 0;
-    build_host(P->B, p, o.value_dtype, 1, &n_rows, &n_cols, &row_ptr, &col_idx, &vals, vals_dtype, o.validate != 0,
+    build_host(P->B, p, o.value_dtype, count, n_rows, n_cols, row_ptr, col_idx, vals, vals_dtype, o.validate != 0,
                o.keep_csr_map != 0, tr);
     P->h = prepare_handle(P->B.L, P->with_row_ptr, nullptr, P->a, o.rows_per_lane, o.pad_loads, o.load_policy,
                           o.tile_min_len);
     if (tr)
         P->hT = prepare_handle(P->B.LT, false, &P->B.LTmap, P->aT, o.rows_per_lane, o.pad_loads, o.load_policy,
                                o.tile_min_len);
-    *out = P.release();
+    return P.release();
+}
+
+}  // namespace
+
+extern "C" {
+
+rgcsr_status rgcsr_plan_from_csr(int64_t n_rows, int64_t n_cols, int64_t nnz, const int64_t *row_ptr,
+                                 const int32_t *col_idx, const void *vals, rgcsr_dtype vals_dtype,
+                                 const rgcsr_opts *opts, rgcsr_plan *out) {
+    ABI_TRY
+    if (!out) fail(RGCSR_EINVAL, "out is null");
+    *out = nullptr;
+    if (n_rows < 0 || n_cols < 0 || nnz < 0) fail(RGCSR_EINVAL, "negative size");
+    if (!row_ptr) fail(RGCSR_EINVAL, "row_ptr is null");
+    if (!(opts ? opts->validate : 1) && row_ptr[n_rows] != nnz) fail(RGCSR_ECSR, "row_ptr[n_rows] != nnz");
+    *out = plan_of(1, &n_rows, &n_cols, &row_ptr, &col_idx, &vals, vals_dtype, opts);
+    ABI_CATCH
+}
+
+rgcsr_status rgcsr_plan_from_csr_batch(int32_t count, const int64_t *n_rows, const int64_t *n_cols,
+                                       const int64_t *const *row_ptr, const int32_t *const *col_idx,
+                                       const void *const *vals, rgcsr_dtype vals_dtype, const rgcsr_opts *opts,
+                                       rgcsr_plan *out) {
+    ABI_TRY
+    if (!out) fail(RGCSR_EINVAL, "out is null");
+    *out = nullptr;
+    if (count < 1 || !n_rows || !n_cols || !row_ptr || !col_idx || !vals) fail(RGCSR_EINVAL, "bad batch arrays");
+    *out = plan_of(count, n_rows, n_cols, row_ptr, col_idx, vals, vals_dtype, opts);
     ABI_CATCH
 }
 

@@ -408,6 +408,44 @@ def test_build_into_torch_memory(torch_cuda, oracle, lay):
     M2.close()
 
 
+@pytest.mark.parametrize("tr", [False, True])
+def test_batch_built_into_torch_memory(torch_cuda, oracle, tr):
+    """A batch planned on the host and built into a torch block holds the same
+    arrays as one that allocates its own: the same offsets, the same SpMV and
+    SpMM bits, each matrix within tolerance of the oracle, and (with the
+    transpose) the same backward bits."""
+    torch = torch_cuda
+    mats = [W.random_csr(1500 + 300 * i, 1200 + 200 * i, seed=60 + i, max_len=40, empty_frac=0.1, long_rows=2,
+                         long_len=900, dtype=np.float32) for i in range(4)]
+    kw = dict(G=64, sigma=256, tau=24, build_transpose=tr)
+    say("batch into torch memory", tr)
+    P = rg.rgcsr_plan_from_csr_batch(mats, **kw)
+    buf = torch.empty(P.device_bytes + 256, dtype=torch.uint8, device="cuda:0")
+    M = P.build(buf[256:])
+    Mo = rg.rgcsr_from_csr_batch(mats, **kw)
+    ro, co = M.batch_offsets()
+    roo, coo = Mo.batch_offsets()
+    np.testing.assert_array_equal(ro, roo)
+    np.testing.assert_array_equal(co, coo)
+    xh = W.uniform_vector(int(co[-1]), 61, np.float32)
+    xd = dev(xh)
+    y, yo = host(M.spmv(xd)), host(Mo.spmv(xd))
+    np.testing.assert_array_equal(y.view(np.uint32), yo.view(np.uint32))
+    for i, A in enumerate(mats):
+        check_spmv(oracle, A, xh[co[i]:co[i + 1]], y[ro[i]:ro[i + 1]])
+    X = dev(W.uniform_matrix(int(co[-1]), 4, 62))
+    np.testing.assert_array_equal(host(M.spmm(X)).view(np.uint32), host(Mo.spmm(X)).view(np.uint32))
+    if tr:
+        dy = dev(W.normal_vector(int(ro[-1]), 63, np.float32))
+        dx, dxo = torch.empty(int(co[-1]), device="cuda:0"), torch.empty(int(co[-1]), device="cuda:0")
+        rg.rgcsr_spmv_transpose_grad(M, None, dy, dx, None)
+        rg.rgcsr_spmv_transpose_grad(Mo, None, dy, dxo, None)
+        np.testing.assert_array_equal(host(dx).view(np.uint32), host(dxo).view(np.uint32))
+    M.close()
+    Mo.close()
+    P.close()
+
+
 def test_destroy_of_a_handle_in_torch_memory_does_not_wait(torch_cuda, oracle):
     """Destroying a handle built into torch memory makes no device call: the
     work queued before it is still running when close() returns, and the

@@ -230,6 +230,40 @@ def test_plan_sizes_the_column_tiles(lib):
         tiled.close()
 
 
+def test_batch_plan_needs_no_gpu(lib):
+    """rgcsr_plan_from_csr_batch converts a block-diagonal batch on the host:
+    a batch of one matrix needs the same device block as the single-matrix
+    plan, a larger batch more than its largest member; empty batches, mixed
+    value types, malformed members and column panels are refused."""
+    mats = [W.random_csr(700 + 100 * i, 500 + 50 * i, seed=20 + i, max_len=30, long_rows=2, long_len=400,
+                         dtype=np.float32) for i in range(3)]
+    kw = dict(G=64, sigma=256, tau=24)
+    one = rg.rgcsr_plan_from_csr_batch(mats[:1], **kw)
+    single = rg.rgcsr_plan_from_csr(mats[0], **kw)
+    assert one.device_bytes == single.device_bytes
+    three = rg.rgcsr_plan_from_csr_batch(mats, **kw)
+    assert three.device_bytes > max(rg.rgcsr_plan_from_csr(A, **kw).device_bytes for A in mats)
+    assert three.device_bytes % 256 == 0
+    for P in (one, single, three):
+        P.close()
+    with pytest.raises(ValueError):
+        rg.rgcsr_plan_from_csr_batch([mats[0], W.CSR(mats[1].n_rows, mats[1].n_cols, mats[1].row_ptr,
+                                                     mats[1].col, mats[1].val.astype(np.float64))], **kw)
+    p = ctypes.c_void_p()
+    o = rg.make_opts(**kw)
+    with pytest.raises(rg.RgcsrError) as e:
+        _lib.call("rgcsr_plan_from_csr_batch", 0, None, None, None, None, None, 1, ctypes.byref(o), ctypes.byref(p))
+    assert e.value.status == 1
+    bad = W.CSR(mats[1].n_rows, mats[1].n_cols, mats[1].row_ptr.copy(), mats[1].col.copy(), mats[1].val)
+    bad.col[0] = bad.n_cols
+    with pytest.raises(rg.RgcsrError) as e:
+        rg.rgcsr_plan_from_csr_batch([mats[0], bad], **kw)
+    assert e.value.status == 2
+    with pytest.raises(rg.RgcsrError) as e:
+        rg.rgcsr_plan_from_csr_batch(mats, col_panels=8, **kw)
+    assert e.value.status == 6
+
+
 def test_plan_build_argument_errors(lib):
     """A buffer below the plan's size or off 256-byte alignment is refused
     before any device work, and the plan stays buildable; bad CSR is refused
