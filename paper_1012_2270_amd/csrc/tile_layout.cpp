@@ -141,7 +141,7 @@ void build_tiles(const HostLayout &L, int64_t min_len, HostTiles &T) {
                 seg = s2;
                 r1++;
             }
-            per_tile[t].push_back(TileUnit{(int32_t)t, (int32_t)r0, (int32_t)r1, lanes_for_seg(seg)});
+            per_tile[t].push_back(TileUnit{(int32_t)t, (int32_t)r0, (int32_t)r1, lanes_for_seg(seg), p[r0], p[r1]});
             // a unit streams its entries and stages a tile of x (32 KB in
             // either precision, about as much as 4,096 entries of value and
             // column)
@@ -166,7 +166,7 @@ void build_tiles(const HostLayout &L, int64_t min_len, HostTiles &T) {
     size_t depth = 0;
     for (auto &v : q) depth = std::max(depth, v.size());
     for (size_t d = 0; d < depth; d++)
-        for (int x = 0; x < 8; x++) T.units.push_back(d < q[x].size() ? q[x][d] : TileUnit{-1, 0, 0, 1});
+        for (int x = 0; x < 8; x++) T.units.push_back(d < q[x].size() ? q[x][d] : TileUnit{-1, 0, 0, 1, 0, 0});
     while (!T.units.empty() && T.units.back().t < 0) T.units.pop_back();
     build_long_work_except(L.long_ptr, T.tiled, T.rest);
 }

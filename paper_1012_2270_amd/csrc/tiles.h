@@ -34,9 +34,12 @@ constexpr int64_t kTileMinEntries = int64_t(1) << 18;  // automatic choice: tile
 // One unit of the tile kernel (a workgroup): tile t, tiled rows [r0, r1),
 // `lanes` lanes per row (a power of two, at most 64, so that no lane adds
 // more than kTileLaneSteps products of a segment, and the rows fit
-// kTilePasses passes); t < 0 marks an empty unit.
+// kTilePasses passes); t < 0 marks an empty unit.  The unit carries its
+// entry range, so its entry loads need no dependent read of the row
+// pointers.
 struct TileUnit {
     int32_t t, r0, r1, lanes;
+    int32_t e0, e1;  // the unit's entries [e0, e1) of the tile-major arrays
 };
 
 struct HostTiles {

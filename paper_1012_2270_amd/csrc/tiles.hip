@@ -54,8 +54,8 @@ __global__ __launch_bounds__(kTileThreads) void tile_spmv_k(TileParams P) {
     const int64_t c0 = (int64_t)u.t * C;
     const int nc = (int)min((int64_t)C, P.n_cols - c0);
     const int32_t *ptr = P.ptr + (int64_t)u.t * (P.n_trows + 1);
-    const int32_t e0 = ptr[u.r0];
-    const int32_t n = ptr[u.r1] - e0;
+    const int32_t e0 = u.e0;
+    const int32_t n = u.e1 - e0;
     const S *val = (const S *)P.val + e0;
     const uint16_t *lc = P.lcol + e0;
     S v[EU];
