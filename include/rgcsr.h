@@ -460,6 +460,8 @@ rgcsr_status hyb_info(hyb_handle A, hyb_info_t *out);
 
 /* Device copy of a Hybrid handle (same conventions as rgcsr_clone). */
 rgcsr_status hyb_clone(hyb_handle A, void *stream, hyb_handle *out);
+/* Synchronises the device, then frees the handle and the device block it
+ * owns (every Hybrid handle owns one).  NULL is accepted. */
 rgcsr_status hyb_destroy(hyb_handle A);
 
 /* ---- Mixed-precision conjugate gradients (Krylov consumer, Section 1) ----- */
